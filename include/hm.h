@@ -1,0 +1,226 @@
+/*
+ * hm.h -- C ABI of the MI355X (gfx950) H-matrix library for the Laplace
+ * single-layer boundary integral equation.
+ *
+ * The library implements the method of Harbrecht & Zaspel, "A scalable
+ * H-matrix approach for the solution of boundary integral equations on
+ * multi-GPU clusters" (arXiv 1806.11558), for one GPU:
+ *
+ *   operator   S u(x) = int_Gamma u(y) / (4 pi |x - y|) dsigma_y = f(x)
+ *              (Sec. 2.1, Example 1), discretised by collocation with one
+ *              piecewise-constant unknown per flat triangle, collocation
+ *              point = centroid (nodes at element centres, Sec. 4.1):
+ *              a_ij = int_{T_j} G(x_i, y) dsigma_y, seven-point Radon rule
+ *              for i != j, closed form for i == j;
+ *   clustering Morton codes + sort, cardinality-based binary cluster tree
+ *              (Sec. 2.3 (C1)-(C4); Sec. 3.1 "Spatial data structure");
+ *   partition  block cluster tree of Algorithm 1 under the admissibility
+ *              condition (Sec. 2.3, eq. admissibilityCondition), built
+ *              level by level with scans (Sec. 3.1, "Block cluster tree
+ *              traversal");
+ *   setup      dense near-field blocks assembled in batches (Sec. 3.3) and
+ *              adaptive cross approximation U V^T of every admissible block
+ *              (Sec. 2.3), batched (Sec. 3.1, "Batching");
+ *   apply      H-matrix-vector product (Sec. 2.3, last paragraph) and its
+ *              transpose, used inside restarted GMRES.
+ *
+ * Conventions shared by every call
+ *   - All functions are extern "C" and return hm_status (hm_free excepted).
+ *   - Arguments are validated on the host before any HIP call; invalid
+ *     arguments return HM_ERR_ARG and leave outputs untouched.
+ *   - Unknowns are the triangles in the caller's order ("application
+ *     order"); every vector crossing the ABI is in that order.
+ *   - Device vectors are [n, nrhs] row-major (rhs index fastest), owned by
+ *     the caller, of dtype HM_F64 (double) or HM_F32 (float).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work of a call is issued on that stream.  A handle is not
+ *     safe for concurrent calls (it owns workspace); use one stream per
+ *     handle.
+ *   - hm_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hm_handle hm_handle;
+
+typedef enum {
+  HM_OK = 0,
+  HM_NOT_CONVERGED = 1,   /* completed; iterative solve missed its tolerance */
+  HM_ERR_ARG = -1,        /* invalid argument (checked before any HIP call)  */
+  HM_ERR_OOM = -2,        /* device allocation failed or mem_limit exceeded  */
+  HM_ERR_HIP = -3,        /* a HIP runtime call failed                       */
+  HM_ERR_ACA = -4,        /* HM_STRICT and a block hit the rank cap          */
+  HM_ERR_STATE = -5       /* handle in an unusable state                     */
+} hm_status;
+
+/* Arithmetic form of the build: kernel evaluation, ACA and storage. */
+typedef enum {
+  HM_F64 = 0,             /* everything in double                            */
+  HM_F32 = 1              /* evaluation, ACA and storage in float; the
+                             geometry (centroids) and the pairwise centroid
+                             difference stay double                         */
+} hm_precision;
+
+/* flags */
+#define HM_STRICT 1       /* a block that reaches max_rank without meeting
+                             the ACA stopping test fails the build           */
+
+typedef struct {
+  int32_t leaf_size;        /* C_leaf of (C3); 1..64.  Paper: 32             */
+  int32_t max_rank;         /* ACA rank cap k_max; 1..256; 0 => 64.  The cap
+                               is also limited by min(m, n) of each block     */
+  int32_t precision;        /* hm_precision                                   */
+  int32_t flags;            /* HM_STRICT                                      */
+  double eta;               /* admissibility parameter eta >= 0.  Paper: 1.0 */
+  double aca_eps;           /* relative Frobenius stopping tolerance of ACA;
+                               0 => fixed-rank mode (every block gets
+                               min(max_rank, m, n) terms, as the paper's k)  */
+  int64_t mem_limit_bytes;  /* 0 => no limit; a build whose device footprint
+                               would exceed it fails with HM_ERR_OOM         */
+} hm_params;
+
+/* Fill *p with the defaults: leaf 32, max_rank 64, HM_F64, eta 1, eps 1e-6. */
+hm_status hm_params_default(hm_params* p);
+
+/*
+ * hm_build -- set up the H-matrix of the collocation operator of one mesh
+ * (Sec. 2.3 and Sec. 3; Algorithm 1).
+ *   vertices   host, double[n_vertices][3]
+ *   triangles  host, int32[n_triangles][3], vertex indices in [0, n_vertices);
+ *              every triangle must have positive area
+ *   p          host, build parameters (copied)
+ *   stream     hipStream_t
+ *   out        receives the new handle (owned by the caller, release with
+ *              hm_free); set to NULL on failure
+ * The host arrays are copied before return and may be freed afterwards.  The
+ * call returns when the handle is ready (it synchronises `stream`).
+ * Errors: HM_ERR_ARG (NULL pointers, n_triangles < 1, bad index, degenerate
+ * triangle, bad parameter), HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA (HM_STRICT).
+ */
+hm_status hm_build(const double* vertices, int64_t n_vertices,
+                   const int32_t* triangles, int64_t n_triangles,
+                   const hm_params* p, void* stream, hm_handle** out);
+
+/*
+ * hm_matvec -- y = H x, the approximate product of Sec. 2.3: dense leaves
+ * apply their stored block, admissible leaves apply U (V^T x).
+ *   x, y   device, [n, nrhs] row-major, dtype `dtype` (HM_F64 or HM_F32);
+ *          y is overwritten; x and y must not overlap
+ *   nrhs   number of right-hand sides, >= 1
+ * Accumulation is in double when either the storage or the vectors are
+ * double, else in float.  Stream-ordered; no host synchronisation.
+ * Deterministic: repeated calls give bitwise identical results.
+ */
+hm_status hm_matvec(hm_handle* h, const void* x, void* y, int32_t nrhs,
+                    int32_t dtype, void* stream);
+
+/*
+ * hm_matvec_T -- y = H^T x with the same storage (dense leaves transposed,
+ * admissible leaves apply V (U^T x)).  Arguments as hm_matvec.
+ */
+hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int32_t nrhs,
+                      int32_t dtype, void* stream);
+
+typedef struct {
+  double tol;          /* relative residual |f - H s| / |f| to reach, > 0   */
+  int32_t restart;     /* GMRES restart length m, 1..1000; 0 => 100         */
+  int32_t max_iter;    /* total Arnoldi steps allowed, >= 1                 */
+  int32_t transpose;   /* 1: solve H^T s = f (adjoint), 0: H s = f          */
+  int32_t use_x0;      /* 1: sigma holds the initial guess on entry         */
+} hm_solve_params;
+
+typedef struct {
+  int32_t iters;          /* Arnoldi steps taken (max over right-hand sides) */
+  int32_t restarts;       /* completed restart cycles                       */
+  int32_t converged;      /* number of right-hand sides that converged      */
+  int32_t pad;
+  double rel_residual;    /* max over rhs of the explicit |f - H s| / |f|   */
+} hm_solve_info;
+
+/*
+ * hm_solve -- restarted GMRES on H s = f (or H^T s = f): x0 = 0 unless
+ * use_x0, Arnoldi basis in double with classical Gram-Schmidt applied twice,
+ * Givens rotations on the host, one matvec per step; the residual is
+ * recomputed explicitly at every restart and at the end.  Each right-hand
+ * side is an independent system; all are advanced together.
+ *   f, sigma  device, [n, nrhs] row-major, dtype `dtype`
+ *   info      host, optional (may be NULL)
+ * Returns HM_OK when every column reached tol, HM_NOT_CONVERGED otherwise
+ * (sigma then holds the last iterate).  Synchronises `stream`.
+ */
+hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs,
+                   int32_t dtype, const hm_solve_params* sp,
+                   hm_solve_info* info, void* stream);
+
+/* Release every resource of h (NULL-safe); waits for work in flight. */
+void hm_free(hm_handle* h);
+
+/* ---- introspection (tests, benchmarks) --------------------------------- */
+
+typedef enum {
+  HM_Q_STATS = 0,         /* hm_stats                                        */
+  HM_Q_MORTON = 1,        /* uint64[n] Morton keys, application order        */
+  HM_Q_PERM = 2,          /* int32[n] pi: Morton position -> triangle        */
+  HM_Q_CLUSTERS = 3,      /* int32[ncl][4] (lo, hi, first child or -1, level),
+                             breadth-first order                             */
+  HM_Q_BOXES = 4,         /* double[ncl][6] (min xyz, max xyz)               */
+  HM_Q_DENSE_BLOCKS = 5,  /* int64[ndense][6] (row_lo,row_hi,col_lo,col_hi,
+                             arena offset of its first row slice, 0)          */
+  HM_Q_LR_BLOCKS = 6,     /* int64[nlr][6] (row_lo,row_hi,col_lo,col_hi,
+                             rank, cap_hit)                                  */
+  HM_Q_LEAVES = 7,        /* int32[nleaf][3] (lo, size, ld) in Morton order  */
+  HM_Q_TIMINGS = 8,       /* double[HM_NPHASE] milliseconds per setup phase  */
+  HM_Q_LR_FACTORS = 9     /* for LR block b = *(int64*)dst on entry: the
+                             dense factors U (m x r) then V (n x r), both
+                             column-major, in the build's storage type        */
+} hm_query_kind;
+
+#define HM_NPHASE 8        /* geometry, morton+sort, tree+boxes, partition,
+                              near field, aca, pack+items, total             */
+
+typedef struct {
+  int64_t n;
+  int64_t n_clusters, n_leaves, n_dense, n_lr, depth;
+  int64_t dense_entries;   /* sum over dense blocks of m*n                   */
+  int64_t lr_entries;      /* sum over admissible blocks of r*(m+n)          */
+  int64_t stored_bytes;    /* bytes of the stored operator (dense + factors,
+                              including leaf padding)                        */
+  int64_t rank_sum, rank_max, cap_hits;
+  int64_t aca_entry_evals; /* matrix entries evaluated by ACA                */
+  int64_t n_items_row, n_items_col;
+  int64_t device_bytes;    /* device memory held by the handle               */
+  int64_t precision;
+  int64_t aca_chunks;
+} hm_stats;
+
+/*
+ * hm_query -- copy a piece of the built structure to host memory `dst`
+ * (dst_bytes long).  *needed (optional) receives the required size; when
+ * dst is NULL or too small, nothing is copied and HM_ERR_ARG is returned
+ * (with *needed set).  Synchronises the handle's stream.
+ */
+hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes,
+                   int64_t* needed);
+
+/*
+ * hm_entries -- evaluate matrix entries a(rows[k], cols[k]) (application
+ * indices) on the device with the build's entry kernel and precision; the
+ * result is written to out[k] as double.  rows, cols, out: host arrays of
+ * length count.  Used to check the quadrature against the oracle.
+ */
+hm_status hm_entries(hm_handle* h, const int32_t* rows, const int32_t* cols,
+                     int64_t count, double* out);
+
+/* Thread-local description of the last error ("" if none). */
+const char* hm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

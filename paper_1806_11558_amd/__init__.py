@@ -1,0 +1,13 @@
+"""MI355X (gfx950) H-matrix library for the Laplace single-layer BIE.
+
+Python binding of ``libhm.so`` (C ABI in ``include/hm.h``).  The binding only
+marshals arguments: every step of the setup, the products and the solve runs
+in the library's HIP kernels.  If the library is not built, every call raises
+``HMLibraryMissing``; there is no fallback.
+"""
+from ._binding import (  # noqa: F401
+    HM_F32, HM_F64, HM_OK, HM_NOT_CONVERGED, HM_STRICT,
+    HMError, HMLibraryMissing, HMatrix, Params, SolveInfo, SolveParams, Stats,
+    hm_build, hm_entries, hm_free, hm_last_error, hm_matvec, hm_matvec_T,
+    hm_params_default, hm_query, hm_solve, lib, library_path,
+)

@@ -1,0 +1,313 @@
+"""ctypes binding of libhm.so: the C calls under their own names plus a small
+``HMatrix`` convenience class.  Device vectors are torch tensors (memory and
+streams only); the binding never computes anything itself."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HM_OK, HM_NOT_CONVERGED = 0, 1
+HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE = -1, -2, -3, -4, -5
+HM_F64, HM_F32 = 0, 1
+HM_STRICT = 1
+(HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
+ HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS) = range(10)
+HM_NPHASE = 8
+PHASES = ("geometry", "morton_sort", "tree_boxes", "partition", "near_field", "aca",
+          "pack_items", "total")
+
+_STATUS = {HM_ERR_ARG: "HM_ERR_ARG", HM_ERR_OOM: "HM_ERR_OOM", HM_ERR_HIP: "HM_ERR_HIP",
+           HM_ERR_ACA: "HM_ERR_ACA", HM_ERR_STATE: "HM_ERR_STATE"}
+
+
+class HMLibraryMissing(RuntimeError):
+    pass
+
+
+class HMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("max_rank", C.c_int32), ("precision", C.c_int32),
+                ("flags", C.c_int32), ("eta", C.c_double), ("aca_eps", C.c_double),
+                ("mem_limit_bytes", C.c_int64)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
+                ("transpose", C.c_int32), ("use_x0", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
+                ("pad", C.c_int32), ("rel_residual", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "n", "n_clusters", "n_leaves", "n_dense", "n_lr", "depth", "dense_entries",
+        "lr_entries", "stored_bytes", "rank_sum", "rank_max", "cap_hits", "aca_entry_evals",
+        "n_items_row", "n_items_col", "device_bytes", "precision", "aca_chunks")]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def library_path() -> str:
+    return os.environ.get("HM_LIBRARY", os.path.join(_HERE, "libhm.so"))
+
+
+def lib():
+    """Load libhm.so (raises HMLibraryMissing if it is not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise HMLibraryMissing(
+            f"{path} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.hm_params_default.argtypes = [C.POINTER(Params)]
+    L.hm_build.argtypes = [vp, i64, vp, i64, C.POINTER(Params), vp, C.POINTER(vp)]
+    L.hm_matvec.argtypes = [vp, vp, vp, i32, i32, vp]
+    L.hm_matvec_T.argtypes = [vp, vp, vp, i32, i32, vp]
+    L.hm_solve.argtypes = [vp, vp, vp, i32, i32, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]
+    L.hm_free.argtypes = [vp]
+    L.hm_free.restype = None
+    L.hm_query.argtypes = [vp, i32, vp, i64, C.POINTER(i64)]
+    L.hm_entries.argtypes = [vp, vp, vp, i64, vp]
+    L.hm_last_error.restype = C.c_char_p
+    L.hm_last_error.argtypes = []
+    for f in ("hm_params_default", "hm_build", "hm_matvec", "hm_matvec_T", "hm_solve",
+              "hm_query", "hm_entries"):
+        getattr(L, f).restype = C.c_int
+    _LIB = L
+    return L
+
+
+def hm_last_error() -> str:
+    return lib().hm_last_error().decode()
+
+
+def _check(status: int, ok=(HM_OK,)) -> int:
+    if status not in ok:
+        raise HMError(status, hm_last_error())
+    return status
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- C calls
+
+def hm_params_default() -> Params:
+    p = Params()
+    _check(lib().hm_params_default(C.byref(p)))
+    return p
+
+
+def hm_build(vertices: np.ndarray, triangles: np.ndarray, params: Params, stream=None) -> int:
+    v = np.ascontiguousarray(vertices, dtype=np.float64)
+    t = np.ascontiguousarray(triangles, dtype=np.int32)
+    if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+        raise HMError(HM_ERR_ARG, "vertices and triangles must be [*, 3]")
+    h = C.c_void_p()
+    _check(lib().hm_build(v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], C.byref(params),
+                          _stream_ptr(stream), C.byref(h)))
+    return h.value
+
+
+def _vec_args(x, n: int):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise HMError(HM_ERR_ARG, "vectors must be CUDA tensors")
+    if x.dtype not in (torch.float32, torch.float64):
+        raise HMError(HM_ERR_ARG, "vectors must be float32 or float64")
+    if not x.is_contiguous():
+        raise HMError(HM_ERR_ARG, "vectors must be contiguous")
+    if x.shape[0] != n or x.dim() not in (1, 2):
+        raise HMError(HM_ERR_ARG, f"vector shape {tuple(x.shape)} does not match n={n}")
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    return nrhs, (HM_F32 if x.dtype == torch.float32 else HM_F64)
+
+
+def hm_matvec(h: int, x, y, stream=None, transpose: bool = False) -> None:
+    n = x.shape[0]
+    nrhs, dt = _vec_args(x, n)
+    nrhs2, dt2 = _vec_args(y, n)
+    if (nrhs, dt) != (nrhs2, dt2) or x.shape != y.shape:
+        raise HMError(HM_ERR_ARG, "x and y must have the same shape and dtype")
+    f = lib().hm_matvec_T if transpose else lib().hm_matvec
+    _check(f(h, x.data_ptr(), y.data_ptr(), nrhs, dt, _stream_ptr(stream)))
+
+
+def hm_matvec_T(h: int, x, y, stream=None) -> None:
+    hm_matvec(h, x, y, stream, transpose=True)
+
+
+def hm_solve(h: int, f, sigma, sp: SolveParams, stream=None) -> tuple[int, SolveInfo]:
+    n = f.shape[0]
+    nrhs, dt = _vec_args(f, n)
+    if sigma.shape != f.shape or sigma.dtype != f.dtype:
+        raise HMError(HM_ERR_ARG, "f and sigma must have the same shape and dtype")
+    _vec_args(sigma, n)
+    info = SolveInfo()
+    st = lib().hm_solve(h, f.data_ptr(), sigma.data_ptr(), nrhs, dt, C.byref(sp), C.byref(info),
+                        _stream_ptr(stream))
+    _check(st, ok=(HM_OK, HM_NOT_CONVERGED))
+    return st, info
+
+
+def hm_free(h: int) -> None:
+    if h:
+        lib().hm_free(h)
+
+
+def hm_query(h: int, what: int, dst: np.ndarray | None = None) -> np.ndarray | int:
+    need = C.c_int64(0)
+    if dst is None:
+        lib().hm_query(h, what, None, 0, C.byref(need))
+        return int(need.value)
+    _check(lib().hm_query(h, what, dst.ctypes.data, dst.nbytes, C.byref(need)))
+    return dst
+
+
+def hm_entries(h: int, rows, cols) -> np.ndarray:
+    r = np.ascontiguousarray(rows, dtype=np.int32).reshape(-1)
+    c = np.ascontiguousarray(cols, dtype=np.int32).reshape(-1)
+    if r.shape != c.shape:
+        raise HMError(HM_ERR_ARG, "rows and cols differ in length")
+    out = np.empty(r.size, dtype=np.float64)
+    _check(lib().hm_entries(h, r.ctypes.data, c.ctypes.data, r.size, out.ctypes.data))
+    return out
+
+
+# ---------------------------------------------------------------- convenience
+
+class HMatrix:
+    """An H-matrix built on the current CUDA device (see include/hm.h)."""
+
+    def __init__(self, vertices, triangles, *, leaf_size: int = 32, eta: float = 1.0,
+                 eps: float = 1e-6, max_rank: int = 64, precision: str = "f64",
+                 strict: bool = False, mem_limit_bytes: int = 0, stream=None):
+        p = hm_params_default()
+        p.leaf_size = leaf_size
+        p.eta = eta
+        p.aca_eps = eps
+        p.max_rank = max_rank
+        p.precision = {"f64": HM_F64, "f32": HM_F32}[precision]
+        p.flags = HM_STRICT if strict else 0
+        p.mem_limit_bytes = mem_limit_bytes
+        self.params = p
+        self.n = int(np.asarray(triangles).shape[0])
+        self.storage_dtype = np.float32 if precision == "f32" else np.float64
+        self._h = hm_build(vertices, triangles, p, stream)
+
+    # products -------------------------------------------------------------
+    def matvec(self, x, out=None, stream=None, transpose: bool = False):
+        import torch
+        y = torch.empty_like(x) if out is None else out
+        hm_matvec(self._h, x, y, stream, transpose)
+        return y
+
+    def matvec_T(self, x, out=None, stream=None):
+        return self.matvec(x, out, stream, transpose=True)
+
+    def solve(self, f, *, tol: float = 1e-8, restart: int = 100, max_iter: int = 1000,
+              transpose: bool = False, x0=None, stream=None):
+        import torch
+        sp = SolveParams(tol=tol, restart=restart, max_iter=max_iter,
+                         transpose=1 if transpose else 0, use_x0=0 if x0 is None else 1)
+        sigma = torch.empty_like(f) if x0 is None else x0.clone()
+        st, info = hm_solve(self._h, f, sigma, sp, stream)
+        return sigma, info, st
+
+    # introspection --------------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().hm_query(self._h, HM_Q_STATS, C.addressof(s), C.sizeof(s), None))
+        return s.as_dict()
+
+    def timings(self) -> dict:
+        t = np.zeros(HM_NPHASE, dtype=np.float64)
+        hm_query(self._h, HM_Q_TIMINGS, t)
+        return dict(zip(PHASES, t.tolist()))
+
+    def _q(self, what, dtype, cols):
+        need = hm_query(self._h, what)
+        out = np.empty(need // np.dtype(dtype).itemsize, dtype=dtype)
+        hm_query(self._h, what, out)
+        return out.reshape(-1, cols) if cols > 1 else out
+
+    def morton_keys(self):
+        return self._q(HM_Q_MORTON, np.uint64, 1)
+
+    def perm(self):
+        return self._q(HM_Q_PERM, np.int32, 1)
+
+    def clusters(self):
+        return self._q(HM_Q_CLUSTERS, np.int32, 4)
+
+    def boxes(self):
+        return self._q(HM_Q_BOXES, np.float64, 6)
+
+    def leaves(self):
+        return self._q(HM_Q_LEAVES, np.int32, 3)
+
+    def dense_blocks(self):
+        return self._q(HM_Q_DENSE_BLOCKS, np.int64, 6)
+
+    def lr_blocks(self):
+        return self._q(HM_Q_LR_BLOCKS, np.int64, 6)
+
+    def lr_factors(self, b: int):
+        """Plain U (m x r) and V (n x r) of low-rank block b."""
+        blk = self.lr_blocks()[b]
+        m, n, r = int(blk[1] - blk[0]), int(blk[3] - blk[2]), int(blk[4])
+        buf = np.zeros(max(r * (m + n), 1), dtype=self.storage_dtype)
+        buf.view(np.int64)[0] = b if buf.itemsize == 8 else 0
+        if buf.itemsize != 8:
+            tmp = np.zeros(max(r * (m + n) // 2 + 1, 1), dtype=np.int64)
+            tmp[0] = b
+            need = C.c_int64(0)
+            raw = np.zeros(max(r * (m + n), 2), dtype=np.float32)
+            raw.view(np.int64)[0] = b
+            _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, raw.ctypes.data, raw.nbytes,
+                                  C.byref(need)))
+            buf = raw[: r * (m + n)]
+        else:
+            _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, buf.ctypes.data, buf.nbytes, None))
+            buf = buf[: r * (m + n)]
+        U = buf[: m * r].reshape(r, m).T.astype(np.float64)
+        V = buf[m * r:].reshape(r, n).T.astype(np.float64)
+        return U, V
+
+    def entries(self, rows, cols):
+        return hm_entries(self._h, rows, cols)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            hm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,997 @@
+// C ABI of the library and the host orchestration of the setup (Sec. 3:
+// clustering, level-wise block tree, batched near field, batched ACA), the
+// products and the GMRES loop.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+// ---- launchers defined in the other translation units
+void launch_centroids(const double* V, const int32_t* T, int64_t n, double* C, hipStream_t s);
+void launch_minmax(const double* C, int64_t n, double* out6, hipStream_t s);
+void launch_morton(const double* C, int64_t n, const double* a, double scale, uint64_t* keys,
+                   int32_t* idx, hipStream_t s);
+template <typename T>
+void launch_geom_sorted(const double* V, const int32_t* Tri, const int32_t* perm, int64_t n,
+                        double* c, T* o, T* aw, T* sf, hipStream_t s);
+int64_t build_cluster_tree(int64_t n, int leaf, Cluster* cl, int64_t cap,
+                           std::vector<int64_t>& level_beg, hipStream_t s);
+void launch_leaf_marks(const Cluster* cl, int64_t ncl, int64_t* mark, hipStream_t s);
+void launch_pos_leaf(const int64_t* mark, const int64_t* excl, int64_t n, int32_t* pos_leaf,
+                     hipStream_t s);
+void launch_leaf_table(const Cluster* cl, int64_t ncl, const int32_t* pos_leaf, int32_t* leaf_lo,
+                       int32_t* leaf_m, int32_t* leaf_cl, int64_t* leaf_ld, int2* cl_leaves,
+                       hipStream_t s);
+void launch_boxes(const Cluster* cl, const std::vector<int64_t>& level_beg, const int32_t* leaf_cl,
+                  int64_t nleaf, const double* c, int64_t n, double* box, hipStream_t s);
+void build_block_tree(const Cluster* cl, const double* box, double eta, int leaf, int2** adm_out,
+                      int64_t* nadm, int2** dns_out, int64_t* ndns, int64_t* depth, hipStream_t s);
+template <typename T>
+void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
+                    int64_t cnt, double* out, hipStream_t s);
+void launch_inverse_perm(const int32_t* perm, int64_t n, int32_t* inv, hipStream_t s);
+template <typename T>
+void launch_near(const Geom<T>& g, const int2* dns, int64_t nd, const Cluster* cl,
+                 const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
+                 const int2* cl_leaves, const int64_t* doff, T* D, hipStream_t s);
+void launch_dense_sizes(const int2* dns, int64_t nd, const Cluster* cl, const int32_t* leaf_lo,
+                        const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
+                        int64_t* sz, hipStream_t s);
+template <typename T>
+void launch_aca_slots(const int2* blk, int64_t nb, const Cluster* cl, int kmax, int64_t* slot,
+                      int64_t* is_big, hipStream_t s);
+void launch_split_lists(const int64_t* is_big, const int64_t* ob, int64_t nb, int32_t* big,
+                        int32_t* small, hipStream_t s);
+template <typename T>
+void launch_aca(const Geom<T>& g, const int2* blk, const Cluster* cl, const int64_t* slot,
+                int64_t slot0, T* pool, const int32_t* big, int64_t nbig, const int32_t* small,
+                int64_t nsmall, int kmax, double eps, int32_t* rank, int32_t* info, hipStream_t s);
+void launch_packed_sizes(const int2* blk, int64_t nb, const int32_t* rank, const int32_t* leaf_lo,
+                         const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
+                         int64_t* sz, hipStream_t s);
+template <typename T>
+void launch_pack(const int2* blk, int64_t nb, const Cluster* cl, const int32_t* leaf_lo,
+                 const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
+                 const int32_t* rank, const int64_t* slot, int64_t slot0, const T* pool, int kmax,
+                 const int64_t* fo, T* arena, uint64_t* ptr_out, hipStream_t s);
+void launch_lr_meta(const int2* lr, int64_t nl, const int32_t* rank, const int32_t* leaf_lo,
+                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves, int64_t* rk,
+                    int64_t* psz, hipStream_t s);
+void launch_item_counts(const int2* dns, int64_t nd, const int2* lr, int64_t nl,
+                        const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
+                        const int2* cl_leaves, int64_t* crow, int64_t* ccol, hipStream_t s);
+template <typename T>
+void launch_item_expand(const int2* dns, int64_t nd, const int2* lr, int64_t nl, const Cluster* cl,
+                        const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
+                        const int2* cl_leaves, const int64_t* doff, const T* D,
+                        const uint64_t* lrptr, const int32_t* rank, const int64_t* toff,
+                        const int64_t* pslot, const int64_t* orow, const int64_t* ocol, Item* irow,
+                        uint64_t* krow, Item* icol, uint64_t* kcol, hipStream_t s);
+void launch_iota(int32_t* v, int64_t n, hipStream_t s);
+void launch_gather_items(const Item* in, const int32_t* idx, int64_t n, Item* out, hipStream_t s);
+void launch_leaf_counts(const uint64_t* keys, int64_t n, int64_t* cnt, hipStream_t s);
+template <typename T>
+void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
+                   const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
+                   const int32_t* rank, const uint64_t* lrptr, T* out, int64_t total, hipStream_t s);
+
+
+
+
+int gmres_tiles(int64_t n);
+void gmres_dots(const double* Q, int64_t ldq, int nk, const double* w, int64_t n, int nr,
+                double* part, double* out, hipStream_t s);
+void gmres_orth_update(const double* Q, int64_t ldq, const double* h, int nk, int64_t n, int nr,
+                       double* w, hipStream_t s);
+void gmres_combine(const double* Q, int64_t ldq, const double* y, int nk, int64_t n, int nr,
+                   double* x, hipStream_t s);
+void gmres_scale_cols(const double* a, const double* sc, int64_t n, int nr, double* out,
+                      hipStream_t s);
+void gmres_sub(const double* a, const double* b, int64_t tot, double* out, hipStream_t s);
+void convert_f32_to_f64(const float* a, int64_t tot, double* out, hipStream_t s);
+void convert_f64_to_f32(const double* a, int64_t tot, float* out, hipStream_t s);
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+constexpr int kMaxNr = 16;   // right-hand sides per product pass
+
+}  // namespace hm
+
+using namespace hm;
+
+// ------------------------------------------------------------------ handle
+struct hm_handle {
+  int device = 0;
+  hm_params p{};
+  int64_t n = 0;
+  int f32 = 0;
+  size_t ts = 8;                 // bytes per stored value
+  std::vector<void*> owned;      // persistent allocations
+  int64_t bytes = 0;
+
+  double* c = nullptr;           // centroids, Morton order
+  void* o = nullptr;
+  void* aw = nullptr;
+  void* sf = nullptr;
+  uint64_t* keys = nullptr;      // Morton keys, application order
+  int32_t* perm = nullptr;       // Morton position -> triangle
+  int32_t* inv = nullptr;
+
+  int64_t ncl = 0, depth = 0;
+  Cluster* cl = nullptr;
+  double* box = nullptr;
+  int2* cl_leaves = nullptr;
+  int64_t nleaf = 0;
+  int32_t *leaf_lo = nullptr, *leaf_m = nullptr, *leaf_cl = nullptr;
+  int64_t* ldpre = nullptr;
+
+  int64_t nd = 0, nl = 0;
+  int2 *dns = nullptr, *lr = nullptr;
+  int64_t* doff = nullptr;
+  void* D = nullptr;
+  int64_t D_elems = 0;
+  int32_t *rank = nullptr, *info = nullptr;
+  uint64_t* lrptr = nullptr;
+  int64_t* lr_meta = nullptr;
+  int64_t lr_elems = 0;
+
+  int64_t nrow_items = 0, ncol_items = 0;
+  int32_t *row_beg = nullptr, *col_beg = nullptr;
+  Item *row_items = nullptr, *col_items = nullptr;
+
+  void *xp = nullptr, *partial = nullptr, *t = nullptr;
+  int grid = 1024;
+
+  hm_stats st{};
+  double ms[HM_NPHASE] = {0};
+
+  void* alloc(size_t b) {
+    if (b == 0) b = 16;
+    if (p.mem_limit_bytes > 0 && bytes + (int64_t)b > p.mem_limit_bytes)
+      throw Error{HM_ERR_OOM, "mem_limit_bytes exceeded (" + std::to_string(bytes + b) + " > " +
+                                  std::to_string(p.mem_limit_bytes) + ")"};
+    void* q = nullptr;
+    if (hipMalloc(&q, b) != hipSuccess || !q) {
+      (void)hipGetLastError();
+      throw Error{HM_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    }
+    owned.push_back(q);
+    bytes += (int64_t)b;
+    return q;
+  }
+  template <typename X>
+  X* alloc_t(size_t cnt) {
+    return static_cast<X*>(alloc(cnt * sizeof(X)));
+  }
+  ~hm_handle() {
+    for (void* q : owned) (void)hipFree(q);
+  }
+  MvPlan plan() const {
+    MvPlan P;
+    P.row_beg = row_beg;
+    P.row_items = row_items;
+    P.col_beg = col_beg;
+    P.col_items = col_items;
+    P.L = MvLeaves{leaf_lo, leaf_m, ldpre, nleaf};
+    P.lr_meta = lr_meta;
+    P.nlr = nl;
+    P.perm = perm;
+    P.n = n;
+    P.xp = xp;
+    P.partial = partial;
+    P.t = t;
+    P.grid = grid;
+    return P;
+  }
+};
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+template <typename F>
+hm_status guarded(F&& f) {
+  try {
+    g_err.clear();
+    return f();
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return HM_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return HM_ERR_STATE;
+  }
+}
+
+hm_status arg_error(const std::string& m) {
+  g_err = m;
+  return HM_ERR_ARG;
+}
+
+// Offsets + total of n int64 values (device); returns the total.
+int64_t scan_total(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+  scan_excl_i64(in, out, n, tmp, s);
+  return d2h_i64(tmp, s);
+}
+
+__global__ void k_lr_meta_fill(const int2* __restrict__ lr, int64_t nl, const int2* __restrict__ cll,
+                               const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
+                               const int64_t* __restrict__ pslot, int64_t* __restrict__ meta) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nl;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = lr[b];
+    const int2 lt = cll[ts.x], ls = cll[ts.y];
+    int64_t* M = meta + 6 * b;
+    M[0] = toff[b];
+    M[1] = pslot[b];
+    M[2] = rank[b];
+    M[3] = lt.y - lt.x + 1;
+    M[4] = ls.y - ls.x + 1;
+    M[5] = 0;
+  }
+}
+
+__global__ void k_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (int32_t)a[e];
+}
+
+// ---------------------------------------------------------------- the build
+template <typename T>
+void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T_host,
+                hipStream_t s) {
+  const int64_t n = h->n;
+  const hm_params& p = h->p;
+  const auto t_start = clk::now();
+  auto t0 = clk::now();
+  int64_t* tmp = dalloc_t<int64_t>(4, s);
+
+  // ---- upload + geometry (application order)
+  double* V = dalloc_t<double>(3 * nv, s);
+  int32_t* Tri = dalloc_t<int32_t>(3 * n, s);
+  HM_HIP(hipMemcpyAsync(V, V_host, 3 * nv * sizeof(double), hipMemcpyHostToDevice, s));
+  HM_HIP(hipMemcpyAsync(Tri, T_host, 3 * n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  double* Capp = dalloc_t<double>(3 * n, s);
+  launch_centroids(V, Tri, n, Capp, s);
+  HM_HIP(hipStreamSynchronize(s));
+  h->ms[0] = ms_since(t0);
+
+  // ---- Morton codes and sort
+  t0 = clk::now();
+  double* mm = dalloc_t<double>(6, s);
+  launch_minmax(Capp, n, mm, s);
+  double mmh[6];
+  HM_HIP(hipMemcpyAsync(mmh, mm, sizeof(mmh), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  double ext = 0.0;
+  for (int d = 0; d < 3; ++d) ext = std::max(ext, mmh[3 + d] - mmh[d]);
+  const double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
+  h->keys = h->alloc_t<uint64_t>(n);
+  h->perm = h->alloc_t<int32_t>(n);
+  h->inv = h->alloc_t<int32_t>(n);
+  uint64_t* ksort = dalloc_t<uint64_t>(n, s);
+  launch_morton(Capp, n, mmh, scale, h->keys, h->perm, s);
+  HM_HIP(hipMemcpyAsync(ksort, h->keys, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+  radix_sort_u64_i32(ksort, h->perm, n, 3 * kMortonBits, s);
+  launch_inverse_perm(h->perm, n, h->inv, s);
+  dfree(ksort, s);
+  dfree(mm, s);
+  dfree(Capp, s);
+
+  // ---- geometry in Morton order
+  h->c = h->alloc_t<double>(3 * n);
+  h->o = h->alloc(3 * kNQ * n * sizeof(T));
+  h->aw = h->alloc(n * sizeof(T));
+  h->sf = h->alloc(n * sizeof(T));
+  launch_geom_sorted<T>(V, Tri, h->perm, n, h->c, (T*)h->o, (T*)h->aw, (T*)h->sf, s);
+  dfree(V, s);
+  dfree(Tri, s);
+  HM_HIP(hipStreamSynchronize(s));
+  h->ms[1] = ms_since(t0);
+  const Geom<T> g{h->c, (const T*)h->o, (const T*)h->aw, (const T*)h->sf, n};
+
+  // ---- cluster tree, leaves, boxes
+  t0 = clk::now();
+  const int64_t cap = 2 * n + 2;
+  Cluster* cltmp = dalloc_t<Cluster>(cap, s);
+  std::vector<int64_t> level_beg;
+  h->ncl = build_cluster_tree(n, p.leaf_size, cltmp, cap, level_beg, s);
+  h->cl = h->alloc_t<Cluster>(h->ncl);
+  HM_HIP(hipMemcpyAsync(h->cl, cltmp, h->ncl * sizeof(Cluster), hipMemcpyDeviceToDevice, s));
+  dfree(cltmp, s);
+  int64_t* mark = dalloc_t<int64_t>(n, s);
+  int64_t* excl = dalloc_t<int64_t>(n, s);
+  HM_HIP(hipMemsetAsync(mark, 0, n * sizeof(int64_t), s));
+  launch_leaf_marks(h->cl, h->ncl, mark, s);
+  h->nleaf = scan_total(mark, excl, n, tmp, s);
+  int32_t* pos_leaf = dalloc_t<int32_t>(n, s);
+  launch_pos_leaf(mark, excl, n, pos_leaf, s);
+  dfree(mark, s);
+  dfree(excl, s);
+  h->leaf_lo = h->alloc_t<int32_t>(h->nleaf);
+  h->leaf_m = h->alloc_t<int32_t>(h->nleaf);
+  h->leaf_cl = h->alloc_t<int32_t>(h->nleaf);
+  h->cl_leaves = h->alloc_t<int2>(h->ncl);
+  h->ldpre = h->alloc_t<int64_t>(h->nleaf + 1);
+  int64_t* leaf_ld = dalloc_t<int64_t>(h->nleaf, s);
+  launch_leaf_table(h->cl, h->ncl, pos_leaf, h->leaf_lo, h->leaf_m, h->leaf_cl, leaf_ld,
+                    h->cl_leaves, s);
+  scan_excl_i64(leaf_ld, h->ldpre, h->nleaf, h->ldpre + h->nleaf, s);
+  dfree(leaf_ld, s);
+  dfree(pos_leaf, s);
+  h->box = h->alloc_t<double>(6 * h->ncl);
+  launch_boxes(h->cl, level_beg, h->leaf_cl, h->nleaf, h->c, n, h->box, s);
+  HM_HIP(hipStreamSynchronize(s));
+  h->ms[2] = ms_since(t0);
+
+  // ---- block cluster tree (Algorithm 1, level-wise)
+  t0 = clk::now();
+  int2 *adm = nullptr, *dns = nullptr;
+  build_block_tree(h->cl, h->box, p.eta, p.leaf_size, &adm, &h->nl, &dns, &h->nd, &h->depth, s);
+  h->lr = h->alloc_t<int2>(h->nl);
+  h->dns = h->alloc_t<int2>(h->nd);
+  if (h->nl) HM_HIP(hipMemcpyAsync(h->lr, adm, h->nl * sizeof(int2), hipMemcpyDeviceToDevice, s));
+  if (h->nd) HM_HIP(hipMemcpyAsync(h->dns, dns, h->nd * sizeof(int2), hipMemcpyDeviceToDevice, s));
+  dfree(adm, s);
+  dfree(dns, s);
+  HM_HIP(hipStreamSynchronize(s));
+  h->ms[3] = ms_since(t0);
+
+  // ---- near field (dense leaves)
+  t0 = clk::now();
+  h->doff = h->alloc_t<int64_t>(h->nd + 1);
+  {
+    int64_t* sz = dalloc_t<int64_t>(h->nd + 1, s);
+    launch_dense_sizes(h->dns, h->nd, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves, sz, s);
+    h->D_elems = scan_total(sz, h->doff, h->nd, tmp, s);
+    dfree(sz, s);
+  }
+  h->D = h->alloc(h->D_elems * sizeof(T));
+  launch_near<T>(g, h->dns, h->nd, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves, h->doff,
+                 (T*)h->D, s);
+  HM_HIP(hipStreamSynchronize(s));
+  h->ms[4] = ms_since(t0);
+
+  // ---- batched ACA in memory-bounded chunks
+  t0 = clk::now();
+  const int kmax = p.max_rank > 0 ? p.max_rank : 64;
+  h->rank = h->alloc_t<int32_t>(h->nl + 1);
+  h->info = h->alloc_t<int32_t>(h->nl + 1);
+  h->lrptr = h->alloc_t<uint64_t>(h->nl + 1);
+  int64_t nchunks = 0;
+  h->lr_elems = 0;
+  if (h->nl > 0) {
+    int64_t* slot = dalloc_t<int64_t>(h->nl, s);
+    int64_t* slot_off = dalloc_t<int64_t>(h->nl + 1, s);
+    int64_t* isbig = dalloc_t<int64_t>(h->nl, s);
+    launch_aca_slots<T>(h->lr, h->nl, h->cl, kmax, slot, isbig, s);
+    scan_excl_i64(slot, slot_off, h->nl, slot_off + h->nl, s);
+    std::vector<int64_t> hoff(h->nl + 1);
+    HM_HIP(hipMemcpyAsync(hoff.data(), slot_off, (h->nl + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    dfree(slot, s);
+    size_t freeb = 0, totb = 0;
+    HM_HIP(hipMemGetInfo(&freeb, &totb));
+    int64_t budget = (int64_t)(0.40 * (double)freeb);
+    if (p.mem_limit_bytes > 0) budget = std::min(budget, (p.mem_limit_bytes - h->bytes) / 2);
+    int64_t pool_elems = std::min<int64_t>(hoff[h->nl], std::max<int64_t>(budget / (int64_t)sizeof(T), 1));
+    // a single block must always fit
+    int64_t maxslot = 0;
+    for (int64_t b = 0; b < h->nl; ++b) maxslot = std::max(maxslot, hoff[b + 1] - hoff[b]);
+    pool_elems = std::max(pool_elems, maxslot);
+    if (p.mem_limit_bytes > 0 && h->bytes + pool_elems * (int64_t)sizeof(T) > p.mem_limit_bytes)
+      throw Error{HM_ERR_OOM, "mem_limit_bytes too small for the ACA workspace"};
+    T* pool = (T*)dalloc(pool_elems * sizeof(T), s);
+    int64_t* ob = dalloc_t<int64_t>(h->nl + 1, s);
+    int32_t* big = dalloc_t<int32_t>(h->nl, s);
+    int32_t* small = dalloc_t<int32_t>(h->nl, s);
+    int64_t* psz = dalloc_t<int64_t>(h->nl + 1, s);
+    int64_t* fo = dalloc_t<int64_t>(h->nl + 1, s);
+    int64_t b0 = 0;
+    while (b0 < h->nl) {
+      int64_t b1 = b0 + 1;
+      while (b1 < h->nl && hoff[b1 + 1] - hoff[b0] <= pool_elems) ++b1;
+      const int64_t nb = b1 - b0;
+      // workgroup / wavefront classes of the chunk's blocks
+      const int64_t nbig = scan_total(isbig + b0, ob, nb, tmp, s);
+      launch_split_lists(isbig + b0, ob, nb, big, small, s);
+      launch_aca<T>(g, h->lr + b0, h->cl, slot_off + b0, hoff[b0], pool, big, nbig, small,
+                    nb - nbig, kmax, p.aca_eps, h->rank + b0, h->info + b0, s);
+      launch_packed_sizes(h->lr + b0, nb, h->rank + b0, h->leaf_lo, h->leaf_m, h->ldpre,
+                          h->cl_leaves, psz, s);
+      const int64_t packed = scan_total(psz, fo, nb, tmp, s);
+      T* arena = (T*)h->alloc(packed * sizeof(T));
+      launch_pack<T>(h->lr + b0, nb, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
+                     h->rank + b0, slot_off + b0, hoff[b0], pool, kmax, fo, arena, h->lrptr + b0, s);
+      h->lr_elems += packed;
+      ++nchunks;
+      b0 = b1;
+    }
+    HM_HIP(hipStreamSynchronize(s));
+    dfree(pool, s);
+    dfree(ob, s);
+    dfree(big, s);
+    dfree(small, s);
+    dfree(psz, s);
+    dfree(fo, s);
+    dfree(slot_off, s);
+    dfree(isbig, s);
+  }
+  h->ms[5] = ms_since(t0);
+
+  // ---- product metadata and per-leaf item lists
+  t0 = clk::now();
+  int64_t toff_total = 0, pslot_total = 0;
+  int64_t* toff = dalloc_t<int64_t>(h->nl + 1, s);
+  int64_t* pslot = dalloc_t<int64_t>(h->nl + 1, s);
+  h->lr_meta = h->alloc_t<int64_t>(6 * (h->nl + 1));
+  if (h->nl > 0) {
+    int64_t* rk = dalloc_t<int64_t>(h->nl, s);
+    int64_t* psz = dalloc_t<int64_t>(h->nl, s);
+    launch_lr_meta(h->lr, h->nl, h->rank, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves, rk, psz, s);
+    toff_total = scan_total(rk, toff, h->nl, tmp, s);
+    pslot_total = scan_total(psz, pslot, h->nl, tmp, s);
+    k_lr_meta_fill<<<grid_for(h->nl, 256), 256, 0, s>>>(h->lr, h->nl, h->cl_leaves, h->rank, toff,
+                                                        pslot, h->lr_meta);
+    HM_LAUNCH_CHECK();
+    dfree(rk, s);
+    dfree(psz, s);
+  }
+  const int64_t nb_all = h->nd + h->nl;
+  int64_t* crow = dalloc_t<int64_t>(nb_all, s);
+  int64_t* ccol = dalloc_t<int64_t>(nb_all, s);
+  int64_t* orow = dalloc_t<int64_t>(nb_all, s);
+  int64_t* ocol = dalloc_t<int64_t>(nb_all, s);
+  launch_item_counts(h->dns, h->nd, h->lr, h->nl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
+                     crow, ccol, s);
+  h->nrow_items = scan_total(crow, orow, nb_all, tmp, s);
+  h->ncol_items = scan_total(ccol, ocol, nb_all, tmp, s);
+  if (h->nrow_items >= INT32_MAX || h->ncol_items >= INT32_MAX)
+    throw Error{HM_ERR_STATE, "item lists exceed 2^31 entries"};
+  Item* irow = dalloc_t<Item>(h->nrow_items, s);
+  Item* icol = dalloc_t<Item>(h->ncol_items, s);
+  uint64_t* krow = dalloc_t<uint64_t>(h->nrow_items, s);
+  uint64_t* kcol = dalloc_t<uint64_t>(h->ncol_items, s);
+  launch_item_expand<T>(h->dns, h->nd, h->lr, h->nl, h->cl, h->leaf_lo, h->leaf_m, h->ldpre,
+                        h->cl_leaves, h->doff, (const T*)h->D, h->lrptr, h->rank, toff, pslot, orow,
+                        ocol, irow, krow, icol, kcol, s);
+  dfree(crow, s);
+  dfree(ccol, s);
+  dfree(orow, s);
+  dfree(ocol, s);
+  dfree(toff, s);
+  dfree(pslot, s);
+  int leaf_bits = 1;
+  while ((1ll << leaf_bits) < h->nleaf) ++leaf_bits;
+  auto finish = [&](Item* items, uint64_t* keys, int64_t cnt, Item** out_items, int32_t** out_beg) {
+    int32_t* idx = dalloc_t<int32_t>(cnt, s);
+    launch_iota(idx, cnt, s);
+    radix_sort_u64_i32(keys, idx, cnt, leaf_bits, s);
+    *out_items = h->alloc_t<Item>(cnt);
+    launch_gather_items(items, idx, cnt, *out_items, s);
+    int64_t* lc = dalloc_t<int64_t>(h->nleaf + 1, s);
+    int64_t* lb = dalloc_t<int64_t>(h->nleaf + 1, s);
+    HM_HIP(hipMemsetAsync(lc, 0, (h->nleaf + 1) * sizeof(int64_t), s));
+    launch_leaf_counts(keys, cnt, lc, s);
+    scan_excl_i64(lc, lb, h->nleaf + 1, nullptr, s);
+    *out_beg = h->alloc_t<int32_t>(h->nleaf + 1);
+    k_to_i32<<<grid_for(h->nleaf + 1, 256), 256, 0, s>>>(lb, h->nleaf + 1, *out_beg);
+    HM_LAUNCH_CHECK();
+    dfree(idx, s);
+    dfree(lc, s);
+    dfree(lb, s);
+  };
+  finish(irow, krow, h->nrow_items, &h->row_items, &h->row_beg);
+  finish(icol, kcol, h->ncol_items, &h->col_items, &h->col_beg);
+  dfree(irow, s);
+  dfree(icol, s);
+  dfree(krow, s);
+  dfree(kcol, s);
+
+  // ---- product workspace (up to kMaxNr right-hand sides per pass)
+  h->xp = h->alloc((size_t)n * kMaxNr * sizeof(double));
+  h->partial = h->alloc((size_t)(pslot_total + 1) * kMaxNr * sizeof(double));
+  h->t = h->alloc((size_t)(toff_total + 1) * kMaxNr * sizeof(double));
+  int dev = 0, ncu = 0;
+  HM_HIP(hipGetDevice(&dev));
+  HM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  h->grid = std::max(ncu, 1) * 32;
+  HM_HIP(hipStreamSynchronize(s));
+  h->ms[6] = ms_since(t0);
+  dfree(tmp, s);
+
+  // ---- statistics
+  std::vector<int32_t> rk(h->nl), inf(h->nl);
+  std::vector<int2> lrh(h->nl), dnh(h->nd);
+  std::vector<Cluster> clh(h->ncl);
+  if (h->nl) {
+    HM_HIP(hipMemcpy(rk.data(), h->rank, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HM_HIP(hipMemcpy(inf.data(), h->info, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HM_HIP(hipMemcpy(lrh.data(), h->lr, h->nl * sizeof(int2), hipMemcpyDeviceToHost));
+  }
+  if (h->nd) HM_HIP(hipMemcpy(dnh.data(), h->dns, h->nd * sizeof(int2), hipMemcpyDeviceToHost));
+  HM_HIP(hipMemcpy(clh.data(), h->cl, h->ncl * sizeof(Cluster), hipMemcpyDeviceToHost));
+  hm_stats& st = h->st;
+  std::memset(&st, 0, sizeof(st));
+  st.n = n;
+  st.n_clusters = h->ncl;
+  st.n_leaves = h->nleaf;
+  st.n_dense = h->nd;
+  st.n_lr = h->nl;
+  st.depth = h->depth;
+  for (int64_t b = 0; b < h->nd; ++b) {
+    const Cluster t = clh[dnh[b].x], sg = clh[dnh[b].y];
+    st.dense_entries += (int64_t)(t.y - t.x) * (sg.y - sg.x);
+  }
+  for (int64_t b = 0; b < h->nl; ++b) {
+    const Cluster t = clh[lrh[b].x], sg = clh[lrh[b].y];
+    const int64_t m = t.y - t.x, nn = sg.y - sg.x;
+    st.lr_entries += (int64_t)rk[b] * (m + nn);
+    st.rank_sum += rk[b];
+    st.rank_max = std::max<int64_t>(st.rank_max, rk[b]);
+    st.cap_hits += inf[b] & 1;
+    const int64_t rows = inf[b] >> 1;
+    st.aca_entry_evals += rows * nn + (int64_t)rk[b] * m;
+  }
+  st.stored_bytes = (h->D_elems + h->lr_elems) * (int64_t)sizeof(T);
+  st.n_items_row = h->nrow_items;
+  st.n_items_col = h->ncol_items;
+  st.device_bytes = h->bytes;
+  st.precision = h->f32;
+  st.aca_chunks = nchunks;
+  h->ms[7] = ms_since(t_start);
+  if ((p.flags & HM_STRICT) && st.cap_hits > 0)
+    throw Error{HM_ERR_ACA, std::to_string(st.cap_hits) + " blocks reached max_rank"};
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+const char* hm_last_error(void) { return g_err.c_str(); }
+
+hm_status hm_params_default(hm_params* p) {
+  if (!p) return arg_error("hm_params_default: NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->leaf_size = 32;
+  p->max_rank = 64;
+  p->precision = HM_F64;
+  p->flags = 0;
+  p->eta = 1.0;
+  p->aca_eps = 1e-6;
+  p->mem_limit_bytes = 0;
+  return HM_OK;
+}
+
+hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* triangles,
+                   int64_t n_triangles, const hm_params* p, void* stream, hm_handle** out) {
+  if (!out) return arg_error("hm_build: out is NULL");
+  *out = nullptr;
+  if (!vertices || !triangles || !p) return arg_error("hm_build: NULL argument");
+  if (n_triangles < 1 || n_triangles > (int64_t)INT32_MAX / 2)
+    return arg_error("hm_build: n_triangles out of range");
+  if (n_vertices < 3 || n_vertices > (int64_t)INT32_MAX) return arg_error("hm_build: n_vertices out of range");
+  if (p->leaf_size < 1 || p->leaf_size > kMaxLeaf) return arg_error("hm_build: leaf_size must be in 1..64");
+  if (p->max_rank < 0 || p->max_rank > kMaxRank) return arg_error("hm_build: max_rank must be in 0..256");
+  if (p->precision != HM_F64 && p->precision != HM_F32) return arg_error("hm_build: bad precision");
+  if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return arg_error("hm_build: eta must be finite and >= 0");
+  if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps)) return arg_error("hm_build: aca_eps must be finite and >= 0");
+  if (p->mem_limit_bytes < 0) return arg_error("hm_build: mem_limit_bytes < 0");
+  if (p->flags & ~HM_STRICT) return arg_error("hm_build: unknown flag");
+  for (int64_t i = 0; i < 3 * n_vertices; ++i)
+    if (!std::isfinite(vertices[i])) return arg_error("hm_build: non-finite vertex coordinate");
+  for (int64_t t = 0; t < n_triangles; ++t) {
+    const int32_t a = triangles[3 * t], b = triangles[3 * t + 1], c = triangles[3 * t + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= n_vertices || b >= n_vertices || c >= n_vertices)
+      return arg_error("hm_build: triangle " + std::to_string(t) + " has a vertex index out of range");
+    const double* A = vertices + 3 * (int64_t)a;
+    const double* B = vertices + 3 * (int64_t)b;
+    const double* C = vertices + 3 * (int64_t)c;
+    const double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    const double e2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                          e1[0] * e2[1] - e1[1] * e2[0]};
+    if (!(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] > 0.0))
+      return arg_error("hm_build: triangle " + std::to_string(t) + " is degenerate");
+  }
+  return guarded([&]() -> hm_status {
+    std::unique_ptr<hm_handle> h(new hm_handle());
+    h->p = *p;
+    if (h->p.max_rank == 0) h->p.max_rank = 64;
+    h->n = n_triangles;
+    h->f32 = (p->precision == HM_F32) ? 1 : 0;
+    h->ts = h->f32 ? 4 : 8;
+    HM_HIP(hipGetDevice(&h->device));
+    hipStream_t s = as_stream(stream);
+    if (h->f32)
+      build_impl<float>(h.get(), vertices, n_vertices, triangles, s);
+    else
+      build_impl<double>(h.get(), vertices, n_vertices, triangles, s);
+    *out = h.release();
+    return HM_OK;
+  });
+}
+
+static hm_status matvec_common(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,
+                               void* stream, bool transposed) {
+  if (!h) return arg_error("hm_matvec: NULL handle");
+  if (!x || !y) return arg_error("hm_matvec: NULL vector");
+  if (nrhs < 1) return arg_error("hm_matvec: nrhs must be >= 1");
+  if (dtype != HM_F64 && dtype != HM_F32) return arg_error("hm_matvec: bad dtype");
+  const size_t vb = (size_t)h->n * nrhs * (dtype == HM_F32 ? 4 : 8);
+  const char* xb = (const char*)x;
+  const char* yb = (const char*)y;
+  if (xb < yb + vb && yb < xb + vb) return arg_error("hm_matvec: x and y overlap");
+  return guarded([&]() -> hm_status {
+    matvec_dispatch(h->plan(), h->f32, x, y, nrhs, dtype == HM_F32 ? 1 : 0, transposed,
+                    as_stream(stream));
+    return HM_OK;
+  });
+}
+
+hm_status hm_matvec(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,
+                    void* stream) {
+  return matvec_common(h, x, y, nrhs, dtype, stream, false);
+}
+
+hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,
+                      void* stream) {
+  return matvec_common(h, x, y, nrhs, dtype, stream, true);
+}
+
+// ------------------------------------------------------------------ GMRES
+hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32_t dtype,
+                   const hm_solve_params* sp, hm_solve_info* info, void* stream) {
+  if (!h) return arg_error("hm_solve: NULL handle");
+  if (!f || !sigma || !sp) return arg_error("hm_solve: NULL argument");
+  if (nrhs < 1 || nrhs > 256) return arg_error("hm_solve: nrhs must be in 1..256");
+  if (dtype != HM_F64 && dtype != HM_F32) return arg_error("hm_solve: bad dtype");
+  if (!(sp->tol > 0.0) || !std::isfinite(sp->tol)) return arg_error("hm_solve: tol must be > 0");
+  if (sp->restart < 0 || sp->restart > 1000) return arg_error("hm_solve: restart must be in 0..1000");
+  if (sp->max_iter < 1) return arg_error("hm_solve: max_iter must be >= 1");
+  return guarded([&]() -> hm_status {
+    hipStream_t s = as_stream(stream);
+    const int64_t n = h->n;
+    const int nr = nrhs;
+    const int64_t nv = n * nr;
+    const int m = sp->restart > 0 ? sp->restart : 100;
+    const bool tr = sp->transpose != 0;
+    const MvPlan P = h->plan();
+    auto apply = [&](const double* in, double* out) {
+      matvec_dispatch(P, h->f32, in, out, nr, 0, tr, s);
+    };
+    // device workspace (freed at return)
+    std::vector<void*> tmp;
+    auto A = [&](size_t cnt) {
+      double* q = (double*)dalloc(cnt * sizeof(double), s);
+      tmp.push_back(q);
+      return q;
+    };
+    double* Q = A((size_t)(m + 1) * nv);
+    double* fd = A(nv);
+    double* x = A(nv);
+    double* w = A(nv);
+    double* hdev = A((size_t)(m + 2) * nr * 2);
+    double* part = A((size_t)(m + 2) * gmres_tiles(n) * nr);
+    double* scl = A(nr);
+    double* ydev = A((size_t)(m + 1) * nr);
+    struct Free {
+      std::vector<void*>& v;
+      hipStream_t s;
+      ~Free() {
+        for (void* q : v) dfree(q, s);
+      }
+    } fr{tmp, s};
+
+    if (dtype == HM_F32) {
+      convert_f32_to_f64((const float*)f, nv, fd, s);
+      if (sp->use_x0) convert_f32_to_f64((const float*)sigma, nv, x, s);
+    } else {
+      HM_HIP(hipMemcpyAsync(fd, f, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (sp->use_x0) HM_HIP(hipMemcpyAsync(x, sigma, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (!sp->use_x0) HM_HIP(hipMemsetAsync(x, 0, nv * sizeof(double), s));
+
+    std::vector<double> hv((size_t)(m + 2) * nr * 2);
+    auto norms = [&](const double* v, std::vector<double>& out) {
+      gmres_dots(v, 0, 1, v, n, nr, part, hdev, s);
+      out.resize(nr);
+      HM_HIP(hipMemcpyAsync(out.data(), hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      for (auto& z : out) z = std::sqrt(std::max(z, 0.0));
+    };
+    std::vector<double> fn;
+    norms(fd, fn);
+    // r = f - H x  (into w)
+    auto residual = [&](std::vector<double>& rn) {
+      apply(x, w);
+      gmres_sub(fd, w, nv, w, s);
+      norms(w, rn);
+    };
+    std::vector<double> rn;
+    residual(rn);
+    std::vector<int> conv(nr, 0);
+    auto rel = [&](int c, double r) { return fn[c] > 0 ? r / fn[c] : 0.0; };
+    for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= sp->tol;
+    int total_it = 0, restarts = 0;
+    // per-column Arnoldi state
+    std::vector<double> H((size_t)(m + 1) * m * nr), cs((size_t)m * nr), sn((size_t)m * nr),
+        gv((size_t)(m + 1) * nr);
+    std::vector<int> kc(nr);
+    std::vector<double> sc(nr);
+    while (total_it < sp->max_iter) {
+      bool all = true;
+      for (int c = 0; c < nr; ++c) all = all && conv[c];
+      if (all) break;
+      // Q0 = r / |r| for active columns
+      for (int c = 0; c < nr; ++c) sc[c] = (!conv[c] && rn[c] > 0) ? 1.0 / rn[c] : 0.0;
+      HM_HIP(hipMemcpyAsync(scl, sc.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      gmres_scale_cols(w, scl, n, nr, Q, s);
+      std::vector<int> active(nr);
+      for (int c = 0; c < nr; ++c) {
+        active[c] = !conv[c];
+        kc[c] = 0;
+        std::fill(gv.begin() + (size_t)c * (m + 1), gv.begin() + (size_t)(c + 1) * (m + 1), 0.0);
+        gv[(size_t)c * (m + 1)] = rn[c];
+      }
+      int j = 0;
+      for (; j < m && total_it < sp->max_iter; ++j) {
+        double* qj = Q + (size_t)j * nv;
+        apply(qj, w);
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+          gmres_dots(Q, nv, j + 1, w, n, nr, part, hdev + (size_t)pass * (m + 2) * nr, s);
+          gmres_orth_update(Q, nv, hdev + (size_t)pass * (m + 2) * nr, j + 1, n, nr, w, s);
+        }
+        gmres_dots(w, 0, 1, w, n, nr, part, hdev + (size_t)(j + 1) * nr, s);
+        HM_HIP(hipMemcpyAsync(hv.data(), hdev, (size_t)(m + 2) * nr * 2 * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+        HM_HIP(hipStreamSynchronize(s));
+        ++total_it;
+        bool any = false;
+        for (int c = 0; c < nr; ++c) {
+          const double hn = std::sqrt(std::max(hv[(size_t)(j + 1) * nr + c], 0.0));
+          sc[c] = 0.0;
+          if (!active[c]) continue;
+          double* Hc = H.data() + (size_t)c * (m + 1) * m;
+          for (int k = 0; k <= j; ++k)
+            Hc[(size_t)k * m + j] = hv[(size_t)k * nr + c] + hv[(size_t)(m + 2) * nr + (size_t)k * nr + c];
+          Hc[(size_t)(j + 1) * m + j] = hn;
+          // previous rotations
+          double* csc = cs.data() + (size_t)c * m;
+          double* snc = sn.data() + (size_t)c * m;
+          for (int k = 0; k < j; ++k) {
+            const double a = Hc[(size_t)k * m + j], b = Hc[(size_t)(k + 1) * m + j];
+            Hc[(size_t)k * m + j] = csc[k] * a + snc[k] * b;
+            Hc[(size_t)(k + 1) * m + j] = -snc[k] * a + csc[k] * b;
+          }
+          const double a = Hc[(size_t)j * m + j], b = Hc[(size_t)(j + 1) * m + j];
+          const double rr = std::hypot(a, b);
+          csc[j] = rr > 0 ? a / rr : 1.0;
+          snc[j] = rr > 0 ? b / rr : 0.0;
+          Hc[(size_t)j * m + j] = rr;
+          Hc[(size_t)(j + 1) * m + j] = 0.0;
+          double* gc = gv.data() + (size_t)c * (m + 1);
+          gc[j + 1] = -snc[j] * gc[j];
+          gc[j] = csc[j] * gc[j];
+          kc[c] = j + 1;
+          const double est = rel(c, std::fabs(gc[j + 1]));
+          if (est <= sp->tol || hn == 0.0) {
+            active[c] = 0;
+          } else {
+            sc[c] = 1.0 / hn;
+            any = true;
+          }
+        }
+        if (!any) break;
+        HM_HIP(hipMemcpyAsync(scl, sc.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+        gmres_scale_cols(w, scl, n, nr, Q + (size_t)(j + 1) * nv, s);
+      }
+      // x += Q y  (upper triangular solves on the host)
+      int kmaxc = 0;
+      for (int c = 0; c < nr; ++c) kmaxc = std::max(kmaxc, kc[c]);
+      if (kmaxc > 0) {
+        std::vector<double> y((size_t)kmaxc * nr, 0.0);
+        for (int c = 0; c < nr; ++c) {
+          const double* Hc = H.data() + (size_t)c * (m + 1) * m;
+          const double* gc = gv.data() + (size_t)c * (m + 1);
+          for (int k = kc[c] - 1; k >= 0; --k) {
+            double v = gc[k];
+            for (int l = k + 1; l < kc[c]; ++l) v -= Hc[(size_t)k * m + l] * y[(size_t)l * nr + c];
+            y[(size_t)k * nr + c] = Hc[(size_t)k * m + k] != 0.0 ? v / Hc[(size_t)k * m + k] : 0.0;
+          }
+        }
+        HM_HIP(hipMemcpyAsync(ydev, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        gmres_combine(Q, nv, ydev, kmaxc, n, nr, x, s);
+      }
+      ++restarts;
+      residual(rn);
+      for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= sp->tol;
+    }
+    // result
+    if (dtype == HM_F32)
+      convert_f64_to_f32(x, nv, (float*)sigma, s);
+    else
+      HM_HIP(hipMemcpyAsync(sigma, x, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HM_HIP(hipStreamSynchronize(s));
+    int nconv = 0;
+    double worst = 0.0;
+    for (int c = 0; c < nr; ++c) {
+      nconv += conv[c];
+      worst = std::max(worst, rel(c, rn[c]));
+    }
+    if (info) {
+      info->iters = total_it;
+      info->restarts = restarts;
+      info->converged = nconv;
+      info->pad = 0;
+      info->rel_residual = worst;
+    }
+    return nconv == nr ? HM_OK : HM_NOT_CONVERGED;
+  });
+}
+
+void hm_free(hm_handle* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int64_t* needed) {
+  if (!h) return arg_error("hm_query: NULL handle");
+  return guarded([&]() -> hm_status {
+    HM_HIP(hipDeviceSynchronize());
+    int64_t need = 0;
+    auto check = [&](int64_t b) -> bool {
+      need = b;
+      if (needed) *needed = b;
+      return dst && dst_bytes >= b;
+    };
+    auto copy_dev = [&](const void* src, int64_t b) -> hm_status {
+      if (!check(b)) return arg_error("hm_query: destination too small");
+      if (b) HM_HIP(hipMemcpy(dst, src, b, hipMemcpyDeviceToHost));
+      return HM_OK;
+    };
+    switch (what) {
+      case HM_Q_STATS:
+        if (!check(sizeof(hm_stats))) return arg_error("hm_query: destination too small");
+        std::memcpy(dst, &h->st, sizeof(hm_stats));
+        return HM_OK;
+      case HM_Q_MORTON: return copy_dev(h->keys, h->n * 8);
+      case HM_Q_PERM: return copy_dev(h->perm, h->n * 4);
+      case HM_Q_CLUSTERS: return copy_dev(h->cl, h->ncl * 16);
+      case HM_Q_BOXES: return copy_dev(h->box, h->ncl * 48);
+      case HM_Q_TIMINGS:
+        if (!check(sizeof(h->ms))) return arg_error("hm_query: destination too small");
+        std::memcpy(dst, h->ms, sizeof(h->ms));
+        return HM_OK;
+      case HM_Q_LEAVES: {
+        if (!check(h->nleaf * 12)) return arg_error("hm_query: destination too small");
+        std::vector<int32_t> lo(h->nleaf), m(h->nleaf);
+        std::vector<int64_t> ld(h->nleaf + 1);
+        HM_HIP(hipMemcpy(lo.data(), h->leaf_lo, h->nleaf * 4, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(m.data(), h->leaf_m, h->nleaf * 4, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(ld.data(), h->ldpre, (h->nleaf + 1) * 8, hipMemcpyDeviceToHost));
+        int32_t* o = (int32_t*)dst;
+        for (int64_t k = 0; k < h->nleaf; ++k) {
+          o[3 * k] = lo[k];
+          o[3 * k + 1] = m[k];
+          o[3 * k + 2] = (int32_t)(ld[k + 1] - ld[k]);
+        }
+        return HM_OK;
+      }
+      case HM_Q_DENSE_BLOCKS:
+      case HM_Q_LR_BLOCKS: {
+        const bool dense = what == HM_Q_DENSE_BLOCKS;
+        const int64_t cnt = dense ? h->nd : h->nl;
+        if (!check(cnt * 48)) return arg_error("hm_query: destination too small");
+        std::vector<int2> bl(cnt);
+        std::vector<Cluster> clh(h->ncl);
+        std::vector<int64_t> off(dense ? cnt : 0);
+        std::vector<int32_t> rk(dense ? 0 : cnt), inf(dense ? 0 : cnt);
+        if (cnt)
+          HM_HIP(hipMemcpy(bl.data(), dense ? h->dns : h->lr, cnt * 8, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(clh.data(), h->cl, h->ncl * 16, hipMemcpyDeviceToHost));
+        if (dense && cnt) HM_HIP(hipMemcpy(off.data(), h->doff, cnt * 8, hipMemcpyDeviceToHost));
+        if (!dense && cnt) {
+          HM_HIP(hipMemcpy(rk.data(), h->rank, cnt * 4, hipMemcpyDeviceToHost));
+          HM_HIP(hipMemcpy(inf.data(), h->info, cnt * 4, hipMemcpyDeviceToHost));
+        }
+        int64_t* o = (int64_t*)dst;
+        for (int64_t b = 0; b < cnt; ++b) {
+          const Cluster t = clh[bl[b].x], sg = clh[bl[b].y];
+          o[6 * b] = t.x;
+          o[6 * b + 1] = t.y;
+          o[6 * b + 2] = sg.x;
+          o[6 * b + 3] = sg.y;
+          o[6 * b + 4] = dense ? off[b] : rk[b];
+          o[6 * b + 5] = dense ? 0 : (inf[b] & 1);
+        }
+        return HM_OK;
+      }
+      case HM_Q_LR_FACTORS: {
+        if (!dst || dst_bytes < 8) return arg_error("hm_query: block index expected in dst");
+        const int64_t b = *(const int64_t*)dst;
+        if (b < 0 || b >= h->nl) return arg_error("hm_query: block index out of range");
+        int2 ts;
+        HM_HIP(hipMemcpy(&ts, h->lr + b, 8, hipMemcpyDeviceToHost));
+        Cluster t, sg;
+        HM_HIP(hipMemcpy(&t, h->cl + ts.x, 16, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(&sg, h->cl + ts.y, 16, hipMemcpyDeviceToHost));
+        int32_t r = 0;
+        HM_HIP(hipMemcpy(&r, h->rank + b, 4, hipMemcpyDeviceToHost));
+        const int64_t total = (int64_t)r * ((t.y - t.x) + (sg.y - sg.x));
+        if (!check(total * (int64_t)h->ts)) return arg_error("hm_query: destination too small");
+        if (total == 0) return HM_OK;
+        void* buf = nullptr;
+        HM_HIP(hipMalloc(&buf, total * h->ts));
+        if (h->f32)
+          launch_unpack<float>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
+                               h->rank, h->lrptr, (float*)buf, total, 0);
+        else
+          launch_unpack<double>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
+                                h->rank, h->lrptr, (double*)buf, total, 0);
+        HM_HIP(hipMemcpy(dst, buf, total * h->ts, hipMemcpyDeviceToHost));
+        HM_HIP(hipFree(buf));
+        return HM_OK;
+      }
+      default:
+        return arg_error("hm_query: unknown query kind");
+    }
+    (void)need;
+  });
+}
+
+hm_status hm_entries(hm_handle* h, const int32_t* rows, const int32_t* cols, int64_t count,
+                     double* out) {
+  if (!h) return arg_error("hm_entries: NULL handle");
+  if (count < 0 || (count > 0 && (!rows || !cols || !out))) return arg_error("hm_entries: bad arguments");
+  for (int64_t k = 0; k < count; ++k)
+    if (rows[k] < 0 || rows[k] >= h->n || cols[k] < 0 || cols[k] >= h->n)
+      return arg_error("hm_entries: index out of range");
+  if (count == 0) return HM_OK;
+  return guarded([&]() -> hm_status {
+    hipStream_t s = 0;
+    int32_t* dr = dalloc_t<int32_t>(count, s);
+    int32_t* dc = dalloc_t<int32_t>(count, s);
+    double* dout = dalloc_t<double>(count, s);
+    HM_HIP(hipMemcpyAsync(dr, rows, count * 4, hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(dc, cols, count * 4, hipMemcpyHostToDevice, s));
+    if (h->f32) {
+      Geom<float> g{h->c, (const float*)h->o, (const float*)h->aw, (const float*)h->sf, h->n};
+      launch_entries<float>(g, h->inv, dr, dc, count, dout, s);
+    } else {
+      Geom<double> g{h->c, (const double*)h->o, (const double*)h->aw, (const double*)h->sf, h->n};
+      launch_entries<double>(g, h->inv, dr, dc, count, dout, s);
+    }
+    HM_HIP(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    dfree(dr, s);
+    dfree(dc, s);
+    dfree(dout, s);
+    HM_HIP(hipStreamSynchronize(s));
+    return HM_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Vector kernels of the restarted GMRES solver (double precision Arnoldi).
+//
+// The paper solves its symmetric Galerkin system by CG with one H-matrix
+// product per step (Sec. 4.1); the collocation matrix used here is not
+// symmetric, so the solve is GMRES with the same product.  All reductions
+// write per-tile partial sums that a second kernel adds in a fixed order, so
+// the solve is bitwise reproducible.
+#include "hm_internal.h"
+
+namespace hm {
+
+namespace {
+constexpr int kRowsPerTile = 2048;
+constexpr int kGT = 256;
+}
+
+int gmres_tiles(int64_t n) { return (int)ceil_div(n, kRowsPerTile); }
+
+// part[(k * tiles + tile) * nr + c] = sum over the tile's rows of
+// Q[k][i][c] * w[i][c]   (Q: nk vectors of n*nr doubles, stride ldq)
+__global__ __launch_bounds__(kGT) void k_dots(const double* __restrict__ Q, int64_t ldq,
+                                              const double* __restrict__ w, int64_t n, int nr,
+                                              int tiles, double* __restrict__ part) {
+  __shared__ double lds[kGT];
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const double* q = Q + (int64_t)k * ldq;
+  const int per = kGT / nr;               // threads per column (nr <= 256)
+  const int c = threadIdx.x % nr, r0 = threadIdx.x / nr;
+  double acc = 0.0;
+  if (r0 < per) {
+    const int64_t beg = (int64_t)tile * kRowsPerTile;
+    const int64_t end = min(beg + kRowsPerTile, n);
+    for (int64_t i = beg + r0; i < end; i += per) acc += q[i * nr + c] * w[i * nr + c];
+  }
+  lds[threadIdx.x] = (r0 < per) ? acc : 0.0;
+  __syncthreads();
+  if (threadIdx.x < nr) {
+    double s = 0.0;
+    for (int t = 0; t < per; ++t) s += lds[t * nr + threadIdx.x];
+    part[((int64_t)k * tiles + tile) * nr + threadIdx.x] = s;
+  }
+}
+
+// out[k * nr + c] = sum_tile part[(k * tiles + tile) * nr + c]
+__global__ void k_dots_final(const double* __restrict__ part, int nk, int tiles, int nr,
+                             double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk * nr) return;
+  const int k = e / nr, c = e % nr;
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s += part[((int64_t)k * tiles + t) * nr + c];
+  out[e] = s;
+}
+
+// w[i][c] -= sum_{k < nk} Q[k][i][c] h[k][c]   (h on the device)
+__global__ void k_orth_update(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ h,
+                              int nk, int64_t n, int nr, double* __restrict__ w) {
+  const int64_t tot = n * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nr);
+    double v = w[e];
+    for (int k = 0; k < nk; ++k) v -= Q[(int64_t)k * ldq + e] * h[k * nr + c];
+    w[e] = v;
+  }
+}
+
+// x[i][c] += sum_{k < nk} Q[k][i][c] y[k][c]
+__global__ void k_combine(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ y,
+                          int nk, int64_t n, int nr, double* __restrict__ x) {
+  const int64_t tot = n * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nr);
+    double v = x[e];
+    for (int k = 0; k < nk; ++k) v += Q[(int64_t)k * ldq + e] * y[k * nr + c];
+    x[e] = v;
+  }
+}
+
+// out[i][c] = a[i][c] * s[c]
+__global__ void k_scale_cols(const double* __restrict__ a, const double* __restrict__ s, int64_t n,
+                             int nr, double* __restrict__ out) {
+  const int64_t tot = n * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = a[e] * s[e % nr];
+}
+
+// out = a - b
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, int64_t tot,
+                      double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = a[e] - b[e];
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ a, int64_t tot, D* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (D)a[e];
+}
+
+// ------------------------------------------------------------------ launchers
+void gmres_dots(const double* Q, int64_t ldq, int nk, const double* w, int64_t n, int nr,
+                double* part, double* out, hipStream_t s) {
+  const int tiles = gmres_tiles(n);
+  dim3 grid(tiles, nk);
+  k_dots<<<grid, kGT, 0, s>>>(Q, ldq, w, n, nr, tiles, part);
+  HM_LAUNCH_CHECK();
+  k_dots_final<<<(unsigned)ceil_div(nk * nr, 256), 256, 0, s>>>(part, nk, tiles, nr, out);
+  HM_LAUNCH_CHECK();
+}
+void gmres_orth_update(const double* Q, int64_t ldq, const double* h, int nk, int64_t n, int nr,
+                       double* w, hipStream_t s) {
+  k_orth_update<<<grid_for(n * nr, 256, 8192), 256, 0, s>>>(Q, ldq, h, nk, n, nr, w);
+  HM_LAUNCH_CHECK();
+}
+void gmres_combine(const double* Q, int64_t ldq, const double* y, int nk, int64_t n, int nr,
+                   double* x, hipStream_t s) {
+  k_combine<<<grid_for(n * nr, 256, 8192), 256, 0, s>>>(Q, ldq, y, nk, n, nr, x);
+  HM_LAUNCH_CHECK();
+}
+void gmres_scale_cols(const double* a, const double* sc, int64_t n, int nr, double* out,
+                      hipStream_t s) {
+  k_scale_cols<<<grid_for(n * nr, 256, 8192), 256, 0, s>>>(a, sc, n, nr, out);
+  HM_LAUNCH_CHECK();
+}
+void gmres_sub(const double* a, const double* b, int64_t tot, double* out, hipStream_t s) {
+  k_sub<<<grid_for(tot, 256, 8192), 256, 0, s>>>(a, b, tot, out);
+  HM_LAUNCH_CHECK();
+}
+void convert_f32_to_f64(const float* a, int64_t tot, double* out, hipStream_t s) {
+  k_convert<float, double><<<grid_for(tot, 256, 8192), 256, 0, s>>>(a, tot, out);
+  HM_LAUNCH_CHECK();
+}
+void convert_f64_to_f32(const double* a, int64_t tot, float* out, hipStream_t s) {
+  k_convert<double, float><<<grid_for(tot, 256, 8192), 256, 0, s>>>(a, tot, out);
+  HM_LAUNCH_CHECK();
+}
+
+}  // namespace hm

@@ -1,0 +1,83 @@
+"""C ABI contract on the CPU: the library loads, exports every declared
+symbol, and rejects invalid arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1806_11558_amd as hm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hm.h")).read()
+    decl = r"^(?:hm_status|void|const char\*)\s+(hm_\w+)\s*\("
+    return sorted(set(re.findall(decl, src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hm.lib()
+    names = _declared()
+    assert {"hm_build", "hm_matvec", "hm_matvec_T", "hm_solve", "hm_free"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(hm.Params) == 40
+    assert ctypes.sizeof(hm.SolveParams) == 24
+    assert ctypes.sizeof(hm.SolveInfo) == 24
+    assert ctypes.sizeof(hm.Stats) == 18 * 8
+
+
+def test_defaults():
+    p = hm.hm_params_default()
+    assert (p.leaf_size, p.max_rank, p.precision, p.eta, p.aca_eps) == (32, 64, hm.HM_F64, 1.0, 1e-6)
+
+
+def _tri():
+    return np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0]]), np.array([[0, 1, 2]])
+
+
+@pytest.mark.parametrize("field,value", [
+    ("leaf_size", 0), ("leaf_size", 65), ("max_rank", -1), ("max_rank", 257),
+    ("precision", 7), ("eta", -1.0), ("eta", float("inf")), ("aca_eps", -1e-3),
+    ("aca_eps", float("nan")), ("mem_limit_bytes", -5), ("flags", 8)])
+def test_invalid_params_rejected(field, value):
+    V, T = _tri()
+    p = hm.hm_params_default()
+    setattr(p, field, value)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_build(V, T, p, stream=0)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("V,T,what", [
+    (np.zeros((3, 3)), np.array([[0, 1, 2]]), "degenerate"),
+    (np.eye(3), np.array([[0, 1, 3]]), "out of range"),
+    (np.eye(3), np.array([[0, -1, 2]]), "out of range"),
+    (np.array([[0.0, 0, 0], [1, 0, 0], [np.nan, 1, 0]]), np.array([[0, 1, 2]]), "non-finite"),
+    (np.eye(3), np.zeros((0, 3), dtype=np.int32), "n_triangles"),
+])
+def test_invalid_meshes_rejected(V, T, what):
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_build(V, T, hm.hm_params_default(), stream=0)
+    assert e.value.status == -1 and what in str(e.value)
+
+
+def test_null_handle_calls():
+    L = hm.lib()
+    assert L.hm_matvec(None, None, None, 1, 0, None) == -1
+    assert L.hm_matvec_T(None, None, None, 1, 0, None) == -1
+    assert L.hm_solve(None, None, None, 1, 0, None, None, None) == -1
+    assert L.hm_query(None, 0, None, 0, None) == -1
+    L.hm_free(None)           # NULL-safe
+    assert "NULL" in hm.hm_last_error() or hm.hm_last_error() == ""
+
+
+def test_null_build_out():
+    L = hm.lib()
+    assert L.hm_build(None, 3, None, 1, None, None, None) == -1
