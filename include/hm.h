@@ -70,13 +70,16 @@ typedef enum {
 /* flags */
 #define HM_STRICT 1       /* a block that reaches max_rank without meeting
                              the ACA stopping test fails the build           */
+#define HM_PROFILE 2      /* products record HIP events around each kernel on
+                             the caller's stream and synchronise it at the
+                             end of the call; totals via HM_Q_KERNEL_TIMES   */
 
 typedef struct {
   int32_t leaf_size;        /* C_leaf of (C3); 1..64.  Paper: 32             */
   int32_t max_rank;         /* ACA rank cap k_max; 1..256; 0 => 64.  The cap
                                is also limited by min(m, n) of each block     */
   int32_t precision;        /* hm_precision                                   */
-  int32_t flags;            /* HM_STRICT                                      */
+  int32_t flags;            /* HM_STRICT | HM_PROFILE                         */
   double eta;               /* admissibility parameter eta >= 0.  Paper: 1.0 */
   double aca_eps;           /* relative Frobenius stopping tolerance of ACA;
                                0 => fixed-rank mode (every block gets
@@ -176,19 +179,26 @@ typedef enum {
                              rank, cap_hit)                                  */
   HM_Q_LEAVES = 7,        /* int32[nleaf][3] (lo, size, ld) in Morton order  */
   HM_Q_TIMINGS = 8,       /* double[HM_NPHASE] milliseconds per setup phase  */
-  HM_Q_LR_FACTORS = 9     /* for LR block b = *(int64*)dst on entry: the
+  HM_Q_LR_FACTORS = 9,    /* for LR block b = *(int64*)dst on entry: the
                              dense factors U (m x r) then V (n x r), both
                              column-major, in the build's storage type        */
+  HM_Q_KERNEL_TIMES = 10  /* double[2][HM_NKERNEL]: accumulated milliseconds
+                             and launch counts of the product kernels
+                             (gather, phase 1, block sums, phase 2) since the
+                             build or the last query (reset on read); needs
+                             HM_PROFILE                                      */
 } hm_query_kind;
 
 #define HM_NPHASE 8        /* geometry, morton+sort, tree+boxes, partition,
                               near field, aca, pack+items, total             */
+#define HM_NKERNEL 4       /* gather, phase 1, block sums, phase 2           */
 
 typedef struct {
   int64_t n;
   int64_t n_clusters, n_leaves, n_dense, n_lr, depth;
   int64_t dense_entries;   /* sum over dense blocks of m*n                   */
   int64_t lr_entries;      /* sum over admissible blocks of r*(m+n)          */
+  int64_t lr_u_entries;    /* sum over admissible blocks of r*m              */
   int64_t stored_bytes;    /* bytes of the stored operator (dense + factors,
                               including leaf padding)                        */
   int64_t rank_sum, rank_max, cap_hits;

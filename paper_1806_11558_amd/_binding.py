@@ -12,9 +12,12 @@ HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE = -1, -2, -3, -4, -5
 HM_F64, HM_F32 = 0, 1
 HM_STRICT = 1
+HM_PROFILE = 2
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
- HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS) = range(10)
+ HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES) = range(11)
 HM_NPHASE = 8
+HM_NKERNEL = 4
+KERNELS = ("gather", "phase1", "block_sums", "phase2")
 PHASES = ("geometry", "morton_sort", "tree_boxes", "partition", "near_field", "aca",
           "pack_items", "total")
 
@@ -51,7 +54,7 @@ class SolveInfo(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "n_clusters", "n_leaves", "n_dense", "n_lr", "depth", "dense_entries",
-        "lr_entries", "stored_bytes", "rank_sum", "rank_max", "cap_hits", "aca_entry_evals",
+        "lr_entries", "lr_u_entries", "stored_bytes", "rank_sum", "rank_max", "cap_hits", "aca_entry_evals",
         "n_items_row", "n_items_col", "device_bytes", "precision", "aca_chunks")]
 
     def as_dict(self) -> dict:
@@ -205,14 +208,15 @@ class HMatrix:
 
     def __init__(self, vertices, triangles, *, leaf_size: int = 32, eta: float = 1.0,
                  eps: float = 1e-6, max_rank: int = 64, precision: str = "f64",
-                 strict: bool = False, mem_limit_bytes: int = 0, stream=None):
+                 strict: bool = False, profile: bool = False, mem_limit_bytes: int = 0,
+                 stream=None):
         p = hm_params_default()
         p.leaf_size = leaf_size
         p.eta = eta
         p.aca_eps = eps
         p.max_rank = max_rank
         p.precision = {"f64": HM_F64, "f32": HM_F32}[precision]
-        p.flags = HM_STRICT if strict else 0
+        p.flags = (HM_STRICT if strict else 0) | (HM_PROFILE if profile else 0)
         p.mem_limit_bytes = mem_limit_bytes
         self.params = p
         self.n = int(np.asarray(triangles).shape[0])
@@ -248,6 +252,14 @@ class HMatrix:
         t = np.zeros(HM_NPHASE, dtype=np.float64)
         hm_query(self._h, HM_Q_TIMINGS, t)
         return dict(zip(PHASES, t.tolist()))
+
+    def kernel_times(self) -> dict:
+        """Accumulated product-kernel milliseconds and launch counts since the
+        last call (needs profile=True)."""
+        t = np.zeros(2 * HM_NKERNEL, dtype=np.float64)
+        hm_query(self._h, HM_Q_KERNEL_TIMES, t)
+        return {k: {"ms": float(t[i]), "launches": int(t[HM_NKERNEL + i])}
+                for i, k in enumerate(KERNELS)}
 
     def _q(self, what, dtype, cols):
         need = hm_query(self._h, what)

@@ -153,6 +153,8 @@ struct hm_handle {
 
   hm_stats st{};
   double ms[HM_NPHASE] = {0};
+  MvProfile prof{};
+  bool profiling = false;
 
   void* alloc(size_t b) {
     if (b == 0) b = 16;
@@ -173,6 +175,8 @@ struct hm_handle {
     return static_cast<X*>(alloc(cnt * sizeof(X)));
   }
   ~hm_handle() {
+    if (profiling)
+      for (auto& e : prof.ev) (void)hipEventDestroy(e);
     for (void* q : owned) (void)hipFree(q);
   }
   MvPlan plan() const {
@@ -190,6 +194,7 @@ struct hm_handle {
     P.partial = partial;
     P.t = t;
     P.grid = grid;
+    P.prof = profiling ? const_cast<MvProfile*>(&prof) : nullptr;
     return P;
   }
 };
@@ -544,6 +549,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     const Cluster t = clh[lrh[b].x], sg = clh[lrh[b].y];
     const int64_t m = t.y - t.x, nn = sg.y - sg.x;
     st.lr_entries += (int64_t)rk[b] * (m + nn);
+    st.lr_u_entries += (int64_t)rk[b] * m;
     st.rank_sum += rk[b];
     st.rank_max = std::max<int64_t>(st.rank_max, rk[b]);
     st.cap_hits += inf[b] & 1;
@@ -597,7 +603,7 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
   if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return arg_error("hm_build: eta must be finite and >= 0");
   if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps)) return arg_error("hm_build: aca_eps must be finite and >= 0");
   if (p->mem_limit_bytes < 0) return arg_error("hm_build: mem_limit_bytes < 0");
-  if (p->flags & ~HM_STRICT) return arg_error("hm_build: unknown flag");
+  if (p->flags & ~(HM_STRICT | HM_PROFILE)) return arg_error("hm_build: unknown flag");
   for (int64_t i = 0; i < 3 * n_vertices; ++i)
     if (!std::isfinite(vertices[i])) return arg_error("hm_build: non-finite vertex coordinate");
   for (int64_t t = 0; t < n_triangles; ++t) {
@@ -622,6 +628,10 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
     h->f32 = (p->precision == HM_F32) ? 1 : 0;
     h->ts = h->f32 ? 4 : 8;
     HM_HIP(hipGetDevice(&h->device));
+    if (p->flags & HM_PROFILE) {
+      for (auto& e : h->prof.ev) HM_HIP(hipEventCreate(&e));
+      h->profiling = true;
+    }
     hipStream_t s = as_stream(stream);
     if (h->f32)
       build_impl<float>(h.get(), vertices, n_vertices, triangles, s);
@@ -881,6 +891,18 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
       case HM_Q_PERM: return copy_dev(h->perm, h->n * 4);
       case HM_Q_CLUSTERS: return copy_dev(h->cl, h->ncl * 16);
       case HM_Q_BOXES: return copy_dev(h->box, h->ncl * 48);
+      case HM_Q_KERNEL_TIMES: {
+        if (!h->profiling) return arg_error("hm_query: build without HM_PROFILE");
+        if (!check(8 * 2 * HM_NKERNEL)) return arg_error("hm_query: destination too small");
+        double* o = (double*)dst;
+        for (int k = 0; k < HM_NKERNEL; ++k) {
+          o[k] = h->prof.ms[k];
+          o[HM_NKERNEL + k] = h->prof.launches[k];
+          h->prof.ms[k] = 0;
+          h->prof.launches[k] = 0;
+        }
+        return HM_OK;
+      }
       case HM_Q_TIMINGS:
         if (!check(sizeof(h->ms))) return arg_error("hm_query: destination too small");
         std::memcpy(dst, h->ms, sizeof(h->ms));

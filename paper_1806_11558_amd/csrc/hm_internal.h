@@ -80,6 +80,12 @@ struct MvLeaves {
   const int64_t* ldpre;   // prefix of ld over leaves (nleaf + 1 entries)
   int64_t nleaf;
 };
+// Optional per-kernel timing of the products (HM_PROFILE).
+struct MvProfile {
+  hipEvent_t ev[5];
+  double ms[4];
+  double launches[4];
+};
 struct MvPlan {
   const int32_t* row_beg;   // leaf -> first row item (nleaf + 1)
   const Item* row_items;    // dense row slices and U slices
@@ -94,6 +100,7 @@ struct MvPlan {
   void* partial;            // workspace: per-slice partial products
   void* t;                  // workspace: V^T x (or U^T x) per block
   int grid;
+  MvProfile* prof;          // null unless profiling
 };
 void matvec_dispatch(const MvPlan& P, int storage_f32, const void* x, void* y, int nrhs,
                      int vec_f32, bool transposed, hipStream_t s);

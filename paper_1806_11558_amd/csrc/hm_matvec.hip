@@ -275,8 +275,11 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   A* xp = static_cast<A*>(P.xp);
   A* partial = static_cast<A*>(P.partial);
   A* t = static_cast<A*>(P.t);
+  MvProfile* pr = P.prof;
+  if (pr) HM_HIP(hipEventRecord(pr->ev[0], s));
   k_gather<VT, A><<<grid_for(P.n * NR, 256, 4096), 256, 0, s>>>(x, nrhs, k0, NR, P.perm, P.n, xp);
   HM_LAUNCH_CHECK();
+  if (pr) HM_HIP(hipEventRecord(pr->ev[1], s));
   const int32_t* b1 = transposed ? P.row_beg : P.col_beg;
   const Item* i1 = transposed ? P.row_items : P.col_items;
   const int32_t* b2 = transposed ? P.col_beg : P.row_beg;
@@ -285,13 +288,27 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   if (P.nlr > 0) {
     k_mv_phase1<T, A, NR><<<g, 256, 0, s>>>(b1, i1, P.L, xp, partial);
     HM_LAUNCH_CHECK();
+  }
+  if (pr) HM_HIP(hipEventRecord(pr->ev[2], s));
+  if (P.nlr > 0) {
     k_mv_sum<A, NR><<<grid_for(P.nlr, 256), 256, 0, s>>>(P.lr_meta, P.nlr, transposed ? 1 : 0,
                                                           partial, t);
     HM_LAUNCH_CHECK();
   }
+  if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
   k_mv_phase2<T, A, VT, NR><<<g, 256, 0, s>>>(b2, i2, P.L, xp, t, transposed ? 1 : 0, P.perm, y,
                                                nrhs, k0);
   HM_LAUNCH_CHECK();
+  if (pr) {
+    HM_HIP(hipEventRecord(pr->ev[4], s));
+    HM_HIP(hipEventSynchronize(pr->ev[4]));
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.f;
+      HM_HIP(hipEventElapsedTime(&ms, pr->ev[k], pr->ev[k + 1]));
+      pr->ms[k] += ms;
+      pr->launches[k] += 1;
+    }
+  }
 }
 
 template <typename T, typename A, typename VT>
