@@ -70,10 +70,11 @@ def mv_bytes(st, s_store, s_vec, s_acc, nrhs=1):
 
 def phase2_bytes(st, s_store, s_acc, s_vec, nrhs=1):
     """Algorithmic bytes of the dominant kernel (dense blocks and U slices
-    applied per row leaf): stored values, gathered x and t once, y once."""
+    applied per row leaf): stored values, gathered x and t once, y once,
+    the permutation and one 4-byte column index per panel column."""
     n = st["n"]
     return (s_store * (st["dense_entries"] + st["lr_u_entries"]) + n * nrhs * s_acc
-            + st["rank_sum"] * nrhs * s_acc + n * nrhs * s_vec + 4 * n + 32 * st["n_items_row"])
+            + st["rank_sum"] * nrhs * s_acc + n * nrhs * s_vec + 4 * n + 4 * st["n_panel_cols"])
 
 
 def run_form(hm, torch, V, T, args, prec, xg, fg, keep):
@@ -187,7 +188,7 @@ def main():
         B16 = mv_bytes(st, s_store, s_vec, s_acc, 16)
         ms = float(np.median([m for r in rs for m in r["ms"]]))
         ms16 = float(np.median([m for r in rs for m in r["ms16"]]))
-        p2 = [r["kt"]["phase2"] for r in rs]
+        p2 = [r["kt"]["fwd_panels"] for r in rs]
         p2_ms = sum(q["ms"] for q in p2) / max(1, sum(q["launches"] for q in p2))
         p2_B = phase2_bytes(st, s_store, s_acc, s_vec)
         o = dict(
@@ -197,7 +198,7 @@ def main():
             matvec16_ms=ms16, matvec16_gbs=B16 / ms16 / 1e6,
             phase2_ms=p2_ms, phase2_bytes=p2_B, phase2_gbs=p2_B / p2_ms / 1e6,
             kernel_ms_per_launch={k: (v["ms"] / v["launches"] if v["launches"] else None)
-                                  for k, v in rs[-1]["kt"].items()},
+                                  for k, v in rs[-1]["kt"].items() if v["launches"]},
             gmres_iters=rs[-1]["gmres_iters"], gmres_s=float(np.median([r["solve_s"] for r in rs])),
             gmres_rel_residual=rs[-1]["gmres_rel_residual"],
             stats={k: st[k] for k in ("n_dense", "n_lr", "dense_entries", "lr_entries",
@@ -234,7 +235,7 @@ def main():
         "matvec_pct_hbm_peak": {p: round(100 * out[p]["matvec_gbs"] / HBM_PEAK_GBS, 1) for p in out},
         "rel_err_sampled": {p: out[p].get("rel_err_sampled") for p in out},
         "roofline": {
-            "kernel": "k_mv_phase2 (dense blocks + U slices per row leaf), " + main_form,
+            "kernel": "k_fwd2 (row-leaf panels: dense blocks + U slices), " + main_form,
             "bound": "hbm",
             "achieved": round(M["phase2_gbs"], 1),
             "peak": HBM_PEAK_GBS,

@@ -183,15 +183,17 @@ typedef enum {
                              dense factors U (m x r) then V (n x r), both
                              column-major, in the build's storage type        */
   HM_Q_KERNEL_TIMES = 10  /* double[2][HM_NKERNEL]: accumulated milliseconds
-                             and launch counts of the product kernels
-                             (gather, phase 1, block sums, phase 2) since the
-                             build or the last query (reset on read); needs
-                             HM_PROFILE                                      */
+                             and launch counts of the product stages since
+                             the build or the last query (reset on read);
+                             needs HM_PROFILE.  Stages: forward gather,
+                             forward V^T x, (unused), forward panels, then
+                             transposed gather, transposed panel dots,
+                             transposed block sums, transposed column leaves */
 } hm_query_kind;
 
 #define HM_NPHASE 8        /* geometry, morton+sort, tree+boxes, partition,
                               near field, aca, pack+items, total             */
-#define HM_NKERNEL 4       /* gather, phase 1, block sums, phase 2           */
+#define HM_NKERNEL 8       /* product stages, see HM_Q_KERNEL_TIMES          */
 
 typedef struct {
   int64_t n;
@@ -203,7 +205,8 @@ typedef struct {
                               including leaf padding)                        */
   int64_t rank_sum, rank_max, cap_hits;
   int64_t aca_entry_evals; /* matrix entries evaluated by ACA                */
-  int64_t n_items_row, n_items_col;
+  int64_t n_panel_cols;     /* columns of all row-leaf panels                 */
+  int64_t n_titems;         /* items of the transposed product's column lists */
   int64_t device_bytes;    /* device memory held by the handle               */
   int64_t precision;
   int64_t aca_chunks;

@@ -16,8 +16,9 @@ HM_PROFILE = 2
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
  HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES) = range(11)
 HM_NPHASE = 8
-HM_NKERNEL = 4
-KERNELS = ("gather", "phase1", "block_sums", "phase2")
+HM_NKERNEL = 8
+KERNELS = ("fwd_gather", "fwd_vtx", "fwd_unused", "fwd_panels",
+           "tr_gather", "tr_panel_dots", "tr_block_sums", "tr_columns")
 PHASES = ("geometry", "morton_sort", "tree_boxes", "partition", "near_field", "aca",
           "pack_items", "total")
 
@@ -55,7 +56,7 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "n_clusters", "n_leaves", "n_dense", "n_lr", "depth", "dense_entries",
         "lr_entries", "lr_u_entries", "stored_bytes", "rank_sum", "rank_max", "cap_hits", "aca_entry_evals",
-        "n_items_row", "n_items_col", "device_bytes", "precision", "aca_chunks")]
+        "n_panel_cols", "n_titems", "device_bytes", "precision", "aca_chunks")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

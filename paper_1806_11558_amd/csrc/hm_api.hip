@@ -37,53 +37,6 @@ template <typename T>
 void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
                     int64_t cnt, double* out, hipStream_t s);
 void launch_inverse_perm(const int32_t* perm, int64_t n, int32_t* inv, hipStream_t s);
-template <typename T>
-void launch_near(const Geom<T>& g, const int2* dns, int64_t nd, const Cluster* cl,
-                 const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
-                 const int2* cl_leaves, const int64_t* doff, T* D, hipStream_t s);
-void launch_dense_sizes(const int2* dns, int64_t nd, const Cluster* cl, const int32_t* leaf_lo,
-                        const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                        int64_t* sz, hipStream_t s);
-template <typename T>
-void launch_aca_slots(const int2* blk, int64_t nb, const Cluster* cl, int kmax, int64_t* slot,
-                      int64_t* is_big, hipStream_t s);
-void launch_split_lists(const int64_t* is_big, const int64_t* ob, int64_t nb, int32_t* big,
-                        int32_t* small, hipStream_t s);
-template <typename T>
-void launch_aca(const Geom<T>& g, const int2* blk, const Cluster* cl, const int64_t* slot,
-                int64_t slot0, T* pool, const int32_t* big, int64_t nbig, const int32_t* small,
-                int64_t nsmall, int kmax, double eps, int32_t* rank, int32_t* info, hipStream_t s);
-void launch_packed_sizes(const int2* blk, int64_t nb, const int32_t* rank, const int32_t* leaf_lo,
-                         const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                         int64_t* sz, hipStream_t s);
-template <typename T>
-void launch_pack(const int2* blk, int64_t nb, const Cluster* cl, const int32_t* leaf_lo,
-                 const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                 const int32_t* rank, const int64_t* slot, int64_t slot0, const T* pool, int kmax,
-                 const int64_t* fo, T* arena, uint64_t* ptr_out, hipStream_t s);
-void launch_lr_meta(const int2* lr, int64_t nl, const int32_t* rank, const int32_t* leaf_lo,
-                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves, int64_t* rk,
-                    int64_t* psz, hipStream_t s);
-void launch_item_counts(const int2* dns, int64_t nd, const int2* lr, int64_t nl,
-                        const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
-                        const int2* cl_leaves, int64_t* crow, int64_t* ccol, hipStream_t s);
-template <typename T>
-void launch_item_expand(const int2* dns, int64_t nd, const int2* lr, int64_t nl, const Cluster* cl,
-                        const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
-                        const int2* cl_leaves, const int64_t* doff, const T* D,
-                        const uint64_t* lrptr, const int32_t* rank, const int64_t* toff,
-                        const int64_t* pslot, const int64_t* orow, const int64_t* ocol, Item* irow,
-                        uint64_t* krow, Item* icol, uint64_t* kcol, hipStream_t s);
-void launch_iota(int32_t* v, int64_t n, hipStream_t s);
-void launch_gather_items(const Item* in, const int32_t* idx, int64_t n, Item* out, hipStream_t s);
-void launch_leaf_counts(const uint64_t* keys, int64_t n, int64_t* cnt, hipStream_t s);
-template <typename T>
-void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
-                   const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                   const int32_t* rank, const uint64_t* lrptr, T* out, int64_t total, hipStream_t s);
-
-
-
 
 int gmres_tiles(int64_t n);
 void gmres_dots(const double* Q, int64_t ldq, int nk, const double* w, int64_t n, int nr,
@@ -136,19 +89,10 @@ struct hm_handle {
 
   int64_t nd = 0, nl = 0;
   int2 *dns = nullptr, *lr = nullptr;
-  int64_t* doff = nullptr;
-  void* D = nullptr;
-  int64_t D_elems = 0;
-  int32_t *rank = nullptr, *info = nullptr;
-  uint64_t* lrptr = nullptr;
-  int64_t* lr_meta = nullptr;
-  int64_t lr_elems = 0;
+  Storage sto;
 
-  int64_t nrow_items = 0, ncol_items = 0;
-  int32_t *row_beg = nullptr, *col_beg = nullptr;
-  Item *row_items = nullptr, *col_items = nullptr;
-
-  void *xp = nullptr, *partial = nullptr, *t = nullptr;
+  void *z = nullptr, *w = nullptr;
+  int max_nr_t = 1;
   int grid = 1024;
 
   hm_stats st{};
@@ -181,18 +125,20 @@ struct hm_handle {
   }
   MvPlan plan() const {
     MvPlan P;
-    P.row_beg = row_beg;
-    P.row_items = row_items;
-    P.col_beg = col_beg;
-    P.col_items = col_items;
-    P.L = MvLeaves{leaf_lo, leaf_m, ldpre, nleaf};
-    P.lr_meta = lr_meta;
+    P.runs = sto.runs;
+    P.nruns = sto.nruns;
+    P.colmap = sto.colmap;
+    P.meta = sto.meta;
     P.nlr = nl;
+    P.ucol = sto.ucol;
+    P.tbeg = sto.tbeg;
+    P.titems = sto.titems;
+    P.L = MvLeaves{leaf_lo, leaf_m, ldpre, nleaf};
     P.perm = perm;
     P.n = n;
-    P.xp = xp;
-    P.partial = partial;
-    P.t = t;
+    P.z = z;
+    P.w = w;
+    P.max_nr_t = max_nr_t;
     P.grid = grid;
     P.prof = profiling ? const_cast<MvProfile*>(&prof) : nullptr;
     return P;
@@ -232,29 +178,6 @@ hm_status arg_error(const std::string& m) {
 int64_t scan_total(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
   scan_excl_i64(in, out, n, tmp, s);
   return d2h_i64(tmp, s);
-}
-
-__global__ void k_lr_meta_fill(const int2* __restrict__ lr, int64_t nl, const int2* __restrict__ cll,
-                               const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
-                               const int64_t* __restrict__ pslot, int64_t* __restrict__ meta) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nl;
-       b += (int64_t)gridDim.x * blockDim.x) {
-    const int2 ts = lr[b];
-    const int2 lt = cll[ts.x], ls = cll[ts.y];
-    int64_t* M = meta + 6 * b;
-    M[0] = toff[b];
-    M[1] = pslot[b];
-    M[2] = rank[b];
-    M[3] = lt.y - lt.x + 1;
-    M[4] = ls.y - ls.x + 1;
-    M[5] = 0;
-  }
-}
-
-__global__ void k_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    out[e] = (int32_t)a[e];
 }
 
 // ---------------------------------------------------------------- the build
@@ -358,168 +281,37 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   HM_HIP(hipStreamSynchronize(s));
   h->ms[3] = ms_since(t0);
 
-  // ---- near field (dense leaves)
-  t0 = clk::now();
-  h->doff = h->alloc_t<int64_t>(h->nd + 1);
+  // ---- near field, batched ACA, panels and product plan
   {
-    int64_t* sz = dalloc_t<int64_t>(h->nd + 1, s);
-    launch_dense_sizes(h->dns, h->nd, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves, sz, s);
-    h->D_elems = scan_total(sz, h->doff, h->nd, tmp, s);
-    dfree(sz, s);
-  }
-  h->D = h->alloc(h->D_elems * sizeof(T));
-  launch_near<T>(g, h->dns, h->nd, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves, h->doff,
-                 (T*)h->D, s);
-  HM_HIP(hipStreamSynchronize(s));
-  h->ms[4] = ms_since(t0);
-
-  // ---- batched ACA in memory-bounded chunks
-  t0 = clk::now();
-  const int kmax = p.max_rank > 0 ? p.max_rank : 64;
-  h->rank = h->alloc_t<int32_t>(h->nl + 1);
-  h->info = h->alloc_t<int32_t>(h->nl + 1);
-  h->lrptr = h->alloc_t<uint64_t>(h->nl + 1);
-  int64_t nchunks = 0;
-  h->lr_elems = 0;
-  if (h->nl > 0) {
-    int64_t* slot = dalloc_t<int64_t>(h->nl, s);
-    int64_t* slot_off = dalloc_t<int64_t>(h->nl + 1, s);
-    int64_t* isbig = dalloc_t<int64_t>(h->nl, s);
-    launch_aca_slots<T>(h->lr, h->nl, h->cl, kmax, slot, isbig, s);
-    scan_excl_i64(slot, slot_off, h->nl, slot_off + h->nl, s);
-    std::vector<int64_t> hoff(h->nl + 1);
-    HM_HIP(hipMemcpyAsync(hoff.data(), slot_off, (h->nl + 1) * sizeof(int64_t),
-                          hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
-    dfree(slot, s);
     size_t freeb = 0, totb = 0;
     HM_HIP(hipMemGetInfo(&freeb, &totb));
     int64_t budget = (int64_t)(0.40 * (double)freeb);
-    if (p.mem_limit_bytes > 0) budget = std::min(budget, (p.mem_limit_bytes - h->bytes) / 2);
-    int64_t pool_elems = std::min<int64_t>(hoff[h->nl], std::max<int64_t>(budget / (int64_t)sizeof(T), 1));
-    // a single block must always fit
-    int64_t maxslot = 0;
-    for (int64_t b = 0; b < h->nl; ++b) maxslot = std::max(maxslot, hoff[b + 1] - hoff[b]);
-    pool_elems = std::max(pool_elems, maxslot);
-    if (p.mem_limit_bytes > 0 && h->bytes + pool_elems * (int64_t)sizeof(T) > p.mem_limit_bytes)
-      throw Error{HM_ERR_OOM, "mem_limit_bytes too small for the ACA workspace"};
-    T* pool = (T*)dalloc(pool_elems * sizeof(T), s);
-    int64_t* ob = dalloc_t<int64_t>(h->nl + 1, s);
-    int32_t* big = dalloc_t<int32_t>(h->nl, s);
-    int32_t* small = dalloc_t<int32_t>(h->nl, s);
-    int64_t* psz = dalloc_t<int64_t>(h->nl + 1, s);
-    int64_t* fo = dalloc_t<int64_t>(h->nl + 1, s);
-    int64_t b0 = 0;
-    while (b0 < h->nl) {
-      int64_t b1 = b0 + 1;
-      while (b1 < h->nl && hoff[b1 + 1] - hoff[b0] <= pool_elems) ++b1;
-      const int64_t nb = b1 - b0;
-      // workgroup / wavefront classes of the chunk's blocks
-      const int64_t nbig = scan_total(isbig + b0, ob, nb, tmp, s);
-      launch_split_lists(isbig + b0, ob, nb, big, small, s);
-      launch_aca<T>(g, h->lr + b0, h->cl, slot_off + b0, hoff[b0], pool, big, nbig, small,
-                    nb - nbig, kmax, p.aca_eps, h->rank + b0, h->info + b0, s);
-      launch_packed_sizes(h->lr + b0, nb, h->rank + b0, h->leaf_lo, h->leaf_m, h->ldpre,
-                          h->cl_leaves, psz, s);
-      const int64_t packed = scan_total(psz, fo, nb, tmp, s);
-      T* arena = (T*)h->alloc(packed * sizeof(T));
-      launch_pack<T>(h->lr + b0, nb, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
-                     h->rank + b0, slot_off + b0, hoff[b0], pool, kmax, fo, arena, h->lrptr + b0, s);
-      h->lr_elems += packed;
-      ++nchunks;
-      b0 = b1;
-    }
-    HM_HIP(hipStreamSynchronize(s));
-    dfree(pool, s);
-    dfree(ob, s);
-    dfree(big, s);
-    dfree(small, s);
-    dfree(psz, s);
-    dfree(fo, s);
-    dfree(slot_off, s);
-    dfree(isbig, s);
+    if (p.mem_limit_bytes > 0) budget = std::min(budget, (p.mem_limit_bytes - h->bytes) / 3);
+    SetupIn in{n, h->cl, h->cl_leaves, h->leaf_lo, h->leaf_m, h->ldpre, h->nleaf,
+               h->dns, h->nd, h->lr, h->nl, p.max_rank > 0 ? p.max_rank : 64, p.aca_eps,
+               std::max<int64_t>(budget, 1 << 20)};
+    build_storage<T>(g, in, h->sto, [h](size_t b) { return h->alloc(b); }, s);
+    h->ms[4] = h->sto.ms_near;
+    h->ms[5] = h->sto.ms_aca;
+    h->ms[6] = h->sto.ms_pack;
   }
-  h->ms[5] = ms_since(t0);
-
-  // ---- product metadata and per-leaf item lists
   t0 = clk::now();
-  int64_t toff_total = 0, pslot_total = 0;
-  int64_t* toff = dalloc_t<int64_t>(h->nl + 1, s);
-  int64_t* pslot = dalloc_t<int64_t>(h->nl + 1, s);
-  h->lr_meta = h->alloc_t<int64_t>(6 * (h->nl + 1));
-  if (h->nl > 0) {
-    int64_t* rk = dalloc_t<int64_t>(h->nl, s);
-    int64_t* psz = dalloc_t<int64_t>(h->nl, s);
-    launch_lr_meta(h->lr, h->nl, h->rank, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves, rk, psz, s);
-    toff_total = scan_total(rk, toff, h->nl, tmp, s);
-    pslot_total = scan_total(psz, pslot, h->nl, tmp, s);
-    k_lr_meta_fill<<<grid_for(h->nl, 256), 256, 0, s>>>(h->lr, h->nl, h->cl_leaves, h->rank, toff,
-                                                        pslot, h->lr_meta);
-    HM_LAUNCH_CHECK();
-    dfree(rk, s);
-    dfree(psz, s);
+  // ---- product workspace: z = [x ; t] with 16 columns, w for the
+  // transposed product sized to at most 2 GB (fewer columns per pass)
+  h->z = h->alloc((size_t)(n + h->sto.toff_total + 1) * kMaxNr * sizeof(double));
+  {
+    const int64_t cols = h->sto.ncols + 1;
+    int nrt = kMaxNr;
+    while (nrt > 1 && (double)cols * nrt * sizeof(double) > 2.0e9) nrt >>= 1;
+    h->max_nr_t = nrt;
+    h->w = h->alloc((size_t)cols * nrt * sizeof(double));
   }
-  const int64_t nb_all = h->nd + h->nl;
-  int64_t* crow = dalloc_t<int64_t>(nb_all, s);
-  int64_t* ccol = dalloc_t<int64_t>(nb_all, s);
-  int64_t* orow = dalloc_t<int64_t>(nb_all, s);
-  int64_t* ocol = dalloc_t<int64_t>(nb_all, s);
-  launch_item_counts(h->dns, h->nd, h->lr, h->nl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
-                     crow, ccol, s);
-  h->nrow_items = scan_total(crow, orow, nb_all, tmp, s);
-  h->ncol_items = scan_total(ccol, ocol, nb_all, tmp, s);
-  if (h->nrow_items >= INT32_MAX || h->ncol_items >= INT32_MAX)
-    throw Error{HM_ERR_STATE, "item lists exceed 2^31 entries"};
-  Item* irow = dalloc_t<Item>(h->nrow_items, s);
-  Item* icol = dalloc_t<Item>(h->ncol_items, s);
-  uint64_t* krow = dalloc_t<uint64_t>(h->nrow_items, s);
-  uint64_t* kcol = dalloc_t<uint64_t>(h->ncol_items, s);
-  launch_item_expand<T>(h->dns, h->nd, h->lr, h->nl, h->cl, h->leaf_lo, h->leaf_m, h->ldpre,
-                        h->cl_leaves, h->doff, (const T*)h->D, h->lrptr, h->rank, toff, pslot, orow,
-                        ocol, irow, krow, icol, kcol, s);
-  dfree(crow, s);
-  dfree(ccol, s);
-  dfree(orow, s);
-  dfree(ocol, s);
-  dfree(toff, s);
-  dfree(pslot, s);
-  int leaf_bits = 1;
-  while ((1ll << leaf_bits) < h->nleaf) ++leaf_bits;
-  auto finish = [&](Item* items, uint64_t* keys, int64_t cnt, Item** out_items, int32_t** out_beg) {
-    int32_t* idx = dalloc_t<int32_t>(cnt, s);
-    launch_iota(idx, cnt, s);
-    radix_sort_u64_i32(keys, idx, cnt, leaf_bits, s);
-    *out_items = h->alloc_t<Item>(cnt);
-    launch_gather_items(items, idx, cnt, *out_items, s);
-    int64_t* lc = dalloc_t<int64_t>(h->nleaf + 1, s);
-    int64_t* lb = dalloc_t<int64_t>(h->nleaf + 1, s);
-    HM_HIP(hipMemsetAsync(lc, 0, (h->nleaf + 1) * sizeof(int64_t), s));
-    launch_leaf_counts(keys, cnt, lc, s);
-    scan_excl_i64(lc, lb, h->nleaf + 1, nullptr, s);
-    *out_beg = h->alloc_t<int32_t>(h->nleaf + 1);
-    k_to_i32<<<grid_for(h->nleaf + 1, 256), 256, 0, s>>>(lb, h->nleaf + 1, *out_beg);
-    HM_LAUNCH_CHECK();
-    dfree(idx, s);
-    dfree(lc, s);
-    dfree(lb, s);
-  };
-  finish(irow, krow, h->nrow_items, &h->row_items, &h->row_beg);
-  finish(icol, kcol, h->ncol_items, &h->col_items, &h->col_beg);
-  dfree(irow, s);
-  dfree(icol, s);
-  dfree(krow, s);
-  dfree(kcol, s);
-
-  // ---- product workspace (up to kMaxNr right-hand sides per pass)
-  h->xp = h->alloc((size_t)n * kMaxNr * sizeof(double));
-  h->partial = h->alloc((size_t)(pslot_total + 1) * kMaxNr * sizeof(double));
-  h->t = h->alloc((size_t)(toff_total + 1) * kMaxNr * sizeof(double));
   int dev = 0, ncu = 0;
   HM_HIP(hipGetDevice(&dev));
   HM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   h->grid = std::max(ncu, 1) * 32;
   HM_HIP(hipStreamSynchronize(s));
-  h->ms[6] = ms_since(t0);
+  h->ms[6] += ms_since(t0);
   dfree(tmp, s);
 
   // ---- statistics
@@ -527,8 +319,8 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   std::vector<int2> lrh(h->nl), dnh(h->nd);
   std::vector<Cluster> clh(h->ncl);
   if (h->nl) {
-    HM_HIP(hipMemcpy(rk.data(), h->rank, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HM_HIP(hipMemcpy(inf.data(), h->info, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HM_HIP(hipMemcpy(rk.data(), h->sto.rank, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HM_HIP(hipMemcpy(inf.data(), h->sto.info, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
     HM_HIP(hipMemcpy(lrh.data(), h->lr, h->nl * sizeof(int2), hipMemcpyDeviceToHost));
   }
   if (h->nd) HM_HIP(hipMemcpy(dnh.data(), h->dns, h->nd * sizeof(int2), hipMemcpyDeviceToHost));
@@ -556,12 +348,12 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     const int64_t rows = inf[b] >> 1;
     st.aca_entry_evals += rows * nn + (int64_t)rk[b] * m;
   }
-  st.stored_bytes = (h->D_elems + h->lr_elems) * (int64_t)sizeof(T);
-  st.n_items_row = h->nrow_items;
-  st.n_items_col = h->ncol_items;
+  st.stored_bytes = (h->sto.D_elems + h->sto.lr_elems) * (int64_t)sizeof(T);
+  st.n_panel_cols = h->sto.ncols;
+  st.n_titems = h->sto.ntitems;
   st.device_bytes = h->bytes;
   st.precision = h->f32;
-  st.aca_chunks = nchunks;
+  st.aca_chunks = h->sto.nchunks;
   h->ms[7] = ms_since(t_start);
   if ((p.flags & HM_STRICT) && st.cap_hits > 0)
     throw Error{HM_ERR_ACA, std::to_string(st.cap_hits) + " blocks reached max_rank"};
@@ -929,15 +721,13 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
         if (!check(cnt * 48)) return arg_error("hm_query: destination too small");
         std::vector<int2> bl(cnt);
         std::vector<Cluster> clh(h->ncl);
-        std::vector<int64_t> off(dense ? cnt : 0);
         std::vector<int32_t> rk(dense ? 0 : cnt), inf(dense ? 0 : cnt);
         if (cnt)
           HM_HIP(hipMemcpy(bl.data(), dense ? h->dns : h->lr, cnt * 8, hipMemcpyDeviceToHost));
         HM_HIP(hipMemcpy(clh.data(), h->cl, h->ncl * 16, hipMemcpyDeviceToHost));
-        if (dense && cnt) HM_HIP(hipMemcpy(off.data(), h->doff, cnt * 8, hipMemcpyDeviceToHost));
         if (!dense && cnt) {
-          HM_HIP(hipMemcpy(rk.data(), h->rank, cnt * 4, hipMemcpyDeviceToHost));
-          HM_HIP(hipMemcpy(inf.data(), h->info, cnt * 4, hipMemcpyDeviceToHost));
+          HM_HIP(hipMemcpy(rk.data(), h->sto.rank, cnt * 4, hipMemcpyDeviceToHost));
+          HM_HIP(hipMemcpy(inf.data(), h->sto.info, cnt * 4, hipMemcpyDeviceToHost));
         }
         int64_t* o = (int64_t*)dst;
         for (int64_t b = 0; b < cnt; ++b) {
@@ -946,7 +736,7 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
           o[6 * b + 1] = t.y;
           o[6 * b + 2] = sg.x;
           o[6 * b + 3] = sg.y;
-          o[6 * b + 4] = dense ? off[b] : rk[b];
+          o[6 * b + 4] = dense ? 0 : rk[b];
           o[6 * b + 5] = dense ? 0 : (inf[b] & 1);
         }
         return HM_OK;
@@ -961,7 +751,7 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
         HM_HIP(hipMemcpy(&t, h->cl + ts.x, 16, hipMemcpyDeviceToHost));
         HM_HIP(hipMemcpy(&sg, h->cl + ts.y, 16, hipMemcpyDeviceToHost));
         int32_t r = 0;
-        HM_HIP(hipMemcpy(&r, h->rank + b, 4, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(&r, h->sto.rank + b, 4, hipMemcpyDeviceToHost));
         const int64_t total = (int64_t)r * ((t.y - t.x) + (sg.y - sg.x));
         if (!check(total * (int64_t)h->ts)) return arg_error("hm_query: destination too small");
         if (total == 0) return HM_OK;
@@ -969,10 +759,10 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
         HM_HIP(hipMalloc(&buf, total * h->ts));
         if (h->f32)
           launch_unpack<float>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
-                               h->rank, h->lrptr, (float*)buf, total, 0);
+                               h->sto.meta, h->sto.uptr, (float*)buf, total, 0);
         else
           launch_unpack<double>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
-                                h->rank, h->lrptr, (double*)buf, total, 0);
+                                h->sto.meta, h->sto.uptr, (double*)buf, total, 0);
         HM_HIP(hipMemcpy(dst, buf, total * h->ts, hipMemcpyDeviceToHost));
         HM_HIP(hipFree(buf));
         return HM_OK;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -62,46 +63,109 @@ struct Geom {
 // Cluster record: lo, hi (Morton positions), first child (-1 for a leaf), level.
 using Cluster = int4;
 
-// One slice of a stored block, as seen from one leaf cluster.
-struct Item {
-  uint64_t data;   // device address of the slice (column-major, ld of its row leaf)
-  int32_t w;       // columns of the slice
-  int32_t src;     // first column's index into the input vector (x or t)
-  int32_t aux;     // LR: partial-sum slot; dense transposed: row leaf of the slice
-  int32_t kind;    // 0 dense, 1 low rank
-  int32_t pad0, pad1;
-};
-static_assert(sizeof(Item) == 32, "Item layout");
 
-// Leaf table and per-leaf item lists used by the products.
+
+// Leaf table and the product plan.
 struct MvLeaves {
   const int32_t* lo;
   const int32_t* m;
   const int64_t* ldpre;   // prefix of ld over leaves (nleaf + 1 entries)
   int64_t nleaf;
 };
-// Optional per-kernel timing of the products (HM_PROFILE).
+// One contiguous column-major panel (ld of its row leaf x w) of a row leaf;
+// its column j multiplies z[colmap[col0 + j]].
+struct Run {
+  uint64_t data;
+  int64_t col0;
+  int32_t w;
+  int32_t pad;
+};
+// Per admissible block: V factor address, rank, offset of its terms in t,
+// first/last leaf of its column (sf, sl) and row (tf, tl) cluster, and the
+// first entry of its U slices in the per-(block, row leaf) records.
+struct LrMeta {
+  uint64_t vptr;
+  int32_t r, toff, sf, sl, tf, tl;
+  int64_t ub;
+};
+// Column-leaf item of the transposed product: kind 0 = columns of a dense
+// slice (partial dots at w[src ..]), kind 1 = V slice at `data` (w = rank,
+// src = toff of its block).
+struct TItem {
+  uint64_t data;
+  int64_t src;
+  int32_t w;
+  int32_t kind;
+};
+// Optional per-kernel timing of the products (HM_PROFILE): four stages of
+// the forward and four of the transposed product.
 struct MvProfile {
   hipEvent_t ev[5];
-  double ms[4];
-  double launches[4];
+  double ms[8];
+  double launches[8];
 };
 struct MvPlan {
-  const int32_t* row_beg;   // leaf -> first row item (nleaf + 1)
-  const Item* row_items;    // dense row slices and U slices
-  const int32_t* col_beg;
-  const Item* col_items;    // V slices and dense blocks seen from a column leaf
-  MvLeaves L;
-  const int64_t* lr_meta;   // per low-rank block: toff, pslot, r, nk_rows, nk_cols, 0
+  const Run* runs;          // [nruns][nleaf]
+  int nruns;
+  const int32_t* colmap;
+  const LrMeta* meta;
   int64_t nlr;
+  const int64_t* ucol;
+  const int32_t* tbeg;      // column leaf -> first transposed item (nleaf + 1)
+  const TItem* titems;
+  MvLeaves L;
   const int32_t* perm;
   int64_t n;
-  void* xp;                 // workspace: gathered x
-  void* partial;            // workspace: per-slice partial products
-  void* t;                  // workspace: V^T x (or U^T x) per block
+  void* z;                  // workspace: [x in Morton order ; t], 16 columns
+  void* w;                  // workspace: panel-column partial dots
+  int max_nr_t;             // right-hand sides per transposed pass (w size)
   int grid;
   MvProfile* prof;          // null unless profiling
 };
+
+// Inputs and outputs of the storage build (near field, ACA, panels).
+struct SetupIn {
+  int64_t n;
+  const Cluster* cl;
+  const int2* cl_leaves;
+  const int32_t* leaf_lo;
+  const int32_t* leaf_m;
+  const int64_t* ldpre;
+  int64_t nleaf;
+  const int2* dns;
+  int64_t nd;
+  const int2* lr;
+  int64_t nl;
+  int kmax;
+  double eps;
+  int64_t pool_budget_bytes;   // upper bound for the ACA working pool
+};
+struct Storage {
+  int64_t D_elems = 0, dense_cols = 0;
+  int32_t* rank = nullptr;
+  int32_t* info = nullptr;
+  LrMeta* meta = nullptr;
+  int64_t* ucol = nullptr;
+  uint64_t* uptr = nullptr;
+  int64_t lr_elems = 0, toff_total = 0, nchunks = 0, u_items = 0;
+  Run* runs = nullptr;
+  int nruns = 0;
+  int32_t* colmap = nullptr;
+  int64_t ncols = 0;
+  TItem* titems = nullptr;
+  int32_t* tbeg = nullptr;
+  int64_t ntitems = 0;
+  double ms_near = 0, ms_aca = 0, ms_pack = 0;
+};
+using Alloc = std::function<void*(size_t)>;
+template <typename T>
+void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Alloc& alloc,
+                   hipStream_t s);
+template <typename T>
+void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
+                   const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
+                   const LrMeta* meta, const uint64_t* uptr, T* out, int64_t total, hipStream_t s);
+
 void matvec_dispatch(const MvPlan& P, int storage_f32, const void* x, void* y, int nrhs,
                      int vec_f32, bool transposed, hipStream_t s);
 

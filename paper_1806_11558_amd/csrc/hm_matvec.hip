@@ -1,76 +1,242 @@
 // H-matrix-vector products y = H x and y = H^T x (Sec. 2.3, last paragraph:
 // dense leaves apply their stored block, admissible leaves the low-rank
-// factors), organised per leaf cluster so that every output row is owned by
-// exactly one workgroup: no atomics, fixed summation order, bitwise
-// reproducible.
+// factors), with every output row owned by exactly one workgroup: no atomics,
+// a fixed summation order, bitwise reproducible results.
 //
-//   forward    t_b = V_b^T x_sigma            (per column leaf, then per block)
-//              y_c = sum dense D x + sum U t  (per row leaf)
-//   transposed s_b = U_b^T x_tau              (per row leaf, then per block)
-//              y_c = sum D^T x + sum V s      (per column leaf)
+// Storage (built by the setup):
+//   row panels  for every row leaf c, its dense slices and (per ACA chunk) its
+//               U slices are each one contiguous column-major panel
+//               ld_c x W; column j of a panel multiplies z[colmap[col0 + j]]
+//               where z = [x in Morton order ; t]
+//   V blocks    the V factor of every admissible block is contiguous: its
+//               column-leaf slices (ld x r, column-major) one after another
 //
-// A slice is column-major with ld a multiple of 4.  A wavefront reads it in
-// 16-byte granules: lane = (column group cg, row granule g) with R = ld/G row
-// granules per column and C = 64/R columns per instruction.
+//   forward     z[0..n)      = x[perm]                          (gather)
+//               z[n + toff_b + l] = sum_i V_b[i][l] x_sigma[i] (one wavefront
+//                                                               per block)
+//               y_c = sum over the row panels of c of  P z[map]  (per leaf)
+//   transposed  w[col] = sum_i P[i][col] x_c[i] for every panel column
+//               (per row leaf), s_b[l] = sum over the row leaves of b of the
+//               w of its U columns (per block), then per column leaf
+//               y_c = sum over dense blocks of the w entries of its columns
+//                   + sum over its V slices of V s_b
+//
+// A wavefront reads a slice in 16-byte granules: lane = (column group cg,
+// row granule g), R = ld/G row granules per column, C = 64/R columns per
+// instruction.
 #include "hm_internal.h"
 
 namespace hm {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// 16-byte granule loads; the stored operator is streamed once per product,
+// so the loads are non-temporal.
 template <typename T>
 struct Gran;
 template <>
 struct Gran<float> {
-  using V = float4;
   static constexpr int G = 4;
   __device__ static inline void load(const float* p, float* o) {
-    float4 v = *reinterpret_cast<const float4*>(p);
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
 };
 template <>
 struct Gran<double> {
-  using V = double2;
   static constexpr int G = 2;
   __device__ static inline void load(const double* p, double* o) {
-    double2 v = *reinterpret_cast<const double2*>(p);
+    const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
     o[0] = v.x; o[1] = v.y;
   }
 };
 
-
-
-// Sum of v over the R lanes g = 0..R-1 of a lane segment; the result is
-// valid in the lane with g == 0.  Every lane of the wavefront must call it.
+// Sum of v over the R lanes g = 0..R-1 of a lane segment; valid in the lane
+// with g == 0.  Every lane of the wavefront must call it.
 template <typename A>
 __device__ inline A seg_sum(A v, int g, int R) {
   for (int s = 1; s < R; s <<= 1) {
-    A o = __shfl_down(v, s, 64);
+    const A o = __shfl_down(v, s, 64);
     if (g + s < R) v += o;
   }
   return v;
 }
 
-// ------------------------------------------------------------------ gather / scatter
-// xp[p][k] = x[perm[p]][k0 + k] for one block of NR right-hand sides.
+// ------------------------------------------------------------------ gather
 template <typename VT, typename A>
 __global__ void k_gather(const VT* __restrict__ x, int nrhs, int k0, int nr,
-                         const int32_t* __restrict__ perm, int64_t n, A* __restrict__ xp) {
+                         const int32_t* __restrict__ perm, int64_t n, A* __restrict__ z) {
   const int64_t tot = n * nr;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = e / nr;
     const int k = (int)(e % nr);
-    xp[e] = (A)x[(int64_t)perm[p] * nrhs + k0 + k];
+    z[e] = (A)x[(int64_t)perm[p] * nrhs + k0 + k];
   }
 }
 
-// ------------------------------------------------------------------ phase 1
-// For every leaf: partial[(aux + j)][k] = sum_i S[j*ld + i] x_leaf[i][k] over
-// the low-rank slices (kind 1) of its list.
+// ------------------------------------------------------------------ forward, phase 1
+// One wavefront per admissible block: t_b = V_b^T x_sigma, written to
+// z[n + toff + l].  Column l of every slice is summed over its row granules
+// (segmented shuffle) and moved to lane l, which accumulates over slices.
 template <typename T, typename A, int NR>
-__global__ __launch_bounds__(256) void k_mv_phase1(const int32_t* __restrict__ beg,
-                                                   const Item* __restrict__ items, MvLeaves L,
-                                                   const A* __restrict__ xp, A* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_fwd1(const LrMeta* __restrict__ meta, int64_t nl,
+                                              MvLeaves L, A* __restrict__ z, int64_t n) {
+  constexpr int G = Gran<T>::G;
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t b = wid; b < nl; b += nw) {
+    const LrMeta M = meta[b];
+    const int r = M.r;
+    if (r == 0) continue;
+    A tl[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) tl[k] = 0;
+    const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
+    for (int lf = M.sf; lf <= M.sl; ++lf) {
+      const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+      const int R = ld / G, C = 64 / R;
+      const int cg = lane / R, g = lane % R;
+      const bool act = cg < C;
+      const int m = L.m[lf], lo = L.lo[lf];
+      A xg[G][NR];
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const int row = g * G + e;
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+          xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
+      }
+      for (int j0 = 0; j0 < r; j0 += C) {
+        const int j = j0 + cg;
+        A p[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) p[k] = 0;
+        if (act && j < r) {
+          T s[G];
+          Gran<T>::load(S + (int64_t)j * ld + g * G, s);
+#pragma unroll
+          for (int e = 0; e < G; ++e)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) p[k] += (A)s[e] * xg[e][k];
+        }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
+        const int q = lane - j0;
+        const bool mine = q >= 0 && q < C && lane < r;
+        const int src = mine ? q * R : 0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+          const A v = __shfl(p[k], src, 64);
+          if (mine) tl[k] += v;
+        }
+      }
+      S += (int64_t)ld * r;
+    }
+    if (lane < r) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = tl[k];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ forward, phase 2
+// Per row leaf: y_c = sum over its panels of P z[colmap], then scattered to
+// application order.
+template <typename T, typename A, typename VT, int NR>
+__global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int nruns, MvLeaves L,
+                                              const int32_t* __restrict__ colmap,
+                                              const A* __restrict__ z,
+                                              const int32_t* __restrict__ perm, VT* __restrict__ y,
+                                              int nrhs, int k0) {
+  constexpr int G = Gran<T>::G;
+  constexpr int UNR = 4;
+  __shared__ A ybuf[4][kMaxLeaf][NR];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+    const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
+    const int R = ld / G, C = 64 / R;
+    const int cg = lane / R, g = lane % R;
+    const bool act = cg < C;
+    const int m = L.m[c], lo = L.lo[c];
+    A acc[G][NR];
+#pragma unroll
+    for (int e = 0; e < G; ++e)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) acc[e][k] = 0;
+    for (int kr = 0; kr < nruns; ++kr) {
+      const Run rn = runs[(int64_t)kr * L.nleaf + c];
+      if (rn.w == 0) continue;
+      const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
+      const int32_t* map = colmap + rn.col0;
+      const int ngrp = (rn.w + C - 1) / C;
+      for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
+        T s[UNR][G];
+        int32_t zi[UNR];
+        bool ok[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int q = q0 + 4 * u;
+          const int j = q * C + cg;
+          ok[u] = act && q < ngrp && j < rn.w;
+          zi[u] = 0;
+          if (ok[u]) {
+            Gran<T>::load(S + (int64_t)j * ld, s[u]);
+            zi[u] = map[j];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (ok[u]) {
+            A zz[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) zz[k] = z[(int64_t)zi[u] * NR + k];
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+#pragma unroll
+              for (int k = 0; k < NR; ++k) acc[e][k] += (A)s[u][e] * zz[k];
+          }
+        }
+      }
+    }
+    // combine the column groups (tree over cg, stride R), then the waves
+#pragma unroll
+    for (int e = 0; e < G; ++e)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        A v = acc[e][k];
+        for (int s = 1; s < C; s <<= 1) {
+          const A o = __shfl_down(v, s * R, 64);
+          if (cg + s < C) v += o;
+        }
+        acc[e][k] = v;
+      }
+    if (cg == 0) {
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const int row = g * G + e;
+        if (row < kMaxLeaf)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) ybuf[wave][row][k] = acc[e][k];
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
+      const int row = e / NR, k = e % NR;
+      const A v = ((ybuf[0][row][k] + ybuf[1][row][k]) + ybuf[2][row][k]) + ybuf[3][row][k];
+      y[(int64_t)perm[lo + row] * nrhs + k0 + k] = (VT)v;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ transposed, phase 1
+// Per row leaf: w[col0 + j] = sum_i P[i][j] x_c[i] for every panel column.
+template <typename T, typename A, int NR>
+__global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, int nruns, MvLeaves L,
+                                             const A* __restrict__ z, A* __restrict__ w) {
   constexpr int G = Gran<T>::G;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
@@ -85,21 +251,21 @@ __global__ __launch_bounds__(256) void k_mv_phase1(const int32_t* __restrict__ b
       const int row = g * G + e;
 #pragma unroll
       for (int k = 0; k < NR; ++k)
-        xg[e][k] = (act && row < m) ? xp[(int64_t)(lo + row) * NR + k] : (A)0;
+        xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
     }
-    const int b0 = beg[c], b1 = beg[c + 1];
-    for (int it = b0 + wave; it < b1; it += 4) {
-      const Item I = items[it];
-      if (I.kind != 1) continue;
-      const T* S = reinterpret_cast<const T*>((uintptr_t)I.data);
-      for (int j0 = 0; j0 < I.w; j0 += C) {
-        const int j = j0 + cg;
+    for (int kr = 0; kr < nruns; ++kr) {
+      const Run rn = runs[(int64_t)kr * L.nleaf + c];
+      if (rn.w == 0) continue;
+      const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
+      const int ngrp = (rn.w + C - 1) / C;
+      for (int q = wave; q < ngrp; q += 4) {
+        const int j = q * C + cg;
         A p[NR];
 #pragma unroll
         for (int k = 0; k < NR; ++k) p[k] = 0;
-        if (act && j < I.w) {
+        if (act && j < rn.w) {
           T s[G];
-          Gran<T>::load(S + (int64_t)j * ld + g * G, s);
+          Gran<T>::load(S + (int64_t)j * ld, s);
 #pragma unroll
           for (int e = 0; e < G; ++e)
 #pragma unroll
@@ -107,50 +273,51 @@ __global__ __launch_bounds__(256) void k_mv_phase1(const int32_t* __restrict__ b
         }
 #pragma unroll
         for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
-        if (act && g == 0 && j < I.w) {
+        if (act && g == 0 && j < rn.w) {
 #pragma unroll
-          for (int k = 0; k < NR; ++k) partial[(int64_t)(I.aux + j) * NR + k] = p[k];
+          for (int k = 0; k < NR; ++k) w[(rn.col0 + j) * NR + k] = p[k];
         }
       }
     }
   }
 }
 
-// t[(toff + l)][k] = sum_q partial[(pslot + q r + l)][k], q < nk.
-// meta[b] = (toff, pslot, r, nk_rows, nk_cols, -) per low-rank block.
+// s_b[l] = sum over the row leaves of b of w[ucol + l]  ->  z[n + toff + l].
+// One wavefront per block, lane = term l.
 template <typename A, int NR>
-__global__ void k_mv_sum(const int64_t* __restrict__ meta, int64_t nl, int use_rows,
-                         const A* __restrict__ partial, A* __restrict__ t) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nl;
-       b += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t* M = meta + 6 * b;
-    const int64_t toff = M[0], ps = M[1], r = M[2], nk = use_rows ? M[3] : M[4];
-    for (int64_t l = 0; l < r; ++l) {
-      A acc[NR];
+__global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta, int64_t nl,
+                                                 const int64_t* __restrict__ ucol,
+                                                 const A* __restrict__ w, A* __restrict__ z,
+                                                 int64_t n) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t b = wid; b < nl; b += nw) {
+    const LrMeta M = meta[b];
+    if (lane >= M.r) continue;
+    A acc[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = 0;
-      for (int64_t q = 0; q < nk; ++q)
+    for (int k = 0; k < NR; ++k) acc[k] = 0;
+    const int nk = M.tl - M.tf + 1;
+    for (int q = 0; q < nk; ++q) {
+      const int64_t col = ucol[M.ub + q] + lane;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] += partial[(ps + q * r + l) * NR + k];
-#pragma unroll
-      for (int k = 0; k < NR; ++k) t[(toff + l) * NR + k] = acc[k];
+      for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
     }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = acc[k];
   }
 }
 
-// ------------------------------------------------------------------ phase 2
-// For every leaf c, y_c = sum over its list:
-//   kind 1 (and kind 0 when !transposed): y += S z[src ..], z = t (kind 1) or
-//     xp (kind 0)                                         ("N" product)
-//   kind 0 when transposed: y[j] += sum_i S[j*ld_s + i] xp[lo_s + i] with
-//     the slice's own row leaf s = aux                     ("T" product)
-// then y[perm[lo + i]][k0 + k] = result.
+// ------------------------------------------------------------------ transposed, phase 2
+// Per column leaf: dense blocks contribute w entries (kind 0, lane = output
+// row), V slices contribute V s (kind 1, granule product).
 template <typename T, typename A, typename VT, int NR>
-__global__ __launch_bounds__(256) void k_mv_phase2(const int32_t* __restrict__ beg,
-                                                   const Item* __restrict__ items, MvLeaves L,
-                                                   const A* __restrict__ xp, const A* __restrict__ t,
-                                                   int transposed, const int32_t* __restrict__ perm,
-                                                   VT* __restrict__ y, int nrhs, int k0) {
+__global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
+                                             const TItem* __restrict__ items, MvLeaves L,
+                                             const A* __restrict__ w, const A* __restrict__ z,
+                                             int64_t n, const int32_t* __restrict__ perm,
+                                             VT* __restrict__ y, int nrhs, int k0) {
   constexpr int G = Gran<T>::G;
   __shared__ A ybuf[4][kMaxLeaf][NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -160,8 +327,7 @@ __global__ __launch_bounds__(256) void k_mv_phase2(const int32_t* __restrict__ b
     const int cg = lane / R, g = lane % R;
     const bool act = cg < C;
     const int m = L.m[c], lo = L.lo[c];
-    A acc[G][NR];
-    A yT[NR];
+    A acc[G][NR], yT[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       yT[k] = 0;
@@ -170,10 +336,14 @@ __global__ __launch_bounds__(256) void k_mv_phase2(const int32_t* __restrict__ b
     }
     const int b0 = beg[c], b1 = beg[c + 1];
     for (int it = b0 + wave; it < b1; it += 4) {
-      const Item I = items[it];
-      const T* S = reinterpret_cast<const T*>((uintptr_t)I.data);
-      if (I.kind == 1 || !transposed) {
-        const A* z = (I.kind == 1) ? t : xp;
+      const TItem I = items[it];
+      if (I.kind == 0) {
+        if (lane < I.w) {
+#pragma unroll
+          for (int k = 0; k < NR; ++k) yT[k] += w[(I.src + lane) * NR + k];
+        }
+      } else {
+        const T* S = reinterpret_cast<const T*>((uintptr_t)I.data);
         for (int j0 = 0; j0 < I.w; j0 += C) {
           const int j = j0 + cg;
           if (act && j < I.w) {
@@ -181,63 +351,22 @@ __global__ __launch_bounds__(256) void k_mv_phase2(const int32_t* __restrict__ b
             Gran<T>::load(S + (int64_t)j * ld + g * G, s);
             A zz[NR];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) zz[k] = z[(int64_t)(I.src + j) * NR + k];
+            for (int k = 0; k < NR; ++k) zz[k] = z[(n + I.src + j) * NR + k];
 #pragma unroll
             for (int e = 0; e < G; ++e)
 #pragma unroll
               for (int k = 0; k < NR; ++k) acc[e][k] += (A)s[e] * zz[k];
           }
         }
-      } else {
-        // dense block seen from its column leaf: T product with the row leaf's x
-        const int sl = I.aux;
-        const int lds = (int)(L.ldpre[sl + 1] - L.ldpre[sl]);
-        const int Rs = lds / G, Cs = 64 / Rs;
-        const int cgs = lane / Rs, gs = lane % Rs;
-        const bool acts = cgs < Cs;
-        const int ms = L.m[sl], los = L.lo[sl];
-        A xg[G][NR];
-#pragma unroll
-        for (int e = 0; e < G; ++e) {
-          const int row = gs * G + e;
-#pragma unroll
-          for (int k = 0; k < NR; ++k)
-            xg[e][k] = (acts && row < ms) ? xp[(int64_t)(los + row) * NR + k] : (A)0;
-        }
-        for (int j0 = 0; j0 < I.w; j0 += Cs) {
-          const int j = j0 + cgs;
-          A p[NR];
-#pragma unroll
-          for (int k = 0; k < NR; ++k) p[k] = 0;
-          if (acts && j < I.w) {
-            T s[G];
-            Gran<T>::load(S + (int64_t)j * lds + gs * G, s);
-#pragma unroll
-            for (int e = 0; e < G; ++e)
-#pragma unroll
-              for (int k = 0; k < NR; ++k) p[k] += (A)s[e] * xg[e][k];
-          }
-#pragma unroll
-          for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], gs, Rs);
-          // column j0 + q lives in lane q*Rs; move it to lane (output row) j0 + q
-          const int q = lane - j0;
-          const int src = (q >= 0 && q < Cs) ? q * Rs : 0;
-#pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const A v = __shfl(p[k], src, 64);
-            if (q >= 0 && q < Cs && q < I.w - j0) yT[k] += v;
-          }
-        }
       }
     }
-    // combine the column groups of the N products (tree over cg, stride R)
 #pragma unroll
     for (int e = 0; e < G; ++e)
 #pragma unroll
       for (int k = 0; k < NR; ++k) {
         A v = acc[e][k];
         for (int s = 1; s < C; s <<= 1) {
-          A o = __shfl_down(v, s * R, 64);
+          const A o = __shfl_down(v, s * R, 64);
           if (cg + s < C) v += o;
         }
         acc[e][k] = v;
@@ -267,65 +396,71 @@ __global__ __launch_bounds__(256) void k_mv_phase2(const int32_t* __restrict__ b
 }
 
 // ------------------------------------------------------------------ host side
-
-
 template <typename T, typename A, typename VT, int NR>
 static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool transposed,
                      hipStream_t s) {
-  A* xp = static_cast<A*>(P.xp);
-  A* partial = static_cast<A*>(P.partial);
-  A* t = static_cast<A*>(P.t);
+  A* z = static_cast<A*>(P.z);
+  A* w = static_cast<A*>(P.w);
   MvProfile* pr = P.prof;
   if (pr) HM_HIP(hipEventRecord(pr->ev[0], s));
-  k_gather<VT, A><<<grid_for(P.n * NR, 256, 4096), 256, 0, s>>>(x, nrhs, k0, NR, P.perm, P.n, xp);
+  k_gather<VT, A><<<grid_for(P.n * NR, 256, 4096), 256, 0, s>>>(x, nrhs, k0, NR, P.perm, P.n, z);
   HM_LAUNCH_CHECK();
   if (pr) HM_HIP(hipEventRecord(pr->ev[1], s));
-  const int32_t* b1 = transposed ? P.row_beg : P.col_beg;
-  const Item* i1 = transposed ? P.row_items : P.col_items;
-  const int32_t* b2 = transposed ? P.col_beg : P.row_beg;
-  const Item* i2 = transposed ? P.col_items : P.row_items;
-  const unsigned g = (unsigned)std::min<int64_t>(P.L.nleaf, P.grid);
-  if (P.nlr > 0) {
-    k_mv_phase1<T, A, NR><<<g, 256, 0, s>>>(b1, i1, P.L, xp, partial);
+  const unsigned gl = (unsigned)std::min<int64_t>(P.L.nleaf, P.grid);
+  const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
+  if (!transposed) {
+    if (P.nlr > 0) {
+      k_fwd1<T, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n);
+      HM_LAUNCH_CHECK();
+    }
+    if (pr) {
+      HM_HIP(hipEventRecord(pr->ev[2], s));
+      HM_HIP(hipEventRecord(pr->ev[3], s));
+    }
+    k_fwd2<T, A, VT, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, P.colmap, z, P.perm, y, nrhs,
+                                             k0);
+    HM_LAUNCH_CHECK();
+  } else {
+    k_tr1<T, A, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, z, w);
+    HM_LAUNCH_CHECK();
+    if (pr) HM_HIP(hipEventRecord(pr->ev[2], s));
+    if (P.nlr > 0) {
+      k_tr_sums<A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.ucol, w, z, P.n);
+      HM_LAUNCH_CHECK();
+    }
+    if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
+    k_tr2<T, A, VT, NR><<<gl, 256, 0, s>>>(P.tbeg, P.titems, P.L, w, z, P.n, P.perm, y, nrhs, k0);
     HM_LAUNCH_CHECK();
   }
-  if (pr) HM_HIP(hipEventRecord(pr->ev[2], s));
-  if (P.nlr > 0) {
-    k_mv_sum<A, NR><<<grid_for(P.nlr, 256), 256, 0, s>>>(P.lr_meta, P.nlr, transposed ? 1 : 0,
-                                                          partial, t);
-    HM_LAUNCH_CHECK();
-  }
-  if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
-  k_mv_phase2<T, A, VT, NR><<<g, 256, 0, s>>>(b2, i2, P.L, xp, t, transposed ? 1 : 0, P.perm, y,
-                                               nrhs, k0);
-  HM_LAUNCH_CHECK();
   if (pr) {
     HM_HIP(hipEventRecord(pr->ev[4], s));
     HM_HIP(hipEventSynchronize(pr->ev[4]));
+    const int base = transposed ? 4 : 0;
     for (int k = 0; k < 4; ++k) {
       float ms = 0.f;
       HM_HIP(hipEventElapsedTime(&ms, pr->ev[k], pr->ev[k + 1]));
-      pr->ms[k] += ms;
-      pr->launches[k] += 1;
+      pr->ms[base + k] += ms;
+      pr->launches[base + k] += 1;
     }
   }
 }
 
 template <typename T, typename A, typename VT>
 void matvec_impl(const MvPlan& P, const VT* x, VT* y, int nrhs, bool transposed, hipStream_t s) {
+  const int cap = transposed ? P.max_nr_t : 16;
   int k0 = 0;
   while (k0 < nrhs) {
     const int left = nrhs - k0;
-    if (left >= 16) {
+    if (left >= 16 && cap >= 16) {
       mv_chunk<T, A, VT, 16>(P, x, y, nrhs, k0, transposed, s);
       k0 += 16;
-    } else if (left >= 8) {
+    } else if (left >= 8 && cap >= 8) {
       mv_chunk<T, A, VT, 8>(P, x, y, nrhs, k0, transposed, s);
       k0 += 8;
-    } else if (left >= 4) {
+    } else if (left >= 4 && cap >= 4) {
       mv_chunk<T, A, VT, 4>(P, x, y, nrhs, k0, transposed, s);
       k0 += 4;
-    } else if (left >= 2) {
+    } else if (left >= 2 && cap >= 2) {
       mv_chunk<T, A, VT, 2>(P, x, y, nrhs, k0, transposed, s);
       k0 += 2;
     } else {

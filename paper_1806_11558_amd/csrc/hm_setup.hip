@@ -11,6 +11,7 @@
 //   A leaf cluster then streams its dense blocks and its U slices in the
 //   product y = H x (Sec. 2.3, last paragraph), and its V slices in the
 //   first phase t = V^T x.
+#include <chrono>
 #include <cmath>
 
 #include "hm_internal.h"
@@ -88,7 +89,8 @@ __global__ void k_inverse_perm(const int32_t* __restrict__ perm, int64_t n,
 
 // ------------------------------------------------------------------ near field
 // Dense leaves of Algorithm 1, assembled in one batch (Sec. 3.3): one
-// workgroup per block, entries written straight into the block's row slices.
+// workgroup per (dense block, row leaf) slice, written straight into the row
+// leaf's panel (ld x n, column-major, zero padding rows).
 struct LeafTab {
   const int32_t* lo;     // first position of leaf
   const int32_t* m;      // size
@@ -101,26 +103,25 @@ __device__ inline int leaf_ld(const LeafTab& L, int lf) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_near(Geom<T> g, const int2* __restrict__ dns, int64_t nd,
+__global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restrict__ sidx,
+                                              const int32_t* __restrict__ ib,
+                                              const int32_t* __restrict__ ilf, int64_t np,
+                                              const int2* __restrict__ dns,
                                               const Cluster* __restrict__ cl, LeafTab L,
-                                              const int64_t* __restrict__ doff, T* __restrict__ D) {
-  for (int64_t b = blockIdx.x; b < nd; b += gridDim.x) {
-    const int2 ts = dns[b];
-    const Cluster tau = cl[ts.x], sig = cl[ts.y];
+                                              const int64_t* __restrict__ offI, T* __restrict__ D) {
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const int32_t u = sidx[p];
+    const int b = ib[u], lf = ilf[u];
+    const Cluster sig = cl[dns[b].y];
     const int n = sig.y - sig.x;
-    const int2 lv = L.cl_leaves[ts.x];
-    const int64_t base0 = doff[b];
-    for (int lf = lv.x; lf <= lv.y; ++lf) {
-      const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
-      T* dst = D + base0 + (int64_t)n * (L.ldpre[lf] - L.ldpre[lv.x]);
-      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
-        const int i = e % ld, j = e / ld;
-        T v = 0;
-        if (i < m) v = entry_at(g, lo + i, sig.x + j);
-        dst[e] = v;
-      }
+    const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
+    T* dst = D + offI[p];
+    for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
+      const int i = e % ld, j = e / ld;
+      T v = 0;
+      if (i < m) v = entry_at(g, lo + i, sig.x + j);
+      dst[e] = v;
     }
-    (void)tau;
   }
 }
 
@@ -505,53 +506,171 @@ __global__ void k_split_lists(const int64_t* __restrict__ is_big, const int64_t*
   }
 }
 
-// ------------------------------------------------------------------ packing
-// Packed size of a factorised block: r * (LD(tau) + LD(sigma)).
-__global__ void k_packed_sizes(const int2* __restrict__ blk, int64_t nb, const int32_t* __restrict__ rank,
-                               LeafTab L, int64_t* __restrict__ sz) {
+// ------------------------------------------------------------------ panels
+// Items are (block, leaf) pairs: the slice of a block that belongs to one leaf
+// of its row cluster (dense slices, U slices) or column cluster.  Sorting the
+// items by leaf (stable, so block order is kept inside a leaf) and scanning
+// their widths gives every row leaf one contiguous panel per item set.
+
+__global__ void k_count_leaves(const int2* __restrict__ blk, int64_t nb,
+                               const int2* __restrict__ cl_leaves, int which,
+                               int64_t* __restrict__ cnt) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
-    const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
-    const int64_t ldt = L.ldpre[lt.y + 1] - L.ldpre[lt.x];
-    const int64_t lds = L.ldpre[ls.y + 1] - L.ldpre[ls.x];
-    sz[b] = (int64_t)rank[b] * (ldt + lds);
+    const int2 lv = cl_leaves[which ? ts.y : ts.x];
+    cnt[b] = lv.y - lv.x + 1;
   }
 }
 
-// Copy the working factors of each block into its leaf slices: U slices of
-// the row leaves, then V slices of the column leaves.
+__global__ void k_expand_leaves(const int2* __restrict__ blk, int64_t nb,
+                                const int2* __restrict__ cl_leaves, int which,
+                                const int64_t* __restrict__ off, uint64_t* __restrict__ key,
+                                int32_t* __restrict__ ib, int32_t* __restrict__ ilf,
+                                int32_t* __restrict__ idx) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = blk[b];
+    const int2 lv = cl_leaves[which ? ts.y : ts.x];
+    int64_t o = off[b];
+    for (int lf = lv.x; lf <= lv.y; ++lf, ++o) {
+      key[o] = (uint64_t)lf;
+      ib[o] = (int32_t)b;
+      ilf[o] = lf;
+      idx[o] = (int32_t)o;
+    }
+  }
+}
+
+// Width of every sorted item: the number of columns of the block (dense) or
+// its rank (U slices).
+__global__ void k_item_width(const int32_t* __restrict__ sidx, const int32_t* __restrict__ ib,
+                             int64_t np, const int2* __restrict__ blk,
+                             const Cluster* __restrict__ cl, const int32_t* __restrict__ rank,
+                             int64_t* __restrict__ wid) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int b = ib[sidx[p]];
+    if (rank) {
+      wid[p] = rank[b];
+    } else {
+      const Cluster s = cl[blk[b].y];
+      wid[p] = s.y - s.x;
+    }
+  }
+}
+
+// Leaf panels: first column col0[c] (in the item set's column space), width
+// W[c] and size ld_c * W[c].  ibeg holds the first sorted item of each leaf.
+__global__ void k_leaf_panels(const int64_t* __restrict__ ibeg, const int64_t* __restrict__ gcol,
+                              int64_t np, int64_t total, const int64_t* __restrict__ ldpre,
+                              int64_t nleaf, int64_t* __restrict__ col0, int64_t* __restrict__ W,
+                              int64_t* __restrict__ psize) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nleaf;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = ibeg[c] < np ? gcol[ibeg[c]] : total;
+    const int64_t e = ibeg[c + 1] < np ? gcol[ibeg[c + 1]] : total;
+    col0[c] = a;
+    W[c] = e - a;
+    psize[c] = (ldpre[c + 1] - ldpre[c]) * (e - a);
+  }
+}
+
+// Element offset of every sorted item inside the panel arena, and the
+// inverse of the sort permutation.
+__global__ void k_item_offsets(const int32_t* __restrict__ sidx, const int32_t* __restrict__ ilf,
+                               int64_t np, const int64_t* __restrict__ gcol,
+                               const int64_t* __restrict__ col0, const int64_t* __restrict__ poff,
+                               const int64_t* __restrict__ ldpre, int64_t* __restrict__ offI,
+                               int32_t* __restrict__ inv) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = sidx[p];
+    const int lf = ilf[u];
+    offI[p] = poff[lf] + (gcol[p] - col0[lf]) * (ldpre[lf + 1] - ldpre[lf]);
+    inv[u] = (int32_t)p;
+  }
+}
+
+// Column maps: a dense column multiplies x at Morton position sigma_lo + j,
+// a U column multiplies t at n + toff_b + l.
+__global__ void k_colmap(const int32_t* __restrict__ sidx, const int32_t* __restrict__ ib,
+                         int64_t np, const int64_t* __restrict__ gcol,
+                         const int64_t* __restrict__ wid, const int2* __restrict__ blk,
+                         const Cluster* __restrict__ cl, const int64_t* __restrict__ toff,
+                         int64_t tbase, int64_t n, int32_t* __restrict__ colmap) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int b = ib[sidx[p]];
+    const int64_t base = toff ? n + tbase + toff[b] : (int64_t)cl[blk[b].y].x;
+    const int64_t w = wid[p];
+    for (int64_t j = 0; j < w; ++j) colmap[gcol[p] + j] = (int32_t)(base + j);
+  }
+}
+
+__global__ void k_runs(const int64_t* __restrict__ col0, const int64_t* __restrict__ W,
+                       const int64_t* __restrict__ poff, int64_t nleaf, uint64_t base, int esize,
+                       int64_t colbase, Run* __restrict__ runs) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nleaf;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    runs[c] = Run{base + (uint64_t)(poff[c] * esize), colbase + col0[c], (int32_t)W[c], 0};
+  }
+}
+
+// ------------------------------------------------------------------ packing
+// U slice of every sorted U item: the rows of leaf lf of block b, ld x r
+// column-major, at its place in the leaf panel.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pack(const int2* __restrict__ blk, int64_t nb,
-                                              const Cluster* __restrict__ cl, LeafTab L,
-                                              const int32_t* __restrict__ rank,
-                                              const int64_t* __restrict__ slot, int64_t slot0,
-                                              const T* __restrict__ pool, int kmax, const int64_t* __restrict__ fo, T* __restrict__ arena,
-                                              uint64_t* __restrict__ ptr_out) {
+__global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx,
+                                                const int32_t* __restrict__ ib,
+                                                const int32_t* __restrict__ ilf, int64_t np,
+                                                const int2* __restrict__ blk,
+                                                const Cluster* __restrict__ cl, LeafTab L,
+                                                const int32_t* __restrict__ rank,
+                                                const int64_t* __restrict__ slot, int64_t slot0,
+                                                const T* __restrict__ pool, int kmax,
+                                                const int64_t* __restrict__ offI,
+                                                T* __restrict__ arena) {
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const int32_t u = sidx[p];
+    const int b = ib[u], lf = ilf[u];
+    const int2 ts = blk[b];
+    const Cluster tau = cl[ts.x], sig = cl[ts.y];
+    const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
+    const int kcap = min(kmax, min(m, n));
+    const T* U = pool + (slot[b] - slot0);
+    const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - tau.x;
+    T* d = arena + offI[p];
+    for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
+      const int i = e % ld, l = e / ld;
+      d[e] = (i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
+    }
+    (void)kcap;
+  }
+}
+
+// V factor of every block, contiguous: its column-leaf slices in leaf order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, int64_t nb,
+                                                const Cluster* __restrict__ cl, LeafTab L,
+                                                const int32_t* __restrict__ rank,
+                                                const int64_t* __restrict__ slot, int64_t slot0,
+                                                const T* __restrict__ pool, int kmax,
+                                                const int64_t* __restrict__ voff,
+                                                T* __restrict__ varena,
+                                                uint64_t* __restrict__ vptr) {
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const int2 ts = blk[b];
     const Cluster tau = cl[ts.x], sig = cl[ts.y];
-    const int m = tau.y - tau.x, n = sig.y - sig.x;
-    const int r = rank[b];
+    const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
     const int kcap = min(kmax, min(m, n));
-    const T* U = pool + (slot[b] - slot0);
-    const T* Vw = U + (int64_t)kcap * m;
-    T* dst = arena + fo[b];
-    if (threadIdx.x == 0) ptr_out[b] = (uint64_t)(uintptr_t)dst;
-    const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
-    const int64_t ldt = L.ldpre[lt.y + 1] - L.ldpre[lt.x];
-    for (int lf = lt.x; lf <= lt.y; ++lf) {
-      const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - tau.x;
-      T* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[lt.x]);
-      for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
-        const int i = e % ld, l = e / ld;
-        d[e] = (i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
-      }
-    }
-    T* dv = dst + (int64_t)r * ldt;
+    const T* Vw = pool + (slot[b] - slot0) + (int64_t)kcap * m;
+    T* dst = varena + voff[b];
+    if (threadIdx.x == 0) vptr[b] = (uint64_t)(uintptr_t)dst;
+    const int2 ls = L.cl_leaves[ts.y];
     for (int lf = ls.x; lf <= ls.y; ++lf) {
       const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - sig.x;
-      T* d = dv + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
+      T* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
       for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
         const int i = e % ld, l = e / ld;
         d[e] = (i < ml) ? Vw[(int64_t)l * n + off + i] : (T)0;
@@ -560,82 +679,105 @@ __global__ __launch_bounds__(256) void k_pack(const int2* __restrict__ blk, int6
   }
 }
 
-// ------------------------------------------------------------------ items
-// Number of slices every block contributes to the row lists and column lists.
-__global__ void k_item_counts(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
-                              int64_t nl, LeafTab L, int64_t* __restrict__ crow,
-                              int64_t* __restrict__ ccol) {
+// V arena size of every block: r * LD(sigma).
+__global__ void k_v_sizes(const int2* __restrict__ blk, int64_t nb, const int32_t* __restrict__ rank,
+                          LeafTab L, int64_t* __restrict__ sz) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ls = L.cl_leaves[blk[b].y];
+    sz[b] = (int64_t)rank[b] * (L.ldpre[ls.y + 1] - L.ldpre[ls.x]);
+  }
+}
+
+// Per U item: its global panel column (for the transposed block sums) and
+// the address of its slice (for unpacking), indexed by (block, row leaf).
+__global__ void k_urec(const int32_t* __restrict__ sidx, const int32_t* __restrict__ ib,
+                       const int32_t* __restrict__ ilf, int64_t np, const int2* __restrict__ blk,
+                       const int2* __restrict__ cl_leaves, const int64_t* __restrict__ ub,
+                       const int64_t* __restrict__ gcol, int64_t colbase,
+                       const int64_t* __restrict__ offI, uint64_t base, int esize,
+                       int64_t* __restrict__ ucol, uint64_t* __restrict__ uptr) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = sidx[p];
+    const int b = ib[u], lf = ilf[u];
+    const int64_t q = ub[b] + (lf - cl_leaves[blk[b].x].x);
+    ucol[q] = colbase + gcol[p];
+    uptr[q] = base + (uint64_t)(offI[p] * esize);
+  }
+}
+
+__global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* __restrict__ cl_leaves,
+                          const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
+                          int64_t toff_base, const uint64_t* __restrict__ vptr,
+                          const int64_t* __restrict__ ub, LrMeta* __restrict__ meta) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = blk[b];
+    const int2 lt = cl_leaves[ts.x], ls = cl_leaves[ts.y];
+    LrMeta M;
+    M.vptr = vptr[b];
+    M.r = rank[b];
+    M.toff = (int32_t)(toff_base + toff[b]);
+    M.sf = ls.x;
+    M.sl = ls.y;
+    M.tf = lt.x;
+    M.tl = lt.y;
+    M.ub = ub[b];
+    meta[b] = M;
+  }
+}
+
+// ------------------------------------------------------------------ transposed items
+// Per column leaf: every dense block whose column cluster contains it gives
+// one item per row leaf (its columns' partial dots in w), every admissible
+// block one V slice.
+__global__ void k_titem_counts(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
+                               int64_t nl, const int2* __restrict__ cl_leaves,
+                               int64_t* __restrict__ cnt) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nd + nl;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = (b < nd) ? dns[b] : lr[b - nd];
-    const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
-    const int64_t nt = lt.y - lt.x + 1, ns = ls.y - ls.x + 1;
-    crow[b] = nt;
-    ccol[b] = (b < nd) ? nt * ns : ns;
+    const int2 lt = cl_leaves[ts.x], ls = cl_leaves[ts.y];
+    cnt[b] = (b < nd) ? (int64_t)(lt.y - lt.x + 1) * (ls.y - ls.x + 1) : (ls.y - ls.x + 1);
   }
 }
 
-template <typename T>
-__global__ void k_item_expand(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
-                              int64_t nl, const Cluster* __restrict__ cl, LeafTab L,
-                              const int64_t* __restrict__ doff, const T* __restrict__ D,
-                              const uint64_t* __restrict__ lrptr, const int32_t* __restrict__ rank,
-                              const int64_t* __restrict__ toff, const int64_t* __restrict__ pslot,
-                              const int64_t* __restrict__ orow, const int64_t* __restrict__ ocol,
-                              Item* __restrict__ irow, uint64_t* __restrict__ krow,
-                              Item* __restrict__ icol, uint64_t* __restrict__ kcol) {
+__global__ void k_titem_expand(const int2* __restrict__ dns, int64_t nd, int64_t nl,
+                               const Cluster* __restrict__ cl, LeafTab L,
+                               const int64_t* __restrict__ off, const int32_t* __restrict__ invD,
+                               const int64_t* __restrict__ oD, const int64_t* __restrict__ gcolD,
+                               const LrMeta* __restrict__ meta, int esize, TItem* __restrict__ out,
+                               uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nd + nl;
        b += (int64_t)gridDim.x * blockDim.x) {
-    const bool dense = b < nd;
-    const int64_t bl = dense ? b : b - nd;
-    const int2 ts = dense ? dns[bl] : lr[bl];
-    const Cluster tau = cl[ts.x], sig = cl[ts.y];
-    const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
-    const int64_t ldt = L.ldpre[lt.y + 1] - L.ldpre[lt.x];
-    int64_t pr = orow[b], pc = ocol[b];
-    if (dense) {
-      const int n = sig.y - sig.x;
-      const T* base = D + doff[bl];
-      for (int lf = lt.x; lf <= lt.y; ++lf, ++pr) {
-        const T* d = base + (int64_t)n * (L.ldpre[lf] - L.ldpre[lt.x]);
-        irow[pr] = Item{(uint64_t)(uintptr_t)d, n, sig.x, -1, 0, 0, 0};
-        krow[pr] = (uint64_t)lf;
-        for (int cf = ls.x; cf <= ls.y; ++cf, ++pc) {
-          const int ld = leaf_ld(L, lf);
-          const T* dt = d + (int64_t)(L.lo[cf] - sig.x) * ld;
-          icol[pc] = Item{(uint64_t)(uintptr_t)dt, L.m[cf], L.lo[lf], lf, 0, 0, 0};
-          kcol[pc] = (uint64_t)cf;
+    int64_t o = off[b];
+    if (b < nd) {
+      const int2 ts = dns[b];
+      const Cluster sig = cl[ts.y];
+      const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
+      for (int lf = lt.x; lf <= lt.y; ++lf) {
+        const int64_t p = invD[oD[b] + (lf - lt.x)];
+        for (int cf = ls.x; cf <= ls.y; ++cf, ++o) {
+          out[o] = TItem{0, gcolD[p] + (L.lo[cf] - sig.x), L.m[cf], 0};
+          key[o] = (uint64_t)cf;
+          idx[o] = (int32_t)o;
         }
       }
     } else {
-      const int r = rank[bl];
-      const T* base = reinterpret_cast<const T*>((uintptr_t)lrptr[bl]);
-      const int to = (int)toff[bl];
-      const int64_t ps = pslot[bl];
-      for (int lf = lt.x; lf <= lt.y; ++lf, ++pr) {
-        const T* d = base + (int64_t)r * (L.ldpre[lf] - L.ldpre[lt.x]);
-        irow[pr] = Item{(uint64_t)(uintptr_t)d, r, to, (int)(ps + (int64_t)(lf - lt.x) * r), 1, 0, 0};
-        krow[pr] = (uint64_t)lf;
-      }
-      const T* bv = base + (int64_t)r * ldt;
-      for (int cf = ls.x; cf <= ls.y; ++cf, ++pc) {
-        const T* d = bv + (int64_t)r * (L.ldpre[cf] - L.ldpre[ls.x]);
-        icol[pc] = Item{(uint64_t)(uintptr_t)d, r, to, (int)(ps + (int64_t)(cf - ls.x) * r), 1, 0, 0};
-        kcol[pc] = (uint64_t)cf;
+      const LrMeta M = meta[b - nd];
+      for (int cf = M.sf; cf <= M.sl; ++cf, ++o) {
+        const uint64_t d = M.vptr + (uint64_t)((int64_t)M.r * (L.ldpre[cf] - L.ldpre[M.sf]) * esize);
+        out[o] = TItem{d, (int64_t)M.toff, M.r, 1};
+        key[o] = (uint64_t)cf;
+        idx[o] = (int32_t)o;
       }
     }
-    (void)tau;
   }
 }
 
-__global__ void k_iota(int32_t* __restrict__ v, int64_t n) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x)
-    v[k] = (int32_t)k;
-}
-
-__global__ void k_gather_items(const Item* __restrict__ in, const int32_t* __restrict__ idx, int64_t n,
-                               Item* __restrict__ out) {
+__global__ void k_gather_titems(const TItem* __restrict__ in, const int32_t* __restrict__ idx,
+                                int64_t n, TItem* __restrict__ out) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x)
     out[k] = in[idx[k]];
@@ -647,42 +789,21 @@ __global__ void k_leaf_counts(const uint64_t* __restrict__ keys, int64_t n, int6
     atomicAdd((unsigned long long*)&cnt[keys[k]], 1ull);
 }
 
-// Per-block values derived from the ranks.
-__global__ void k_lr_meta(const int2* __restrict__ lr, int64_t nl, const int32_t* __restrict__ rank,
-                          LeafTab L, int64_t* __restrict__ rk, int64_t* __restrict__ psz) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nl;
-       b += (int64_t)gridDim.x * blockDim.x) {
-    const int2 ts = lr[b];
-    const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
-    const int64_t nk = max(lt.y - lt.x + 1, ls.y - ls.x + 1);
-    rk[b] = rank[b];
-    psz[b] = (int64_t)rank[b] * nk;
-  }
-}
-
-// Dense block sizes: n * LD(tau).
-__global__ void k_dense_sizes(const int2* __restrict__ dns, int64_t nd, const Cluster* __restrict__ cl,
-                              LeafTab L, int64_t* __restrict__ sz) {
-  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nd;
-       b += (int64_t)gridDim.x * blockDim.x) {
-    const int2 ts = dns[b];
-    const Cluster s = cl[ts.y];
-    const int2 lt = L.cl_leaves[ts.x];
-    sz[b] = (int64_t)(s.y - s.x) * (L.ldpre[lt.y + 1] - L.ldpre[lt.x]);
-  }
+__global__ void k_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (int32_t)a[e];
 }
 
 // Unpack one factorised block back into plain column-major U (m x r), V (n x r).
 template <typename T>
 __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* __restrict__ cl,
-                         LeafTab L, const int32_t* __restrict__ rank,
-                         const uint64_t* __restrict__ lrptr, T* __restrict__ out) {
+                         LeafTab L, const LrMeta* __restrict__ meta,
+                         const uint64_t* __restrict__ uptr, T* __restrict__ out) {
   const int2 ts = lr[b];
   const Cluster tau = cl[ts.x], sig = cl[ts.y];
-  const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
-  const T* base = reinterpret_cast<const T*>((uintptr_t)lrptr[b]);
-  const int2 lt = L.cl_leaves[ts.x], ls = L.cl_leaves[ts.y];
-  const int64_t ldt = L.ldpre[lt.y + 1] - L.ldpre[lt.x];
+  const LrMeta M = meta[b];
+  const int m = tau.y - tau.x, n = sig.y - sig.x, r = M.r;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)(m + n) * r;
        e += (int64_t)gridDim.x * blockDim.x) {
     const bool isu = e < (int64_t)m * r;
@@ -690,57 +811,25 @@ __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* 
     const int rows = isu ? m : n;
     const int i = (int)(ee % rows), l = (int)(ee / rows);
     const int pos = (isu ? tau.x : sig.x) + i;
-    int lf0 = isu ? lt.x : ls.x, lf1 = isu ? lt.y : ls.y;
+    const int lf0 = isu ? M.tf : M.sf, lf1 = isu ? M.tl : M.sl;
     int lf = lf0;
     while (lf < lf1 && L.lo[lf + 1] <= pos) ++lf;
-    const T* sl = (isu ? base : base + (int64_t)r * ldt) + (int64_t)r * (L.ldpre[lf] - L.ldpre[lf0]);
+    const T* sl;
+    if (isu)
+      sl = reinterpret_cast<const T*>((uintptr_t)uptr[M.ub + (lf - lf0)]);
+    else
+      sl = reinterpret_cast<const T*>((uintptr_t)M.vptr) + (int64_t)r * (L.ldpre[lf] - L.ldpre[lf0]);
     out[e] = sl[(int64_t)l * leaf_ld(L, lf) + (pos - L.lo[lf])];
   }
 }
 
-// ------------------------------------------------------------------ launchers
-template <typename T>
-void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
-                    int64_t cnt, double* out, hipStream_t s) {
-  k_entries<T><<<grid_for(cnt, 256), 256, 0, s>>>(g, inv, rows, cols, cnt, out);
-  HM_LAUNCH_CHECK();
-}
-void launch_inverse_perm(const int32_t* perm, int64_t n, int32_t* inv, hipStream_t s) {
-  k_inverse_perm<<<grid_for(n, 256), 256, 0, s>>>(perm, n, inv);
-  HM_LAUNCH_CHECK();
-}
-
-template <typename T>
-void launch_near(const Geom<T>& g, const int2* dns, int64_t nd, const Cluster* cl,
-                 const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
-                 const int2* cl_leaves, const int64_t* doff, T* D, hipStream_t s) {
-  if (nd == 0) return;
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_near<T><<<grid_for(nd, 1, 1 << 20), 256, 0, s>>>(g, dns, nd, cl, L, doff, D);
-  HM_LAUNCH_CHECK();
-}
-
-void launch_dense_sizes(const int2* dns, int64_t nd, const Cluster* cl, const int32_t* leaf_lo,
-                        const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                        int64_t* sz, hipStream_t s) {
-  if (nd == 0) return;
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_dense_sizes<<<grid_for(nd, 256), 256, 0, s>>>(dns, nd, cl, L, sz);
-  HM_LAUNCH_CHECK();
-}
-
-// Batched ACA of the blocks blk[0..nb) followed by packing into `arena`
-// (allocated here, exact size) -- see the host orchestration for chunking.
+// ------------------------------------------------------------------ ACA launchers
 template <typename T>
 void launch_aca_slots(const int2* blk, int64_t nb, const Cluster* cl, int kmax, int64_t* slot,
                       int64_t* is_big, hipStream_t s) {
   k_aca_slots<T><<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, kmax, slot, is_big);
   HM_LAUNCH_CHECK();
 }
-template void launch_aca_slots<float>(const int2*, int64_t, const Cluster*, int, int64_t*, int64_t*,
-                                      hipStream_t);
-template void launch_aca_slots<double>(const int2*, int64_t, const Cluster*, int, int64_t*, int64_t*,
-                                       hipStream_t);
 
 void launch_split_lists(const int64_t* is_big, const int64_t* ob, int64_t nb, int32_t* big,
                         int32_t* small, hipStream_t s) {
@@ -763,102 +852,345 @@ void launch_aca(const Geom<T>& g, const int2* blk, const Cluster* cl, const int6
   HM_LAUNCH_CHECK();
 }
 
-void launch_packed_sizes(const int2* blk, int64_t nb, const int32_t* rank, const int32_t* leaf_lo,
-                         const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                         int64_t* sz, hipStream_t s) {
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_packed_sizes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, rank, L, sz);
+__global__ void k_widen_i32(const int32_t* __restrict__ a, int64_t n, int64_t* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = a[e];
+}
+
+// ------------------------------------------------------------------ host side
+template <typename T>
+void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
+                    int64_t cnt, double* out, hipStream_t s) {
+  k_entries<T><<<grid_for(cnt, 256), 256, 0, s>>>(g, inv, rows, cols, cnt, out);
   HM_LAUNCH_CHECK();
 }
+template void launch_entries<float>(const Geom<float>&, const int32_t*, const int32_t*,
+                                    const int32_t*, int64_t, double*, hipStream_t);
+template void launch_entries<double>(const Geom<double>&, const int32_t*, const int32_t*,
+                                     const int32_t*, int64_t, double*, hipStream_t);
+
+void launch_inverse_perm(const int32_t* perm, int64_t n, int32_t* inv, hipStream_t s) {
+  k_inverse_perm<<<grid_for(n, 256), 256, 0, s>>>(perm, n, inv);
+  HM_LAUNCH_CHECK();
+}
+
+namespace {
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+int64_t scan_total(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s) {
+  scan_excl_i64(in, out, n, tmp, s);
+  return d2h_i64(tmp, s);
+}
+int bits_for(int64_t v) {
+  int b = 1;
+  while ((1ll << b) < v) ++b;
+  return b;
+}
+
+// Temporary device buffers released together.
+struct Temps {
+  hipStream_t s;
+  std::vector<void*> v;
+  template <typename X>
+  X* get(int64_t cnt) {
+    X* p = dalloc_t<X>(cnt > 0 ? cnt : 1, s);
+    v.push_back(p);
+    return p;
+  }
+  void release() {
+    for (void* p : v) dfree(p, s);
+    v.clear();
+  }
+  ~Temps() { release(); }
+};
+
+// A set of (block, leaf) items sorted by leaf, with leaf panels laid out.
+struct PanelSet {
+  int64_t np = 0, cols = 0, elems = 0;
+  int32_t *ib = nullptr, *ilf = nullptr, *sidx = nullptr, *inv = nullptr;
+  int64_t *wid = nullptr, *gcol = nullptr, *col0 = nullptr, *W = nullptr, *poff = nullptr,
+          *offI = nullptr;
+};
+
+// Expands the row-leaf items of blocks blk[0..nb), sorts them by leaf and lays
+// out one panel per leaf (widths: cluster size of sigma, or rank).
+void panel_layout(const int2* blk, int64_t nb, const Cluster* cl, const int2* cl_leaves,
+                  const int64_t* ldpre, int64_t nleaf, const int32_t* rank, int64_t* off,
+                  PanelSet& P, Temps& T, int64_t* tmp, hipStream_t s) {
+  int64_t* cnt = T.get<int64_t>(nb);
+  k_count_leaves<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl_leaves, 0, cnt);
+  HM_LAUNCH_CHECK();
+  P.np = scan_total(cnt, off, nb, tmp, s);
+  if (P.np >= INT32_MAX) throw Error{HM_ERR_STATE, "more than 2^31 block slices"};
+  uint64_t* key = T.get<uint64_t>(P.np);
+  P.ib = T.get<int32_t>(P.np);
+  P.ilf = T.get<int32_t>(P.np);
+  P.sidx = T.get<int32_t>(P.np);
+  k_expand_leaves<<<grid_for(nb, 64), 64, 0, s>>>(blk, nb, cl_leaves, 0, off, key, P.ib, P.ilf,
+                                                  P.sidx);
+  HM_LAUNCH_CHECK();
+  radix_sort_u64_i32(key, P.sidx, P.np, bits_for(nleaf), s);
+  P.wid = T.get<int64_t>(P.np);
+  P.gcol = T.get<int64_t>(P.np);
+  k_item_width<<<grid_for(P.np, 256), 256, 0, s>>>(P.sidx, P.ib, P.np, blk, cl, rank, P.wid);
+  HM_LAUNCH_CHECK();
+  P.cols = scan_total(P.wid, P.gcol, P.np, tmp, s);
+  int64_t* lc = T.get<int64_t>(nleaf + 1);
+  int64_t* ibeg = T.get<int64_t>(nleaf + 1);
+  HM_HIP(hipMemsetAsync(lc, 0, (nleaf + 1) * sizeof(int64_t), s));
+  k_leaf_counts<<<grid_for(P.np, 256), 256, 0, s>>>(key, P.np, lc);
+  HM_LAUNCH_CHECK();
+  scan_excl_i64(lc, ibeg, nleaf + 1, nullptr, s);
+  P.col0 = T.get<int64_t>(nleaf);
+  P.W = T.get<int64_t>(nleaf);
+  int64_t* psize = T.get<int64_t>(nleaf);
+  k_leaf_panels<<<grid_for(nleaf, 256), 256, 0, s>>>(ibeg, P.gcol, P.np, P.cols, ldpre, nleaf,
+                                                     P.col0, P.W, psize);
+  HM_LAUNCH_CHECK();
+  P.poff = T.get<int64_t>(nleaf);
+  P.elems = scan_total(psize, P.poff, nleaf, tmp, s);
+  P.offI = T.get<int64_t>(P.np);
+  P.inv = T.get<int32_t>(P.np);
+  k_item_offsets<<<grid_for(P.np, 256), 256, 0, s>>>(P.sidx, P.ilf, P.np, P.gcol, P.col0, P.poff,
+                                                     ldpre, P.offI, P.inv);
+  HM_LAUNCH_CHECK();
+}
+}  // namespace
 
 template <typename T>
-void launch_pack(const int2* blk, int64_t nb, const Cluster* cl, const int32_t* leaf_lo,
-                 const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                 const int32_t* rank, const int64_t* slot, int64_t slot0, const T* pool, int kmax,
-                 const int64_t* fo, T* arena, uint64_t* ptr_out, hipStream_t s) {
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_pack<T><<<grid_for(nb, 1, 1 << 20), 256, 0, s>>>(blk, nb, cl, L, rank, slot, slot0, pool, kmax,
-                                                     fo, arena, ptr_out);
-  HM_LAUNCH_CHECK();
-}
+void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Alloc& alloc,
+                   hipStream_t s) {
+  const LeafTab L{in.leaf_lo, in.leaf_m, in.ldpre, in.cl_leaves};
+  const int esize = (int)sizeof(T);
+  const int64_t n = in.n, nleaf = in.nleaf;
+  Temps keep{s, {}};       // lives until the product plan is complete
+  int64_t* tmp = keep.get<int64_t>(4);
 
-void launch_lr_meta(const int2* lr, int64_t nl, const int32_t* rank, const int32_t* leaf_lo,
-                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves, int64_t* rk,
-                    int64_t* psz, hipStream_t s) {
-  if (nl == 0) return;
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_lr_meta<<<grid_for(nl, 256), 256, 0, s>>>(lr, nl, rank, L, rk, psz);
+  // ---- near field: dense slices in row-leaf panels
+  auto t0 = clk::now();
+  PanelSet PD;
+  int64_t* oD = keep.get<int64_t>(in.nd + 1);
+  Temps td{s, {}};
+  panel_layout(in.dns, in.nd, in.cl, in.cl_leaves, in.ldpre, nleaf, nullptr, oD, PD, td, tmp, s);
+  out.D_elems = PD.elems;
+  out.dense_cols = PD.cols;
+  T* D = static_cast<T*>(alloc((size_t)PD.elems * esize));
+  int32_t* colmapD = keep.get<int32_t>(PD.cols);
+  k_colmap<<<grid_for(PD.np, 256), 256, 0, s>>>(PD.sidx, PD.ib, PD.np, PD.gcol, PD.wid, in.dns,
+                                                in.cl, nullptr, 0, n, colmapD);
   HM_LAUNCH_CHECK();
-}
+  std::vector<Run*> run_parts;
+  std::vector<std::pair<int32_t*, int64_t>> colmap_parts;
+  Run* runD = keep.get<Run>(nleaf);
+  k_runs<<<grid_for(nleaf, 256), 256, 0, s>>>(PD.col0, PD.W, PD.poff, nleaf, (uint64_t)(uintptr_t)D,
+                                              esize, 0, runD);
+  HM_LAUNCH_CHECK();
+  run_parts.push_back(runD);
+  colmap_parts.push_back({colmapD, PD.cols});
+  if (PD.np > 0) {
+    k_near<T><<<grid_for(PD.np, 1, 1 << 20), 256, 0, s>>>(g, PD.sidx, PD.ib, PD.ilf, PD.np,
+                                                          in.dns, in.cl, L, PD.offI, D);
+    HM_LAUNCH_CHECK();
+  }
+  // keep what the transposed items need
+  int32_t* invD = keep.get<int32_t>(PD.np);
+  int64_t* gcolD = keep.get<int64_t>(PD.np);
+  if (PD.np) {
+    HM_HIP(hipMemcpyAsync(invD, PD.inv, PD.np * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HM_HIP(hipMemcpyAsync(gcolD, PD.gcol, PD.np * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  }
+  td.release();
+  HM_HIP(hipStreamSynchronize(s));
+  out.ms_near = ms_since(t0);
 
-void launch_item_counts(const int2* dns, int64_t nd, const int2* lr, int64_t nl,
-                        const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
-                        const int2* cl_leaves, int64_t* crow, int64_t* ccol, hipStream_t s) {
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_item_counts<<<grid_for(nd + nl, 256), 256, 0, s>>>(dns, nd, lr, nl, L, crow, ccol);
-  HM_LAUNCH_CHECK();
-}
+  // ---- batched ACA in memory-bounded chunks; U slices in row-leaf panels,
+  // V factors block-contiguous
+  t0 = clk::now();
+  const int kmax = in.kmax;
+  const int64_t nl = in.nl;
+  out.rank = static_cast<int32_t*>(alloc((nl + 1) * sizeof(int32_t)));
+  out.info = static_cast<int32_t*>(alloc((nl + 1) * sizeof(int32_t)));
+  out.meta = static_cast<LrMeta*>(alloc((nl + 1) * sizeof(LrMeta)));
+  int64_t* ub = static_cast<int64_t*>(alloc((nl + 1) * sizeof(int64_t)));
+  {
+    int64_t* cnt = keep.get<int64_t>(nl);
+    if (nl) {
+      k_count_leaves<<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl_leaves, 0, cnt);
+      HM_LAUNCH_CHECK();
+    }
+    out.u_items = scan_total(cnt, ub, nl, tmp, s);
+  }
+  out.ucol = static_cast<int64_t*>(alloc((out.u_items + 1) * sizeof(int64_t)));
+  out.uptr = static_cast<uint64_t*>(alloc((out.u_items + 1) * sizeof(uint64_t)));
+  int64_t toff_base = 0, ucols = 0;
+  double ms_pack = 0;
+  if (nl > 0) {
+    Temps ta{s, {}};
+    int64_t* slot = ta.get<int64_t>(nl);
+    int64_t* slot_off = ta.get<int64_t>(nl + 1);
+    int64_t* isbig = ta.get<int64_t>(nl);
+    launch_aca_slots<T>(in.lr, nl, in.cl, kmax, slot, isbig, s);
+    scan_excl_i64(slot, slot_off, nl, slot_off + nl, s);
+    std::vector<int64_t> hoff(nl + 1);
+    HM_HIP(hipMemcpyAsync(hoff.data(), slot_off, (nl + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    int64_t pool_elems = std::min<int64_t>(hoff[nl], std::max<int64_t>(in.pool_budget_bytes / esize, 1));
+    int64_t maxslot = 0;
+    for (int64_t b = 0; b < nl; ++b) maxslot = std::max(maxslot, hoff[b + 1] - hoff[b]);
+    pool_elems = std::max(pool_elems, maxslot);
+    T* pool = static_cast<T*>(dalloc((size_t)pool_elems * esize, s));
+    int64_t* ob = ta.get<int64_t>(nl + 1);
+    int32_t* big = ta.get<int32_t>(nl);
+    int32_t* small = ta.get<int32_t>(nl);
+    int64_t* toffc = ta.get<int64_t>(nl + 1);
+    int64_t* rk64 = ta.get<int64_t>(nl);
+    int64_t* vsz = ta.get<int64_t>(nl);
+    int64_t* voff = ta.get<int64_t>(nl + 1);
+    uint64_t* vptr = ta.get<uint64_t>(nl);
+    int64_t* oU = ta.get<int64_t>(nl + 1);
+    int64_t b0 = 0;
+    while (b0 < nl) {
+      int64_t b1 = b0 + 1;
+      while (b1 < nl && hoff[b1 + 1] - hoff[b0] <= pool_elems) ++b1;
+      const int64_t nb = b1 - b0;
+      const int64_t nbig = scan_total(isbig + b0, ob, nb, tmp, s);
+      launch_split_lists(isbig + b0, ob, nb, big, small, s);
+      launch_aca<T>(g, in.lr + b0, in.cl, slot_off + b0, hoff[b0], pool, big, nbig, small,
+                    nb - nbig, kmax, in.eps, out.rank + b0, out.info + b0, s);
+      HM_HIP(hipStreamSynchronize(s));
+      const auto tp = clk::now();
+      // term offsets in t
+      k_widen_i32<<<grid_for(nb, 256), 256, 0, s>>>(out.rank + b0, nb, rk64);
+      HM_LAUNCH_CHECK();
+      const int64_t terms = scan_total(rk64, toffc, nb, tmp, s);
+      // V factors
+      k_v_sizes<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, out.rank + b0, L, vsz);
+      HM_LAUNCH_CHECK();
+      const int64_t velems = scan_total(vsz, voff, nb, tmp, s);
+      T* varena = static_cast<T*>(alloc((size_t)velems * esize));
+      k_pack_v<T><<<grid_for(nb, 1, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
+                                                          slot_off + b0, hoff[b0], pool, kmax, voff,
+                                                          varena, vptr);
+      HM_LAUNCH_CHECK();
+      k_lr_meta<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, out.rank + b0,
+                                                  toffc, toff_base, vptr, ub + b0, out.meta + b0);
+      HM_LAUNCH_CHECK();
+      // U slices in row-leaf panels
+      Temps tu{s, {}};
+      PanelSet PU;
+      panel_layout(in.lr + b0, nb, in.cl, in.cl_leaves, in.ldpre, nleaf, out.rank + b0, oU, PU,
+                   tu, tmp, s);
+      T* uarena = static_cast<T*>(alloc((size_t)PU.elems * esize));
+      if (PU.np > 0) {
+        k_pack_u<T><<<grid_for(PU.np, 1, 1 << 20), 256, 0, s>>>(
+            PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0, in.cl, L, out.rank + b0, slot_off + b0,
+            hoff[b0], pool, kmax, PU.offI, uarena);
+        HM_LAUNCH_CHECK();
+      }
+      const int64_t colbase = out.dense_cols + ucols;
+      int32_t* cm = keep.get<int32_t>(PU.cols);
+      k_colmap<<<grid_for(PU.np, 256), 256, 0, s>>>(PU.sidx, PU.ib, PU.np, PU.gcol, PU.wid,
+                                                    in.lr + b0, in.cl, toffc, toff_base, n, cm);
+      HM_LAUNCH_CHECK();
+      colmap_parts.push_back({cm, PU.cols});
+      Run* rc = keep.get<Run>(nleaf);
+      k_runs<<<grid_for(nleaf, 256), 256, 0, s>>>(PU.col0, PU.W, PU.poff, nleaf,
+                                                  (uint64_t)(uintptr_t)uarena, esize, colbase, rc);
+      HM_LAUNCH_CHECK();
+      run_parts.push_back(rc);
+      k_urec<<<grid_for(PU.np, 256), 256, 0, s>>>(PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0,
+                                                  in.cl_leaves, ub + b0, PU.gcol, colbase, PU.offI,
+                                                  (uint64_t)(uintptr_t)uarena, esize, out.ucol,
+                                                  out.uptr);
+      HM_LAUNCH_CHECK();
+      HM_HIP(hipStreamSynchronize(s));
+      tu.release();
+      ms_pack += ms_since(tp);
+      toff_base += terms;
+      ucols += PU.cols;
+      out.lr_elems += velems + PU.elems;
+      ++out.nchunks;
+      b0 = b1;
+    }
+    HM_HIP(hipStreamSynchronize(s));
+    dfree(pool, s);
+  }
+  out.toff_total = toff_base;
+  if (toff_base >= INT32_MAX) throw Error{HM_ERR_STATE, "more than 2^31 low-rank terms"};
+  out.ms_aca = ms_since(t0) - ms_pack;
 
-template <typename T>
-void launch_item_expand(const int2* dns, int64_t nd, const int2* lr, int64_t nl, const Cluster* cl,
-                        const int32_t* leaf_lo, const int32_t* leaf_m, const int64_t* ldpre,
-                        const int2* cl_leaves, const int64_t* doff, const T* D,
-                        const uint64_t* lrptr, const int32_t* rank, const int64_t* toff,
-                        const int64_t* pslot, const int64_t* orow, const int64_t* ocol, Item* irow,
-                        uint64_t* krow, Item* icol, uint64_t* kcol, hipStream_t s) {
-  LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_item_expand<T><<<grid_for(nd + nl, 64), 64, 0, s>>>(dns, nd, lr, nl, cl, L, doff, D, lrptr,
-                                                         rank, toff, pslot, orow, ocol, irow, krow,
-                                                         icol, kcol);
-  HM_LAUNCH_CHECK();
+  // ---- product plan: runs, column map, transposed items
+  t0 = clk::now();
+  out.nruns = (int)run_parts.size();
+  out.runs = static_cast<Run*>(alloc((size_t)out.nruns * nleaf * sizeof(Run)));
+  for (int k = 0; k < out.nruns; ++k)
+    HM_HIP(hipMemcpyAsync(out.runs + (int64_t)k * nleaf, run_parts[k], nleaf * sizeof(Run),
+                          hipMemcpyDeviceToDevice, s));
+  out.ncols = out.dense_cols + ucols;
+  out.colmap = static_cast<int32_t*>(alloc((out.ncols + 1) * sizeof(int32_t)));
+  {
+    int64_t o = 0;
+    for (auto& pc : colmap_parts) {
+      if (pc.second)
+        HM_HIP(hipMemcpyAsync(out.colmap + o, pc.first, pc.second * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
+      o += pc.second;
+    }
+  }
+  {
+    Temps tt{s, {}};
+    const int64_t nb_all = in.nd + nl;
+    int64_t* cnt = tt.get<int64_t>(nb_all);
+    int64_t* off = tt.get<int64_t>(nb_all + 1);
+    k_titem_counts<<<grid_for(nb_all, 256), 256, 0, s>>>(in.dns, in.nd, in.lr, nl, in.cl_leaves, cnt);
+    HM_LAUNCH_CHECK();
+    out.ntitems = scan_total(cnt, off, nb_all, tmp, s);
+    if (out.ntitems >= INT32_MAX) throw Error{HM_ERR_STATE, "more than 2^31 transposed items"};
+    TItem* raw = tt.get<TItem>(out.ntitems);
+    uint64_t* key = tt.get<uint64_t>(out.ntitems);
+    int32_t* idx = tt.get<int32_t>(out.ntitems);
+    k_titem_expand<<<grid_for(nb_all, 64), 64, 0, s>>>(in.dns, in.nd, nl, in.cl, L, off, invD, oD,
+                                                       gcolD, out.meta, esize, raw, key, idx);
+    HM_LAUNCH_CHECK();
+    radix_sort_u64_i32(key, idx, out.ntitems, bits_for(nleaf), s);
+    out.titems = static_cast<TItem*>(alloc((out.ntitems + 1) * sizeof(TItem)));
+    k_gather_titems<<<grid_for(out.ntitems, 256), 256, 0, s>>>(raw, idx, out.ntitems, out.titems);
+    HM_LAUNCH_CHECK();
+    int64_t* lc = tt.get<int64_t>(nleaf + 1);
+    int64_t* lb = tt.get<int64_t>(nleaf + 1);
+    HM_HIP(hipMemsetAsync(lc, 0, (nleaf + 1) * sizeof(int64_t), s));
+    k_leaf_counts<<<grid_for(out.ntitems, 256), 256, 0, s>>>(key, out.ntitems, lc);
+    HM_LAUNCH_CHECK();
+    scan_excl_i64(lc, lb, nleaf + 1, nullptr, s);
+    out.tbeg = static_cast<int32_t*>(alloc((nleaf + 1) * sizeof(int32_t)));
+    k_to_i32<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(lb, nleaf + 1, out.tbeg);
+    HM_LAUNCH_CHECK();
+    HM_HIP(hipStreamSynchronize(s));
+  }
+  out.ms_pack = ms_pack + ms_since(t0);
+  keep.release();
 }
-
-void launch_iota(int32_t* v, int64_t n, hipStream_t s) {
-  k_iota<<<grid_for(n, 256), 256, 0, s>>>(v, n);
-  HM_LAUNCH_CHECK();
-}
-void launch_gather_items(const Item* in, const int32_t* idx, int64_t n, Item* out, hipStream_t s) {
-  k_gather_items<<<grid_for(n, 256), 256, 0, s>>>(in, idx, n, out);
-  HM_LAUNCH_CHECK();
-}
-void launch_leaf_counts(const uint64_t* keys, int64_t n, int64_t* cnt, hipStream_t s) {
-  k_leaf_counts<<<grid_for(n, 256), 256, 0, s>>>(keys, n, cnt);
-  HM_LAUNCH_CHECK();
-}
+template void build_storage<float>(const Geom<float>&, const SetupIn&, Storage&, const Alloc&,
+                                   hipStream_t);
+template void build_storage<double>(const Geom<double>&, const SetupIn&, Storage&, const Alloc&,
+                                    hipStream_t);
 
 template <typename T>
 void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                   const int32_t* rank, const uint64_t* lrptr, T* out, int64_t total, hipStream_t s) {
+                   const LrMeta* meta, const uint64_t* uptr, T* out, int64_t total, hipStream_t s) {
   LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_unpack<T><<<grid_for(total, 256), 256, 0, s>>>(lr, b, cl, L, rank, lrptr, out);
+  k_unpack<T><<<grid_for(total, 256), 256, 0, s>>>(lr, b, cl, L, meta, uptr, out);
   HM_LAUNCH_CHECK();
 }
-
-#define HM_INST(T)                                                                                 \
-  template void launch_entries<T>(const Geom<T>&, const int32_t*, const int32_t*, const int32_t*,  \
-                                  int64_t, double*, hipStream_t);                                  \
-  template void launch_near<T>(const Geom<T>&, const int2*, int64_t, const Cluster*,               \
-                               const int32_t*, const int32_t*, const int64_t*, const int2*,        \
-                               const int64_t*, T*, hipStream_t);                                   \
-  template void launch_aca<T>(const Geom<T>&, const int2*, const Cluster*, const int64_t*, int64_t, \
-                              T*, const int32_t*, int64_t, const int32_t*, int64_t, int, double,   \
-                              int32_t*, int32_t*, hipStream_t);                                    \
-  template void launch_pack<T>(const int2*, int64_t, const Cluster*, const int32_t*,               \
-                               const int32_t*, const int64_t*, const int2*, const int32_t*,        \
-                               const int64_t*, int64_t, const T*, int, const int64_t*, T*,         \
-                               uint64_t*, hipStream_t);                                            \
-  template void launch_item_expand<T>(const int2*, int64_t, const int2*, int64_t, const Cluster*,  \
-                                      const int32_t*, const int32_t*, const int64_t*, const int2*, \
-                                      const int64_t*, const T*, const uint64_t*, const int32_t*,   \
-                                      const int64_t*, const int64_t*, const int64_t*,              \
-                                      const int64_t*, Item*, uint64_t*, Item*, uint64_t*,          \
-                                      hipStream_t);                                                \
-  template void launch_unpack<T>(const int2*, int64_t, const Cluster*, const int32_t*,             \
-                                 const int32_t*, const int64_t*, const int2*, const int32_t*,      \
-                                 const uint64_t*, T*, int64_t, hipStream_t);
-HM_INST(float)
-HM_INST(double)
-#undef HM_INST
+template void launch_unpack<float>(const int2*, int64_t, const Cluster*, const int32_t*,
+                                   const int32_t*, const int64_t*, const int2*, const LrMeta*,
+                                   const uint64_t*, float*, int64_t, hipStream_t);
+template void launch_unpack<double>(const int2*, int64_t, const Cluster*, const int32_t*,
+                                    const int32_t*, const int64_t*, const int2*, const LrMeta*,
+                                    const uint64_t*, double*, int64_t, hipStream_t);
 
 }  // namespace hm
