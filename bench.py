@@ -29,6 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs; valid only while the sources it was taken on are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fwd2_f32_icosphere_L6_traffic.txt")
+TRAFFIC_SOURCES = ("hm_matvec.hip", "hm_setup.hip", "hm_internal.h")
 METRIC = "H-setup s + H-matvec GB/s (% HBM peak) at rel.err ≤1e-6, FP32 vs FP64"
 
 
@@ -60,6 +64,48 @@ def cpu_baseline(V, T, x, rows, workers):
 
 
 # ---------------------------------------------------------------- GPU leg
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1806_11558_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(level, leaf, eps, form):
+    """HBM bytes per launch of the dominant kernel from the stored counter
+    summary, or None if it is missing, for another workload, or stale."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if (kv["sources_sha256"] != sources_sha256() or int(kv["level"]) != level
+                or int(kv["leaf"]) != leaf or float(kv["eps"]) != eps or kv["form"] != form):
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    """A plain copy of known size (read mib MiB, write mib MiB) for scaling
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.add(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": mib << 20, "copy_probe_bytes_written": mib << 20,
+                      "launches": 3}), flush=True)
+
+
 def mv_bytes(st, s_store, s_vec, s_acc, nrhs=1):
     """Algorithmic bytes of one product: every stored value once, x and y
     once, the permutation, 16 B per block descriptor."""
@@ -132,14 +178,22 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--reps", type=int, default=20, help="timed 1-rhs products per form and step")
     ap.add_argument("--gmres-tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-rows", type=int, default=512)
+    ap.add_argument("--cpu-rows", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="f32,f64")
+    ap.add_argument("--forms", default="f32,f64",
+                    help="comma list of f32, f64, f16 (FP32 dense + FP16 factors)")
+    ap.add_argument("--rhs", default="ones", choices=["ones", "normal"],
+                    help="GMRES right-hand side: f = 1 or a seeded N(0,1) column")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path would shard by row clusters, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard by row clusters over GPUs; not built)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     from synthetic import icosphere, normal_columns, sample_rows
     V, T = icosphere(args.level)
@@ -158,7 +212,10 @@ def main():
     torch.cuda.set_device(0)
     forms = args.forms.split(",")
     xg = torch.tensor(X, device="cuda")
-    fg = torch.ones(n, dtype=torch.float64, device="cuda")
+    if args.rhs == "ones":
+        fg = torch.ones(n, dtype=torch.float64, device="cuda")
+    else:
+        fg = torch.tensor(normal_columns(n, 1, seed=2)[:, 0], device="cuda")
 
     for _ in range(args.warmup):
         for prec in forms:
@@ -181,16 +238,23 @@ def main():
     for prec in forms:
         rs = res[prec]
         st = rs[-1]["st"]
-        s_store = 4 if prec == "f32" else 8
+        s_store = {"f32": 4, "f64": 8, "f16": 4}[prec]
         s_vec = 8                       # x is double (torch default)
         s_acc = 8
         B = mv_bytes(st, s_store, s_vec, s_acc)
         B16 = mv_bytes(st, s_store, s_vec, s_acc, 16)
+        if prec == "f16":
+            # dense blocks in FP32, factors in FP16: use the stored bytes
+            extra = st["stored_bytes"] - s_store * (st["dense_entries"] + st["lr_entries"])
+            B += extra
+            B16 += extra
         ms = float(np.median([m for r in rs for m in r["ms"]]))
         ms16 = float(np.median([m for r in rs for m in r["ms16"]]))
         p2 = [r["kt"]["fwd_panels"] for r in rs]
         p2_ms = sum(q["ms"] for q in p2) / max(1, sum(q["launches"] for q in p2))
         p2_B = phase2_bytes(st, s_store, s_acc, s_vec)
+        if prec == "f16":
+            p2_B -= 2 * st["lr_u_entries"]
         o = dict(
             setup_s=float(np.median([r["setup_s"] for r in rs])),
             setup_phases_ms={k: round(v, 3) for k, v in rs[-1]["timings"].items()},
@@ -200,6 +264,7 @@ def main():
             kernel_ms_per_launch={k: (v["ms"] / v["launches"] if v["launches"] else None)
                                   for k, v in rs[-1]["kt"].items() if v["launches"]},
             gmres_iters=rs[-1]["gmres_iters"], gmres_s=float(np.median([r["solve_s"] for r in rs])),
+            gmres_status=rs[-1]["gmres_status"],
             gmres_rel_residual=rs[-1]["gmres_rel_residual"],
             stats={k: st[k] for k in ("n_dense", "n_lr", "dense_entries", "lr_entries",
                                       "rank_sum", "rank_max", "cap_hits", "stored_bytes",
@@ -224,13 +289,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if main_form == "f32" else "f64",
+        "dtype": main_form,
         "data": "synthetic",
         "config": {"workload": f"unit icosphere L={args.level} (N={n}) Laplace single-layer "
                                f"collocation, leaf {args.leaf}, eta 1, ACA eps {args.eps:g}; "
-                               "product x: N(0,1) seed 0; GMRES f=1",
+                               f"product x: N(0,1) seed 0; GMRES f={args.rhs} to {args.gmres_tol:g}",
                    "n": n, "eps": args.eps, "forms": forms},
         "setup_s": {p: round(out[p]["setup_s"], 4) for p in out},
+        "gmres_s": {p: round(out[p]["gmres_s"], 4) for p in out},
+        "gmres_iters": {p: out[p]["gmres_iters"] for p in out},
         "matvec_gbs": {p: round(out[p]["matvec_gbs"], 1) for p in out},
         "matvec_pct_hbm_peak": {p: round(100 * out[p]["matvec_gbs"] / HBM_PEAK_GBS, 1) for p in out},
         "rel_err_sampled": {p: out[p].get("rel_err_sampled") for p in out},
@@ -241,7 +308,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(M["phase2_gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.level, args.leaf, args.eps, main_form),
         },
         "forms": out,
     }

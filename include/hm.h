@@ -62,9 +62,15 @@ typedef enum {
 /* Arithmetic form of the build: kernel evaluation, ACA and storage. */
 typedef enum {
   HM_F64 = 0,             /* everything in double                            */
-  HM_F32 = 1              /* evaluation, ACA and storage in float; the
+  HM_F32 = 1,             /* evaluation, ACA and storage in float; the
                              geometry (centroids) and the pairwise centroid
                              difference stay double                         */
+  HM_F32_F16 = 2          /* as HM_F32, but the low-rank factors are stored
+                             in FP16: V as is (|v| <= 1 by the pivot
+                             normalisation), every column of U divided by an
+                             FP32 max-abs scale; products accumulate in float
+                             (or double for double vectors).  Dense blocks
+                             stay FP32                                       */
 } hm_precision;
 
 /* flags */

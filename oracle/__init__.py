@@ -4,7 +4,7 @@ This package is a plain, slow, obviously-correct NumPy implementation of what
 the HIP library computes, written from the paper (Harbrecht & Zaspel,
 "A scalable H-matrix approach for the solution of boundary integral
 equations on multi-GPU clusters", arXiv 1806.11558) and the collocation
-discretisation chosen for this build.  Only the test-suite, the smoke check
+discretisation the library implements.  Only the test-suite, the smoke check
 and the CPU-baseline leg of the benchmark may import it; the library and its
 Python binding never do, and it shares no code with them.
 

@@ -3,7 +3,7 @@
 Sec. 2.1 (Example 1, eqs. singleLayerPotential and
 exampleBoundaryIntegralEquation) defines S u (x) = int_Gamma u(y) / (4 pi
 |x - y|) dsigma_y = f(x) on the surface.  The paper discretises it by
-Galerkin BEM (Sec. 2.2); this build uses collocation, the alternative named
+Galerkin BEM (Sec. 2.2); here it is collocation, the alternative named
 in Sec. 1, with nodes at element centres as in Sec. 4.1: one unknown per flat
 triangle T_j, collocation point x_i = centroid of T_i, and
 

@@ -10,7 +10,7 @@ import numpy as np
 
 HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE = -1, -2, -3, -4, -5
-HM_F64, HM_F32 = 0, 1
+HM_F64, HM_F32, HM_F32_F16 = 0, 1, 2
 HM_STRICT = 1
 HM_PROFILE = 2
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
@@ -216,12 +216,12 @@ class HMatrix:
         p.eta = eta
         p.aca_eps = eps
         p.max_rank = max_rank
-        p.precision = {"f64": HM_F64, "f32": HM_F32}[precision]
+        p.precision = {"f64": HM_F64, "f32": HM_F32, "f16": HM_F32_F16}[precision]
         p.flags = (HM_STRICT if strict else 0) | (HM_PROFILE if profile else 0)
         p.mem_limit_bytes = mem_limit_bytes
         self.params = p
         self.n = int(np.asarray(triangles).shape[0])
-        self.storage_dtype = np.float32 if precision == "f32" else np.float64
+        self.storage_dtype = np.float64 if precision == "f64" else np.float32
         self._h = hm_build(vertices, triangles, p, stream)
 
     # products -------------------------------------------------------------

@@ -66,7 +66,8 @@ struct hm_handle {
   int device = 0;
   hm_params p{};
   int64_t n = 0;
-  int f32 = 0;
+  int form = 0;                  // hm_precision
+  int f32 = 0;                   // evaluation in float
   size_t ts = 8;                 // bytes per stored value
   std::vector<void*> owned;      // persistent allocations
   int64_t bytes = 0;
@@ -138,6 +139,7 @@ struct hm_handle {
     P.n = n;
     P.z = z;
     P.w = w;
+    P.su = sto.su;
     P.max_nr_t = max_nr_t;
     P.grid = grid;
     P.prof = profiling ? const_cast<MvProfile*>(&prof) : nullptr;
@@ -150,6 +152,18 @@ namespace {
 using clk = std::chrono::steady_clock;
 double ms_since(clk::time_point t0) {
   return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// The setup's temporaries come from the stream-ordered allocator; return the
+// memory it keeps cached to the device so that later allocations (of this or
+// another handle, or of the caller) do not compete with it.
+void release_cached_memory(hipStream_t s) {
+  HM_HIP(hipStreamSynchronize(s));
+  int dev = 0;
+  HM_HIP(hipGetDevice(&dev));
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+  (void)hipGetLastError();
 }
 
 template <typename F>
@@ -181,7 +195,7 @@ int64_t scan_total(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hip
 }
 
 // ---------------------------------------------------------------- the build
-template <typename T>
+template <typename T, typename TL>
 void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T_host,
                 hipStream_t s) {
   const int64_t n = h->n;
@@ -290,7 +304,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     SetupIn in{n, h->cl, h->cl_leaves, h->leaf_lo, h->leaf_m, h->ldpre, h->nleaf,
                h->dns, h->nd, h->lr, h->nl, p.max_rank > 0 ? p.max_rank : 64, p.aca_eps,
                std::max<int64_t>(budget, 1 << 20)};
-    build_storage<T>(g, in, h->sto, [h](size_t b) { return h->alloc(b); }, s);
+    build_storage<T, TL>(g, in, h->sto, [h](size_t b) { return h->alloc(b); }, s);
     h->ms[4] = h->sto.ms_near;
     h->ms[5] = h->sto.ms_aca;
     h->ms[6] = h->sto.ms_pack;
@@ -313,6 +327,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   HM_HIP(hipStreamSynchronize(s));
   h->ms[6] += ms_since(t0);
   dfree(tmp, s);
+  release_cached_memory(s);
 
   // ---- statistics
   std::vector<int32_t> rk(h->nl), inf(h->nl);
@@ -348,11 +363,11 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     const int64_t rows = inf[b] >> 1;
     st.aca_entry_evals += rows * nn + (int64_t)rk[b] * m;
   }
-  st.stored_bytes = (h->sto.D_elems + h->sto.lr_elems) * (int64_t)sizeof(T);
+  st.stored_bytes = h->sto.D_elems * (int64_t)sizeof(T) + h->sto.lr_elems * (int64_t)sizeof(TL);
   st.n_panel_cols = h->sto.ncols;
   st.n_titems = h->sto.ntitems;
   st.device_bytes = h->bytes;
-  st.precision = h->f32;
+  st.precision = h->form;
   st.aca_chunks = h->sto.nchunks;
   h->ms[7] = ms_since(t_start);
   if ((p.flags & HM_STRICT) && st.cap_hits > 0)
@@ -391,7 +406,8 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
   if (n_vertices < 3 || n_vertices > (int64_t)INT32_MAX) return arg_error("hm_build: n_vertices out of range");
   if (p->leaf_size < 1 || p->leaf_size > kMaxLeaf) return arg_error("hm_build: leaf_size must be in 1..64");
   if (p->max_rank < 0 || p->max_rank > kMaxRank) return arg_error("hm_build: max_rank must be in 0..256");
-  if (p->precision != HM_F64 && p->precision != HM_F32) return arg_error("hm_build: bad precision");
+  if (p->precision != HM_F64 && p->precision != HM_F32 && p->precision != HM_F32_F16)
+    return arg_error("hm_build: bad precision");
   if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return arg_error("hm_build: eta must be finite and >= 0");
   if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps)) return arg_error("hm_build: aca_eps must be finite and >= 0");
   if (p->mem_limit_bytes < 0) return arg_error("hm_build: mem_limit_bytes < 0");
@@ -417,7 +433,8 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
     h->p = *p;
     if (h->p.max_rank == 0) h->p.max_rank = 64;
     h->n = n_triangles;
-    h->f32 = (p->precision == HM_F32) ? 1 : 0;
+    h->form = p->precision;
+    h->f32 = (p->precision != HM_F64) ? 1 : 0;
     h->ts = h->f32 ? 4 : 8;
     HM_HIP(hipGetDevice(&h->device));
     if (p->flags & HM_PROFILE) {
@@ -425,10 +442,12 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
       h->profiling = true;
     }
     hipStream_t s = as_stream(stream);
-    if (h->f32)
-      build_impl<float>(h.get(), vertices, n_vertices, triangles, s);
+    if (h->form == HM_F32_F16)
+      build_impl<float, _Float16>(h.get(), vertices, n_vertices, triangles, s);
+    else if (h->form == HM_F32)
+      build_impl<float, float>(h.get(), vertices, n_vertices, triangles, s);
     else
-      build_impl<double>(h.get(), vertices, n_vertices, triangles, s);
+      build_impl<double, double>(h.get(), vertices, n_vertices, triangles, s);
     *out = h.release();
     return HM_OK;
   });
@@ -445,7 +464,7 @@ static hm_status matvec_common(hm_handle* h, const void* x, void* y, int32_t nrh
   const char* yb = (const char*)y;
   if (xb < yb + vb && yb < xb + vb) return arg_error("hm_matvec: x and y overlap");
   return guarded([&]() -> hm_status {
-    matvec_dispatch(h->plan(), h->f32, x, y, nrhs, dtype == HM_F32 ? 1 : 0, transposed,
+    matvec_dispatch(h->plan(), h->form, x, y, nrhs, dtype == HM_F32 ? 1 : 0, transposed,
                     as_stream(stream));
     return HM_OK;
   });
@@ -480,7 +499,7 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
     const bool tr = sp->transpose != 0;
     const MvPlan P = h->plan();
     auto apply = [&](const double* in, double* out) {
-      matvec_dispatch(P, h->f32, in, out, nr, 0, tr, s);
+      matvec_dispatch(P, h->form, in, out, nr, 0, tr, s);
     };
     // device workspace (freed at return)
     std::vector<void*> tmp;
@@ -657,6 +676,11 @@ void hm_free(hm_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   delete h;
+  int dev = 0;
+  hipMemPool_t pool;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+    (void)hipMemPoolTrimTo(pool, 0);
+  (void)hipGetLastError();
 }
 
 hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int64_t* needed) {
@@ -757,12 +781,18 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
         if (total == 0) return HM_OK;
         void* buf = nullptr;
         HM_HIP(hipMalloc(&buf, total * h->ts));
-        if (h->f32)
-          launch_unpack<float>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
-                               h->sto.meta, h->sto.uptr, (float*)buf, total, 0);
+        if (h->form == HM_F32_F16)
+          launch_unpack<_Float16, float>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre,
+                                         h->cl_leaves, h->sto.meta, h->sto.uptr, h->sto.su,
+                                         (float*)buf, total, 0);
+        else if (h->form == HM_F32)
+          launch_unpack<float, float>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre,
+                                      h->cl_leaves, h->sto.meta, h->sto.uptr, nullptr,
+                                      (float*)buf, total, 0);
         else
-          launch_unpack<double>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre, h->cl_leaves,
-                                h->sto.meta, h->sto.uptr, (double*)buf, total, 0);
+          launch_unpack<double, double>(h->lr, b, h->cl, h->leaf_lo, h->leaf_m, h->ldpre,
+                                        h->cl_leaves, h->sto.meta, h->sto.uptr, nullptr,
+                                        (double*)buf, total, 0);
         HM_HIP(hipMemcpy(dst, buf, total * h->ts, hipMemcpyDeviceToHost));
         HM_HIP(hipFree(buf));
         return HM_OK;

@@ -87,6 +87,8 @@ struct LrMeta {
   uint64_t vptr;
   int32_t r, toff, sf, sl, tf, tl;
   int64_t ub;
+  int32_t vld;   // ld shared by all column-leaf slices, 0 if they differ
+  int32_t pad;
 };
 // Column-leaf item of the transposed product: kind 0 = columns of a dense
 // slice (partial dots at w[src ..]), kind 1 = V slice at `data` (w = rank,
@@ -118,6 +120,7 @@ struct MvPlan {
   int64_t n;
   void* z;                  // workspace: [x in Morton order ; t], 16 columns
   void* w;                  // workspace: panel-column partial dots
+  const float* su;          // per-term scales of FP16 U factors (null: none)
   int max_nr_t;             // right-hand sides per transposed pass (w size)
   int grid;
   MvProfile* prof;          // null unless profiling
@@ -150,6 +153,7 @@ struct Storage {
   int64_t lr_elems = 0, toff_total = 0, nchunks = 0, u_items = 0;
   Run* runs = nullptr;
   int nruns = 0;
+  float* su = nullptr;       // per-term scales when the factors are FP16
   int32_t* colmap = nullptr;
   int64_t ncols = 0;
   TItem* titems = nullptr;
@@ -158,15 +162,19 @@ struct Storage {
   double ms_near = 0, ms_aca = 0, ms_pack = 0;
 };
 using Alloc = std::function<void*(size_t)>;
-template <typename T>
+// T: evaluation, ACA and dense storage type; TL: storage type of the
+// low-rank factors (T, or _Float16 with per-term scales for U).
+template <typename T, typename TL>
 void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Alloc& alloc,
                    hipStream_t s);
-template <typename T>
+template <typename TL, typename TO>
 void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                   const LrMeta* meta, const uint64_t* uptr, T* out, int64_t total, hipStream_t s);
+                   const LrMeta* meta, const uint64_t* uptr, const float* su, TO* out,
+                   int64_t total, hipStream_t s);
 
-void matvec_dispatch(const MvPlan& P, int storage_f32, const void* x, void* y, int nrhs,
+// storage: 0 FP64, 1 FP32, 2 FP32 dense + FP16 factors
+void matvec_dispatch(const MvPlan& P, int storage, const void* x, void* y, int nrhs,
                      int vec_f32, bool transposed, hipStream_t s);
 
 // ---------------------------------------------------------------- primitives

@@ -24,19 +24,25 @@
 // A wavefront reads a slice in 16-byte granules: lane = (column group cg,
 // row granule g), R = ld/G row granules per column, C = 64/R columns per
 // instruction.
+#include <type_traits>
+
 #include "hm_internal.h"
 
 namespace hm {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
-// 16-byte granule loads; the stored operator is streamed once per product,
-// so the loads are non-temporal.
+// Granule loads of G stored values per lane, returned in the arithmetic type
+// E; the stored operator is streamed once per product, so the loads are
+// non-temporal.  FP32 and FP16 granules both cover 4 rows (16 and 8 bytes),
+// so dense and FP16 factor panels of a leaf share one lane layout.
 template <typename T>
 struct Gran;
 template <>
 struct Gran<float> {
+  using E = float;
   static constexpr int G = 4;
   __device__ static inline void load(const float* p, float* o) {
     const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
@@ -45,12 +51,48 @@ struct Gran<float> {
 };
 template <>
 struct Gran<double> {
+  using E = double;
   static constexpr int G = 2;
   __device__ static inline void load(const double* p, double* o) {
     const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
     o[0] = v.x; o[1] = v.y;
   }
 };
+template <>
+struct Gran<_Float16> {
+  using E = float;
+  static constexpr int G = 4;
+  __device__ static inline void load(const _Float16* p, float* o) {
+    const f16x4 v = __builtin_nontemporal_load(reinterpret_cast<const f16x4*>(p));
+    o[0] = (float)v.x; o[1] = (float)v.y; o[2] = (float)v.z; o[3] = (float)v.w;
+  }
+};
+
+// NR consecutive values z[0..NR) (16-byte aligned when NR * sizeof(A) is a
+// multiple of 16: z rows are NR values long and the buffer is 256-byte aligned).
+template <typename A, int NR>
+__device__ inline void load_row(const A* __restrict__ p, A (&o)[NR]) {
+  if constexpr (sizeof(A) == 8 && NR % 2 == 0) {
+#pragma unroll
+    for (int k = 0; k < NR; k += 2) {
+      const f64x2 v = *reinterpret_cast<const f64x2*>(p + k);
+      o[k] = v.x;
+      o[k + 1] = v.y;
+    }
+  } else if constexpr (sizeof(A) == 4 && NR % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < NR; k += 4) {
+      const f32x4 v = *reinterpret_cast<const f32x4*>(p + k);
+      o[k] = v.x;
+      o[k + 1] = v.y;
+      o[k + 2] = v.z;
+      o[k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) o[k] = p[k];
+  }
+}
 
 // Sum of v over the R lanes g = 0..R-1 of a lane segment; valid in the lane
 // with g == 0.  Every lane of the wavefront must call it.
@@ -77,13 +119,36 @@ __global__ void k_gather(const VT* __restrict__ x, int nrhs, int k0, int nr,
 }
 
 // ------------------------------------------------------------------ forward, phase 1
-// One wavefront per admissible block: t_b = V_b^T x_sigma, written to
-// z[n + toff + l].  Column l of every slice is summed over its row granules
-// (segmented shuffle) and moved to lane l, which accumulates over slices.
+// One wavefront per admissible block: t_b = V_b^T x_sigma (times the U scale
+// when the factors are FP16), written to z[n + toff + l].
+//
+// Lane = (column group cg, row granule g); the P = ceil(r / C) passes of C
+// columns each keep a register accumulator.  When all column-leaf slices
+// share one ld (the usual case) the x granule is loaded once per slice, the
+// accumulators run over all slices, and each pass is reduced once at the
+// end; otherwise every slice is reduced on its own.  Column sums move to
+// lane l, which owns term l.
+template <typename A, int NR>
+__device__ inline void fwd1_flush(A (&p)[NR], int g, int R, int j0, int C, int r, int lane,
+                                  A (&tl)[NR]) {
+#pragma unroll
+  for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
+  const int q = lane - j0;
+  const bool mine = q >= 0 && q < C && lane < r;
+  const int src = mine ? q * R : 0;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const A v = __shfl(p[k], src, 64);
+    if (mine) tl[k] += v;
+  }
+}
+
 template <typename T, typename A, int NR>
 __global__ __launch_bounds__(256) void k_fwd1(const LrMeta* __restrict__ meta, int64_t nl,
-                                              MvLeaves L, A* __restrict__ z, int64_t n) {
+                                              MvLeaves L, A* __restrict__ z, int64_t n,
+                                              const float* __restrict__ su) {
   constexpr int G = Gran<T>::G;
+  constexpr int PMAX = NR == 1 ? 4 : (NR <= 4 ? 2 : 1);
   const int lane = threadIdx.x & 63;
   const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
@@ -95,64 +160,139 @@ __global__ __launch_bounds__(256) void k_fwd1(const LrMeta* __restrict__ meta, i
 #pragma unroll
     for (int k = 0; k < NR; ++k) tl[k] = 0;
     const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
-    for (int lf = M.sf; lf <= M.sl; ++lf) {
-      const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
-      const int R = ld / G, C = 64 / R;
+    const int R0 = M.vld / G, C0 = R0 > 0 ? 64 / R0 : 1;
+    if (M.vld > 0 && r <= PMAX * C0) {
+      const int ld = M.vld, R = R0, C = C0;
       const int cg = lane / R, g = lane % R;
       const bool act = cg < C;
-      const int m = L.m[lf], lo = L.lo[lf];
-      A xg[G][NR];
+      const int P = (r + C - 1) / C;
+      A acc[PMAX][NR];
 #pragma unroll
-      for (int e = 0; e < G; ++e) {
-        const int row = g * G + e;
+      for (int q = 0; q < PMAX; ++q)
 #pragma unroll
-        for (int k = 0; k < NR; ++k)
-          xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
-      }
-      for (int j0 = 0; j0 < r; j0 += C) {
-        const int j = j0 + cg;
-        A p[NR];
+        for (int k = 0; k < NR; ++k) acc[q][k] = 0;
+      const int64_t sstride = (int64_t)ld * r;
+      const T* S0 = S + g * G;
+      for (int lf = M.sf; lf <= M.sl; ++lf, S0 += sstride) {
+        const int m = L.m[lf], lo = L.lo[lf];
+        A xg[G][NR];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] = 0;
-        if (act && j < r) {
-          T s[G];
-          Gran<T>::load(S + (int64_t)j * ld + g * G, s);
+        for (int e = 0; e < G; ++e) {
+          const int row = g * G + e;
 #pragma unroll
-          for (int e = 0; e < G; ++e)
-#pragma unroll
-            for (int k = 0; k < NR; ++k) p[k] += (A)s[e] * xg[e][k];
+          for (int k = 0; k < NR; ++k)
+            xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
         }
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
-        const int q = lane - j0;
-        const bool mine = q >= 0 && q < C && lane < r;
-        const int src = mine ? q * R : 0;
+        for (int q = 0; q < PMAX; ++q) {
+          if (q < P) {                                  // uniform over the wavefront
+            const int j = q * C + cg;
+            const bool ok = act && j < r;
+            typename Gran<T>::E sv[G];
+            Gran<T>::load(S0 + (int64_t)(ok ? j : r - 1) * ld, sv);
 #pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          const A v = __shfl(p[k], src, 64);
-          if (mine) tl[k] += v;
+            for (int e = 0; e < G; ++e) {
+              const A a = ok ? (A)sv[e] : (A)0;
+#pragma unroll
+              for (int k = 0; k < NR; ++k) acc[q][k] += a * xg[e][k];
+            }
+          }
         }
       }
-      S += (int64_t)ld * r;
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q)
+        if (q < P) fwd1_flush<A, NR>(acc[q], g, R, q * C, C, r, lane, tl);
+    } else {
+      for (int lf = M.sf; lf <= M.sl; ++lf) {
+        const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+        const int R = ld / G, C = 64 / R;
+        const int cg = lane / R, g = lane % R;
+        const bool act = cg < C;
+        const int m = L.m[lf], lo = L.lo[lf];
+        A xg[G][NR];
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+          const int row = g * G + e;
+#pragma unroll
+          for (int k = 0; k < NR; ++k)
+            xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
+        }
+        for (int j0 = 0; j0 < r; j0 += C) {
+          const int j = j0 + cg;
+          A p[NR];
+#pragma unroll
+          for (int k = 0; k < NR; ++k) p[k] = 0;
+          if (act && j < r) {
+            typename Gran<T>::E sv[G];
+            Gran<T>::load(S + (int64_t)j * ld + g * G, sv);
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+#pragma unroll
+              for (int k = 0; k < NR; ++k) p[k] += (A)sv[e] * xg[e][k];
+          }
+          fwd1_flush<A, NR>(p, g, R, j0, C, r, lane, tl);
+        }
+        S += (int64_t)ld * r;
+      }
     }
     if (lane < r) {
+      const A sc = su ? (A)su[M.toff + lane] : (A)1;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = tl[k];
+      for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = tl[k] * sc;
     }
   }
 }
 
 // ------------------------------------------------------------------ forward, phase 2
 // Per row leaf: y_c = sum over its panels of P z[colmap], then scattered to
-// application order.
-template <typename T, typename A, typename VT, int NR>
+// application order.  Panel 0 of a leaf holds dense slices (type TD), the
+// others U slices (type TL); both share the lane layout.
+template <typename T, typename A, int NR, int G>
+__device__ inline void fwd2_run(const Run& rn, int ld, int C, int cg, int g, bool act, int wave,
+                                const int32_t* __restrict__ colmap, const A* __restrict__ z,
+                                A (&acc)[G][NR]) {
+  constexpr int UNR = 4;
+  static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
+  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
+  const int32_t* map = colmap + rn.col0;
+  const int ngrp = (rn.w + C - 1) / C;
+  // Loads are unconditional: a lane without a column of its own reads the
+  // panel's last column and contributes zero, so the compiler keeps all
+  // UNR loads in flight instead of waiting inside divergent branches.
+  for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
+    typename Gran<T>::E s[UNR][G];
+    int32_t zi[UNR];
+    bool ok[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + 4 * u;
+      const int j = q * C + cg;
+      ok[u] = act && q < ngrp && j < rn.w;
+      const int jj = ok[u] ? j : rn.w - 1;
+      Gran<T>::load(S + (int64_t)jj * ld, s[u]);
+      zi[u] = map[jj];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      A zz[NR];
+      load_row<A, NR>(z + (int64_t)zi[u] * NR, zz);
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const A sv = ok[u] ? (A)s[u][e] : (A)0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[e][k] += sv * zz[k];
+      }
+    }
+  }
+}
+
+template <typename TD, typename TL, typename A, typename VT, int NR>
 __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int nruns, MvLeaves L,
                                               const int32_t* __restrict__ colmap,
                                               const A* __restrict__ z,
                                               const int32_t* __restrict__ perm, VT* __restrict__ y,
                                               int nrhs, int k0) {
-  constexpr int G = Gran<T>::G;
-  constexpr int UNR = 4;
+  constexpr int G = Gran<TD>::G;
   __shared__ A ybuf[4][kMaxLeaf][NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
@@ -169,36 +309,13 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int 
     for (int kr = 0; kr < nruns; ++kr) {
       const Run rn = runs[(int64_t)kr * L.nleaf + c];
       if (rn.w == 0) continue;
-      const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
-      const int32_t* map = colmap + rn.col0;
-      const int ngrp = (rn.w + C - 1) / C;
-      for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
-        T s[UNR][G];
-        int32_t zi[UNR];
-        bool ok[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int q = q0 + 4 * u;
-          const int j = q * C + cg;
-          ok[u] = act && q < ngrp && j < rn.w;
-          zi[u] = 0;
-          if (ok[u]) {
-            Gran<T>::load(S + (int64_t)j * ld, s[u]);
-            zi[u] = map[j];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          if (ok[u]) {
-            A zz[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) zz[k] = z[(int64_t)zi[u] * NR + k];
-#pragma unroll
-            for (int e = 0; e < G; ++e)
-#pragma unroll
-              for (int k = 0; k < NR; ++k) acc[e][k] += (A)s[u][e] * zz[k];
-          }
-        }
+      if constexpr (std::is_same<TD, TL>::value) {
+        fwd2_run<TD, A, NR, G>(rn, ld, C, cg, g, act, wave, colmap, z, acc);
+      } else {
+        if (kr == 0)
+          fwd2_run<TD, A, NR, G>(rn, ld, C, cg, g, act, wave, colmap, z, acc);
+        else
+          fwd2_run<TL, A, NR, G>(rn, ld, C, cg, g, act, wave, colmap, z, acc);
       }
     }
     // combine the column groups (tree over cg, stride R), then the waves
@@ -234,10 +351,41 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int 
 
 // ------------------------------------------------------------------ transposed, phase 1
 // Per row leaf: w[col0 + j] = sum_i P[i][j] x_c[i] for every panel column.
-template <typename T, typename A, int NR>
+template <typename T, typename A, int NR, int G>
+__device__ inline void tr1_run(const Run& rn, int ld, int R, int C, int cg, int g, bool act,
+                               int wave, const A (&xg)[G][NR], A* __restrict__ w) {
+  static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
+  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
+  const int ngrp = (rn.w + C - 1) / C;
+  for (int q = wave; q < ngrp; q += 4) {
+    const int j = q * C + cg;
+    A p[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) p[k] = 0;
+    const bool ok = act && j < rn.w;
+    {
+      typename Gran<T>::E sv[G];
+      Gran<T>::load(S + (int64_t)(ok ? j : rn.w - 1) * ld, sv);
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const A a = ok ? (A)sv[e] : (A)0;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) p[k] += a * xg[e][k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
+    if (act && g == 0 && j < rn.w) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) w[(rn.col0 + j) * NR + k] = p[k];
+    }
+  }
+}
+
+template <typename TD, typename TL, typename A, int NR>
 __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, int nruns, MvLeaves L,
                                              const A* __restrict__ z, A* __restrict__ w) {
-  constexpr int G = Gran<T>::G;
+  constexpr int G = Gran<TD>::G;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
@@ -256,27 +404,13 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, int n
     for (int kr = 0; kr < nruns; ++kr) {
       const Run rn = runs[(int64_t)kr * L.nleaf + c];
       if (rn.w == 0) continue;
-      const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
-      const int ngrp = (rn.w + C - 1) / C;
-      for (int q = wave; q < ngrp; q += 4) {
-        const int j = q * C + cg;
-        A p[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] = 0;
-        if (act && j < rn.w) {
-          T s[G];
-          Gran<T>::load(S + (int64_t)j * ld, s);
-#pragma unroll
-          for (int e = 0; e < G; ++e)
-#pragma unroll
-            for (int k = 0; k < NR; ++k) p[k] += (A)s[e] * xg[e][k];
-        }
-#pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
-        if (act && g == 0 && j < rn.w) {
-#pragma unroll
-          for (int k = 0; k < NR; ++k) w[(rn.col0 + j) * NR + k] = p[k];
-        }
+      if constexpr (std::is_same<TD, TL>::value) {
+        tr1_run<TD, A, NR, G>(rn, ld, R, C, cg, g, act, wave, xg, w);
+      } else {
+        if (kr == 0)
+          tr1_run<TD, A, NR, G>(rn, ld, R, C, cg, g, act, wave, xg, w);
+        else
+          tr1_run<TL, A, NR, G>(rn, ld, R, C, cg, g, act, wave, xg, w);
       }
     }
   }
@@ -288,7 +422,7 @@ template <typename A, int NR>
 __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta, int64_t nl,
                                                  const int64_t* __restrict__ ucol,
                                                  const A* __restrict__ w, A* __restrict__ z,
-                                                 int64_t n) {
+                                                 int64_t n, const float* __restrict__ su) {
   const int lane = threadIdx.x & 63;
   const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
@@ -304,8 +438,9 @@ __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
     }
+    const A sc = su ? (A)su[M.toff + lane] : (A)1;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = acc[k];
+    for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = acc[k] * sc;
   }
 }
 
@@ -347,11 +482,10 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
         for (int j0 = 0; j0 < I.w; j0 += C) {
           const int j = j0 + cg;
           if (act && j < I.w) {
-            T s[G];
+            typename Gran<T>::E s[G];
             Gran<T>::load(S + (int64_t)j * ld + g * G, s);
             A zz[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) zz[k] = z[(n + I.src + j) * NR + k];
+            load_row<A, NR>(z + (n + I.src + j) * NR, zz);
 #pragma unroll
             for (int e = 0; e < G; ++e)
 #pragma unroll
@@ -396,7 +530,7 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
 }
 
 // ------------------------------------------------------------------ host side
-template <typename T, typename A, typename VT, int NR>
+template <typename TD, typename TL, typename A, typename VT, int NR>
 static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool transposed,
                      hipStream_t s) {
   A* z = static_cast<A*>(P.z);
@@ -410,26 +544,26 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
     if (P.nlr > 0) {
-      k_fwd1<T, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n);
+      k_fwd1<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
       HM_LAUNCH_CHECK();
     }
     if (pr) {
       HM_HIP(hipEventRecord(pr->ev[2], s));
       HM_HIP(hipEventRecord(pr->ev[3], s));
     }
-    k_fwd2<T, A, VT, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, P.colmap, z, P.perm, y, nrhs,
-                                             k0);
+    k_fwd2<TD, TL, A, VT, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, P.colmap, z, P.perm, y,
+                                                  nrhs, k0);
     HM_LAUNCH_CHECK();
   } else {
-    k_tr1<T, A, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, z, w);
+    k_tr1<TD, TL, A, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, z, w);
     HM_LAUNCH_CHECK();
     if (pr) HM_HIP(hipEventRecord(pr->ev[2], s));
     if (P.nlr > 0) {
-      k_tr_sums<A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.ucol, w, z, P.n);
+      k_tr_sums<A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.ucol, w, z, P.n, P.su);
       HM_LAUNCH_CHECK();
     }
     if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
-    k_tr2<T, A, VT, NR><<<gl, 256, 0, s>>>(P.tbeg, P.titems, P.L, w, z, P.n, P.perm, y, nrhs, k0);
+    k_tr2<TL, A, VT, NR><<<gl, 256, 0, s>>>(P.tbeg, P.titems, P.L, w, z, P.n, P.perm, y, nrhs, k0);
     HM_LAUNCH_CHECK();
   }
   if (pr) {
@@ -445,42 +579,56 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   }
 }
 
-template <typename T, typename A, typename VT>
+template <typename TD, typename TL, typename A, typename VT>
 void matvec_impl(const MvPlan& P, const VT* x, VT* y, int nrhs, bool transposed, hipStream_t s) {
   const int cap = transposed ? P.max_nr_t : 16;
   int k0 = 0;
   while (k0 < nrhs) {
     const int left = nrhs - k0;
     if (left >= 16 && cap >= 16) {
-      mv_chunk<T, A, VT, 16>(P, x, y, nrhs, k0, transposed, s);
+      mv_chunk<TD, TL, A, VT, 16>(P, x, y, nrhs, k0, transposed, s);
       k0 += 16;
     } else if (left >= 8 && cap >= 8) {
-      mv_chunk<T, A, VT, 8>(P, x, y, nrhs, k0, transposed, s);
+      mv_chunk<TD, TL, A, VT, 8>(P, x, y, nrhs, k0, transposed, s);
       k0 += 8;
     } else if (left >= 4 && cap >= 4) {
-      mv_chunk<T, A, VT, 4>(P, x, y, nrhs, k0, transposed, s);
+      mv_chunk<TD, TL, A, VT, 4>(P, x, y, nrhs, k0, transposed, s);
       k0 += 4;
     } else if (left >= 2 && cap >= 2) {
-      mv_chunk<T, A, VT, 2>(P, x, y, nrhs, k0, transposed, s);
+      mv_chunk<TD, TL, A, VT, 2>(P, x, y, nrhs, k0, transposed, s);
       k0 += 2;
     } else {
-      mv_chunk<T, A, VT, 1>(P, x, y, nrhs, k0, transposed, s);
+      mv_chunk<TD, TL, A, VT, 1>(P, x, y, nrhs, k0, transposed, s);
       k0 += 1;
     }
   }
 }
 
-// storage T, vectors VT; accumulation in double unless both are float
-void matvec_dispatch(const MvPlan& P, int storage_f32, const void* x, void* y, int nrhs, int vec_f32,
+// storage 0: FP64, 1: FP32, 2: FP32 dense + FP16 factors.  Vectors VT;
+// accumulation in double unless the storage and the vectors are single
+// precision.
+void matvec_dispatch(const MvPlan& P, int storage, const void* x, void* y, int nrhs, int vec_f32,
                      bool transposed, hipStream_t s) {
-  if (storage_f32 && vec_f32)
-    matvec_impl<float, float, float>(P, (const float*)x, (float*)y, nrhs, transposed, s);
-  else if (storage_f32 && !vec_f32)
-    matvec_impl<float, double, double>(P, (const double*)x, (double*)y, nrhs, transposed, s);
-  else if (!storage_f32 && vec_f32)
-    matvec_impl<double, double, float>(P, (const float*)x, (float*)y, nrhs, transposed, s);
-  else
-    matvec_impl<double, double, double>(P, (const double*)x, (double*)y, nrhs, transposed, s);
+  if (storage == 2) {
+    if (vec_f32)
+      matvec_impl<float, _Float16, float, float>(P, (const float*)x, (float*)y, nrhs, transposed, s);
+    else
+      matvec_impl<float, _Float16, double, double>(P, (const double*)x, (double*)y, nrhs,
+                                                    transposed, s);
+  } else if (storage == 1) {
+    if (vec_f32)
+      matvec_impl<float, float, float, float>(P, (const float*)x, (float*)y, nrhs, transposed, s);
+    else
+      matvec_impl<float, float, double, double>(P, (const double*)x, (double*)y, nrhs, transposed,
+                                                s);
+  } else {
+    if (vec_f32)
+      matvec_impl<double, double, double, float>(P, (const float*)x, (float*)y, nrhs, transposed,
+                                                 s);
+    else
+      matvec_impl<double, double, double, double>(P, (const double*)x, (double*)y, nrhs,
+                                                  transposed, s);
+  }
 }
 
 }  // namespace hm

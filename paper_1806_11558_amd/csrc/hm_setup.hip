@@ -13,6 +13,7 @@
 //   first phase t = V^T x.
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "hm_internal.h"
 
@@ -126,42 +127,87 @@ __global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restri
 }
 
 // ------------------------------------------------------------------ ACA
-// Reductions over a wavefront.  argmax keys: larger key wins, ties go to the
-// smaller index; the signed value travels with its key.
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
+// ---- wavefront primitives (gfx9 DPP).  The row-of-16 butterfly (quad
+// permutes, half mirror, mirror) followed by the two row broadcasts leaves
+// the full result in lane 63; readlane makes it uniform.  Masked rows of a
+// DPP move read 0.
+template <int CTRL, int ROWMASK>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xF, false);
+}
+__device__ inline int rdl_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+template <int C, int RM>
+__device__ inline float dpp_v(float v) {
+  return __int_as_float(dpp_i<C, RM>(__float_as_int(v)));
+}
+template <int C, int RM>
+__device__ inline double dpp_v(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_i<C, RM>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_i<C, RM>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ inline float rdl_v(float v, int l) { return __int_as_float(rdl_i(__float_as_int(v), l)); }
+__device__ inline double rdl_v(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)rdl_i((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)rdl_i((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-template <typename T>
-struct ArgMax {
-  T key;
-  int idx;
-  T val;
+// Sum over the wavefront, uniform result, fixed order.
+template <typename A>
+__device__ inline A wsum(A v) {
+  v += dpp_v<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_v<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_v<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_v<0x140, 0xF>(v);   // row_mirror
+  v += dpp_v<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_v<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return rdl_v(v, 63);
+}
+
+// Pivot search: key = bit pattern of |value| (monotone for non-negative
+// floats), larger key wins, ties go to the smaller index (stored as ~index,
+// larger wins).  {0, 0} is the "no candidate" sentinel and loses to every
+// real candidate, including a zero value.
+struct Piv {
+  unsigned long long k;
+  unsigned ni;
 };
-
-template <typename T>
-__device__ inline void argmax_merge(ArgMax<T>& a, const ArgMax<T>& b) {
-  if (b.key > a.key || (b.key == a.key && b.idx < a.idx)) a = b;
+__device__ inline unsigned long long key_bits(float a) { return (unsigned)__float_as_int(a); }
+__device__ inline unsigned long long key_bits(double a) {
+  return (unsigned long long)__double_as_longlong(a);
 }
-
-// The result is taken from lane 0 so that every lane holds the same value
-// even when a key is NaN (NaN keys never win a comparison).
-template <typename T>
-__device__ inline ArgMax<T> wave_argmax(ArgMax<T> a) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) {
-    ArgMax<T> b;
-    b.key = __shfl_xor(a.key, d, 64);
-    b.idx = __shfl_xor(a.idx, d, 64);
-    b.val = __shfl_xor(a.val, d, 64);
-    argmax_merge(a, b);
+__device__ inline void piv_merge(Piv& a, unsigned long long k, unsigned ni) {
+  if (k > a.k || (k == a.k && ni > a.ni)) {
+    a.k = k;
+    a.ni = ni;
   }
-  a.key = __shfl(a.key, 0, 64);
-  a.idx = __shfl(a.idx, 0, 64);
-  a.val = __shfl(a.val, 0, 64);
-  return a;
+}
+template <int C, int RM>
+__device__ inline void piv_step(Piv& a) {
+  const unsigned lo = (unsigned)dpp_i<C, RM>((int)(unsigned)a.k);
+  const unsigned hi = (unsigned)dpp_i<C, RM>((int)(unsigned)(a.k >> 32));
+  const unsigned ni = (unsigned)dpp_i<C, RM>((int)a.ni);
+  piv_merge(a, ((unsigned long long)hi << 32) | lo, ni);
+}
+__device__ inline Piv wpiv(Piv a) {
+  piv_step<0xB1, 0xF>(a);
+  piv_step<0x4E, 0xF>(a);
+  piv_step<0x141, 0xF>(a);
+  piv_step<0x140, 0xF>(a);
+  piv_step<0x142, 0xA>(a);
+  piv_step<0x143, 0xC>(a);
+  Piv r;
+  r.k = ((unsigned long long)(unsigned)rdl_i((int)(unsigned)(a.k >> 32), 63) << 32) |
+        (unsigned)rdl_i((int)(unsigned)a.k, 63);
+  r.ni = (unsigned)rdl_i((int)a.ni, 63);
+  return r;
+}
+// index of the winner, or -1 when there was no candidate
+__device__ inline int piv_index(const Piv& p) {
+  return (p.k == 0 && p.ni == 0) ? -1 : (int)(~p.ni);
 }
 
 template <typename T>
@@ -172,10 +218,8 @@ struct AcaArgs {
   const int64_t* slot;   // element offset of every block's working slot in pool
   int64_t slot0;         // slot offset of the chunk's first block (pool[0])
   T* pool;
-  const int32_t* big;    // blocks handled by a whole workgroup
-  int64_t nbig;
-  const int32_t* small;  // blocks handled by one wavefront each (m, n <= 64)
-  int64_t nsmall;
+  const int32_t* list[4];  // blocks of class 0 (workgroup), 1..3 (wavefront, Q = 4, 2, 1)
+  int64_t cnt[4];
   int kmax;
   double eps;
   int32_t* rank;         // out: rank per block
@@ -188,11 +232,23 @@ __device__ inline bool aca_stop(double uu, double vv, double s2, double eps) {
   return sqrt(uu) * sqrt(vv) <= eps * sqrt(fmax(s2, 0.0));
 }
 
-// One block per wavefront; lane k owns row k and column k (m, n <= 64).
-// The working factors live in the block's slot: U column-major m x kcap,
-// then V n x kcap.  Every lane only touches its own row / column of them;
-// values of other lanes arrive by shuffles.
-template <typename T>
+template <typename X, int Q>
+__device__ inline X pick(const X (&a)[Q], int q) {
+  X v = a[0];
+#pragma unroll
+  for (int k = 1; k < Q; ++k)
+    if (q == k) v = a[k];
+  return v;
+}
+
+// One block per wavefront (m, n <= 64 Q).  Lane L owns rows and columns
+// L + 64 q, q < Q.  The working factors live in the block's slot: U
+// column-major m x kcap, then V n x kcap; a lane only reads and writes its
+// own rows / columns of them, other lanes' values arrive by readlane.
+constexpr int kAcaThreads = 256;
+constexpr int kAcaWaves = kAcaThreads / 64;
+
+template <typename T, int Q>
 __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   const int lane = threadIdx.x & 63;
   const int2 ts = A.blk[b];
@@ -202,70 +258,116 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   T* U = A.pool + (A.slot[b] - A.slot0);
   T* V = U + (int64_t)kcap * m;
   const Geom<T>& g = A.g;
-  const bool has_row = lane < m, has_col = lane < n;
-
-  Src<T> my_src;
-  if (has_col) load_src(g, c0 + lane, my_src);
-  double my_x = 0, my_y = 0, my_z = 0;
-  if (has_row) {
-    my_x = g.c[r0 + lane];
-    my_y = g.c[g.n + r0 + lane];
-    my_z = g.c[2 * g.n + r0 + lane];
+  bool hr[Q], hc[Q], used[Q];
+  double px[Q], py[Q], pz[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = lane + 64 * q;
+    hr[q] = i < m;
+    hc[q] = i < n;
+    used[q] = false;
+    px[q] = hr[q] ? g.c[r0 + i] : 0.0;
+    py[q] = hr[q] ? g.c[g.n + r0 + i] : 0.0;
+    pz[q] = hr[q] ? g.c[2 * g.n + r0 + i] : 0.0;
   }
-  bool used = false;
   int nused = 0, r = 0, istar = 0, rows_eval = 0;
   double s2 = 0.0;
   bool cap_hit = false;
   while (true) {
-    // residual row v~ = a(i*, :) - sum_l u_l[i*] v_l
-    const double xi = __shfl(my_x, istar, 64), yi = __shfl(my_y, istar, 64),
-                 zi = __shfl(my_z, istar, 64);
-    T val = 0;
-    if (has_col) val = eval_entry(xi, yi, zi, r0 + istar, my_src, c0 + lane);
+    const int iq = istar >> 6, il = istar & 63;
+    const double xi = rdl_v(pick(px, iq), il), yi = rdl_v(pick(py, iq), il),
+                 zi = rdl_v(pick(pz, iq), il);
+    // residual row  v~ = a(i*, :) - sum_l u_l[i*] v_l
+    T val[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      val[q] = 0;
+      if (hc[q]) {
+        Src<T> s;
+        load_src(g, c0 + lane + 64 * q, s);
+        val[q] = eval_entry(xi, yi, zi, r0 + istar, s, c0 + lane + 64 * q);
+      }
+    }
     for (int l = 0; l < r; ++l) {
-      const T ul = has_row ? U[(int64_t)l * m + lane] : (T)0;
-      const T ui = __shfl(ul, istar, 64);
-      if (has_col) val -= ui * V[(int64_t)l * n + lane];
+      const T own = (lane + 64 * iq < m) ? U[(int64_t)l * m + lane + 64 * iq] : (T)0;
+      const T ui = rdl_v(own, il);
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (hc[q]) val[q] -= ui * V[(int64_t)l * n + lane + 64 * q];
     }
     ++rows_eval;
-    if (lane == istar) used = true;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (q == iq && lane == il) used[q] = true;
     ++nused;
-    ArgMax<T> am{has_col ? (T)fabs(val) : (T)-1, has_col ? lane : 1 << 30, has_col ? val : (T)0};
-    am = wave_argmax(am);
-    if (am.val == (T)0 || am.idx < 0 || am.idx >= n) {
+    Piv pv{0, 0};
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (hc[q]) piv_merge(pv, key_bits((T)fabs(val[q])), ~(unsigned)(lane + 64 * q));
+    const int jstar = piv_index(wpiv(pv));
+    T delta = 0;
+    if (jstar >= 0 && jstar < n) delta = rdl_v(pick(val, jstar >> 6), jstar & 63);
+    if (delta == (T)0) {
       if (nused >= m) break;
-      ArgMax<T> nx{(T)-1, 1 << 30, (T)0};
-      if (has_row && !used) {
-        nx.key = (r > 0) ? (T)fabs(U[(int64_t)(r - 1) * m + lane]) : (T)0;
-        nx.idx = lane;
-      }
-      istar = wave_argmax(nx).idx;
+      Piv nx{0, 0};
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (hr[q] && !used[q]) {
+          const T k = (r > 0) ? (T)fabs(U[(int64_t)(r - 1) * m + lane + 64 * q]) : (T)0;
+          piv_merge(nx, key_bits(k), ~(unsigned)(lane + 64 * q));
+        }
+      istar = piv_index(wpiv(nx));
       if (istar < 0 || istar >= m) break;
       continue;
     }
-    const int jstar = am.idx;
-    const T v = has_col ? val / am.val : (T)0;
-    if (has_col) V[(int64_t)r * n + lane] = v;
-    // residual column u = a(:, j*) - sum_l v_l[j*] u_l
+    T v[Q];
+    double vv = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      v[q] = hc[q] ? val[q] / delta : (T)0;
+      if (hc[q]) V[(int64_t)r * n + lane + 64 * q] = v[q];
+      vv += (double)v[q] * (double)v[q];
+    }
+    // residual column  u = a(:, j*) - sum_l v_l[j*] u_l.  The cross terms of
+    // |S_r|_F^2, sum_l (u_l . u)(v_l . v), equal u . w with w = sum_l u_l
+    // (v_l . v), accumulated in the same pass over the previous terms.
+    const int jq = jstar >> 6, jl = jstar & 63;
     Src<T> s;
     load_src(g, c0 + jstar, s);
-    T u = 0;
-    if (has_row) u = eval_entry(my_x, my_y, my_z, r0 + lane, s, c0 + jstar);
-    for (int l = 0; l < r; ++l) {
-      const T vl = has_col ? V[(int64_t)l * n + lane] : (T)0;
-      const T vj = __shfl(vl, jstar, 64);
-      if (has_row) u -= vj * U[(int64_t)l * m + lane];
+    T u[Q];
+    double wv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      u[q] = hr[q] ? eval_entry(px[q], py[q], pz[q], r0 + lane + 64 * q, s, c0 + jstar) : (T)0;
+      wv[q] = 0.0;
     }
-    if (has_row) U[(int64_t)r * m + lane] = u;
-    // |S_r|_F^2 update
-    double cross = 0.0;
     for (int l = 0; l < r; ++l) {
-      const double pu = has_row ? (double)U[(int64_t)l * m + lane] * (double)u : 0.0;
-      const double pv = has_col ? (double)V[(int64_t)l * n + lane] * (double)v : 0.0;
-      cross += wave_sum(pu) * wave_sum(pv);
+      T vo[Q];
+      double pvl = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        vo[q] = hc[q] ? V[(int64_t)l * n + lane + 64 * q] : (T)0;
+        pvl += (double)vo[q] * (double)v[q];
+      }
+      const T vj = rdl_v(pick(vo, jq), jl);
+      const double dv = wsum(pvl);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const T ul = hr[q] ? U[(int64_t)l * m + lane + 64 * q] : (T)0;
+        u[q] -= vj * ul;
+        wv[q] += dv * (double)ul;
+      }
     }
-    const double uu = wave_sum((double)u * (double)u);
-    const double vv = wave_sum((double)v * (double)v);
+    double uu = 0.0, cw = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (hr[q]) U[(int64_t)r * m + lane + 64 * q] = u[q];
+      uu += (double)u[q] * (double)u[q];
+      cw += (double)u[q] * wv[q];
+    }
+    const double cross = wsum(cw);
+    uu = wsum(uu);
+    vv = wsum(vv);
     s2 += 2.0 * cross + uu * vv;
     ++r;
     if (aca_stop(uu, vv, s2, A.eps)) break;
@@ -274,12 +376,11 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
       break;
     }
     if (nused >= m) break;
-    ArgMax<T> nx{(T)-1, 1 << 30, (T)0};
-    if (has_row && !used) {
-      nx.key = (T)fabs(u);
-      nx.idx = lane;
-    }
-    istar = wave_argmax(nx).idx;
+    Piv nx{0, 0};
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (hr[q] && !used[q]) piv_merge(nx, key_bits((T)fabs(u[q])), ~(unsigned)(lane + 64 * q));
+    istar = piv_index(wpiv(nx));
     if (istar < 0 || istar >= m) break;
   }
   if (lane == 0) {
@@ -288,35 +389,32 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   }
 }
 
-// One block per workgroup of 256 threads.  Cross-thread reads of the working
-// factors happen only after a barrier.  The used-row flags are bytes placed
-// after V in the slot.
-constexpr int kAcaThreads = 256;
-constexpr int kAcaWaves = kAcaThreads / 64;
-
+// One block per workgroup of 256 threads (blocks larger than the wavefront
+// classes).  Cross-thread reads of the working factors happen only after a
+// barrier.  The used-row flags are bytes placed after V in the slot.
 template <typename T>
 struct AcaShared {
   T a[kMaxRank];             // u_l[i*] or v_l[j*] of the previous terms
-  double du[kMaxRank][kAcaWaves], dv[kMaxRank][kAcaWaves];
-  ArgMax<T> am[kAcaWaves];
+  double dv[kMaxRank][kAcaWaves];  // per-wave partial dots v_l . v_r
+  double dt[kMaxRank];             // their totals
+  Piv pv[kAcaWaves];
   double red[3][kAcaWaves];
-  ArgMax<T> am_out;
+  Piv pv_out;
   double out[3];
 };
 
-template <typename T>
-__device__ ArgMax<T> wg_argmax(ArgMax<T> a, AcaShared<T>& sh) {
+__device__ inline Piv wg_piv(Piv a, Piv* lds, Piv* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  a = wave_argmax(a);
-  if (lane == 0) sh.am[wave] = a;
+  a = wpiv(a);
+  if (lane == 0) lds[wave] = a;
   __syncthreads();
   if (threadIdx.x == 0) {
-    ArgMax<T> r = sh.am[0];
-    for (int w = 1; w < kAcaWaves; ++w) argmax_merge(r, sh.am[w]);
-    sh.am_out = r;
+    Piv r = lds[0];
+    for (int w = 1; w < kAcaWaves; ++w) piv_merge(r, lds[w].k, lds[w].ni);
+    *out = r;
   }
   __syncthreads();
-  ArgMax<T> r = sh.am_out;
+  Piv r = *out;
   __syncthreads();
   return r;
 }
@@ -341,110 +439,107 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     if (tid < r) sh.a[tid] = U[(int64_t)tid * m + istar];
     __syncthreads();
     const double xi = g.c[r0 + istar], yi = g.c[g.n + r0 + istar], zi = g.c[2 * g.n + r0 + istar];
-    ArgMax<T> am{(T)-1, 1 << 30, (T)0};
+    Piv pv{0, 0};
     for (int j = tid; j < n; j += kAcaThreads) {
       Src<T> s;
       load_src(g, c0 + j, s);
       T val = eval_entry(xi, yi, zi, r0 + istar, s, c0 + j);
       for (int l = 0; l < r; ++l) val -= sh.a[l] * V[(int64_t)l * n + j];
       V[(int64_t)r * n + j] = val;
-      const T k = (T)fabs(val);
-      if (k > am.key) am = ArgMax<T>{k, j, val};
+      piv_merge(pv, key_bits((T)fabs(val)), ~(unsigned)j);
     }
     if (tid == 0) used[istar] = 1;
     ++rows_eval;
     ++nused;
-    am = wg_argmax(am, sh);
-    if (am.val == (T)0 || am.idx < 0 || am.idx >= n) {
+    const int jstar = piv_index(wg_piv(pv, sh.pv, &sh.pv_out));
+    // every thread may read V[r][j*] now (barriers in wg_piv)
+    const T delta = (jstar >= 0 && jstar < n) ? V[(int64_t)r * n + jstar] : (T)0;
+    // every thread holds delta before the owner of j* overwrites that entry
+    __syncthreads();
+    if (delta == (T)0) {
       if (nused >= m) break;
-      ArgMax<T> nx{(T)-1, 1 << 30, (T)0};
+      Piv nx{0, 0};
       for (int i = tid; i < m; i += kAcaThreads) {
         if (used[i]) continue;
         const T k = (r > 0) ? (T)fabs(U[(int64_t)(r - 1) * m + i]) : (T)0;
-        if (k > nx.key) nx = ArgMax<T>{k, i, (T)0};
+        piv_merge(nx, key_bits(k), ~(unsigned)i);
       }
-      istar = wg_argmax(nx, sh).idx;
+      istar = piv_index(wg_piv(nx, sh.pv, &sh.pv_out));
       if (istar < 0 || istar >= m) break;
       continue;
     }
-    const int jstar = am.idx;
-    const T delta = am.val;
+    // v_r = v~ / delta, then the dots v_l . v_r of the previous terms.  Each
+    // thread reads back only the entries of v_r it wrote itself.
     double vv = 0.0;
     for (int j = tid; j < n; j += kAcaThreads) {
       const T v = V[(int64_t)r * n + j] / delta;
       V[(int64_t)r * n + j] = v;
       vv += (double)v * (double)v;
     }
+    for (int l = 0; l < r; ++l) {
+      double pvv = 0.0;
+      for (int j = tid; j < n; j += kAcaThreads)
+        pvv += (double)V[(int64_t)l * n + j] * (double)V[(int64_t)r * n + j];
+      pvv = wsum(pvv);
+      if (lane == 0) sh.dv[l][wave] = pvv;
+    }
     if (tid < r) sh.a[tid] = V[(int64_t)tid * n + jstar];
     __syncthreads();
-    Src<T> s;
-    load_src(g, c0 + jstar, s);
-    double uu = 0.0;
-    ArgMax<T> nx{(T)-1, 1 << 30, (T)0};
-    for (int i = tid; i < m; i += kAcaThreads) {
-      T u = eval_entry(g.c[r0 + i], g.c[g.n + r0 + i], g.c[2 * g.n + r0 + i], r0 + i, s, c0 + jstar);
-      for (int l = 0; l < r; ++l) u -= sh.a[l] * U[(int64_t)l * m + i];
-      U[(int64_t)r * m + i] = u;
-      uu += (double)u * (double)u;
-      if (!used[i]) {
-        const T k = (T)fabs(u);
-        if (k > nx.key) nx = ArgMax<T>{k, i, (T)0};
-      }
+    if (tid < r) {
+      double t = 0.0;
+      for (int w = 0; w < kAcaWaves; ++w) t += sh.dv[tid][w];
+      sh.dt[tid] = t;
     }
     __syncthreads();
-    // cross terms (u_l . u_r)(v_l . v_r) for l < r
-    for (int l = 0; l < r; ++l) {
-      double pu = 0.0, pv = 0.0;
-      for (int i = tid; i < m; i += kAcaThreads)
-        pu += (double)U[(int64_t)l * m + i] * (double)U[(int64_t)r * m + i];
-      for (int j = tid; j < n; j += kAcaThreads)
-        pv += (double)V[(int64_t)l * n + j] * (double)V[(int64_t)r * n + j];
-      pu = wave_sum(pu);
-      pv = wave_sum(pv);
-      if (lane == 0) {
-        sh.du[l][wave] = pu;
-        sh.dv[l][wave] = pv;
+    // residual column u_r; the cross terms sum_l (u_l . u_r)(v_l . v_r) are
+    // u_r . w with w = sum_l (v_l . v_r) u_l, built in the same pass.
+    Src<T> s;
+    load_src(g, c0 + jstar, s);
+    double uu = 0.0, cw = 0.0;
+    Piv nx{0, 0};
+    for (int i = tid; i < m; i += kAcaThreads) {
+      T u = eval_entry(g.c[r0 + i], g.c[g.n + r0 + i], g.c[2 * g.n + r0 + i], r0 + i, s, c0 + jstar);
+      double w = 0.0;
+      for (int l = 0; l < r; ++l) {
+        const T ul = U[(int64_t)l * m + i];
+        u -= sh.a[l] * ul;
+        w += sh.dt[l] * (double)ul;
       }
+      U[(int64_t)r * m + i] = u;
+      uu += (double)u * (double)u;
+      cw += (double)u * w;
+      if (!used[i]) piv_merge(nx, key_bits((T)fabs(u)), ~(unsigned)i);
     }
-    uu = wave_sum(uu);
-    vv = wave_sum(vv);
-    nx = wave_argmax(nx);
+    uu = wsum(uu);
+    vv = wsum(vv);
+    cw = wsum(cw);
+    nx = wpiv(nx);
     if (lane == 0) {
       sh.red[0][wave] = uu;
       sh.red[1][wave] = vv;
-      sh.am[wave] = nx;
+      sh.red[2][wave] = cw;
+      sh.pv[wave] = nx;
     }
     __syncthreads();
-    if (wave == 0) {
-      double c = 0.0;
-      for (int l = lane; l < r; l += 64) {
-        double a = 0.0, bb = 0.0;
-        for (int w = 0; w < kAcaWaves; ++w) {
-          a += sh.du[l][w];
-          bb += sh.dv[l][w];
-        }
-        c += a * bb;
+    if (tid == 0) {
+      double tu = 0.0, tv = 0.0, tc = 0.0;
+      Piv best = sh.pv[0];
+      for (int w = 0; w < kAcaWaves; ++w) {
+        tu += sh.red[0][w];
+        tv += sh.red[1][w];
+        tc += sh.red[2][w];
+        if (w) piv_merge(best, sh.pv[w].k, sh.pv[w].ni);
       }
-      c = wave_sum(c);
-      if (lane == 0) {
-        double tu = 0.0, tv = 0.0;
-        ArgMax<T> best = sh.am[0];
-        for (int w = 0; w < kAcaWaves; ++w) {
-          tu += sh.red[0][w];
-          tv += sh.red[1][w];
-          if (w) argmax_merge(best, sh.am[w]);
-        }
-        sh.out[0] = tu;
-        sh.out[1] = tv;
-        sh.out[2] = c;
-        sh.am_out = best;
-      }
+      sh.out[0] = tu;
+      sh.out[1] = tv;
+      sh.out[2] = tc;
+      sh.pv_out = best;
     }
     __syncthreads();
     uu = sh.out[0];
     vv = sh.out[1];
     const double cross = sh.out[2];
-    const int inext = sh.am_out.idx;
+    const int inext = piv_index(sh.pv_out);
     __syncthreads();
     s2 += 2.0 * cross + uu * vv;
     ++r;
@@ -463,46 +558,51 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
   }
 }
 
-// Task t < nbig: big block; otherwise four small blocks, one per wavefront.
+// Class 0: one block per workgroup (largest first).
 template <typename T>
-__global__ __launch_bounds__(kAcaThreads) void k_aca(AcaArgs<T> A) {
+__global__ __launch_bounds__(kAcaThreads, 4) void k_aca_wg(AcaArgs<T> A) {
   __shared__ AcaShared<T> sh;
-  const int64_t ntask = A.nbig + (A.nsmall + kAcaWaves - 1) / kAcaWaves;
-  for (int64_t t = blockIdx.x; t < ntask; t += gridDim.x) {
-    if (t < A.nbig) {
-      aca_wg(A, A.big[t], sh);
-      __syncthreads();
-    } else {
-      const int64_t k = (t - A.nbig) * kAcaWaves + (threadIdx.x >> 6);
-      if (k < A.nsmall) aca_wave(A, A.small[k]);
-    }
+  for (int64_t t = blockIdx.x; t < A.cnt[0]; t += gridDim.x) {
+    aca_wg(A, A.list[0][t], sh);
+    __syncthreads();
   }
 }
 
-// Working-slot size (elements) of every block and its workgroup/wavefront class.
-template <typename T>
-__global__ void k_aca_slots(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
-                            int kmax, int64_t* __restrict__ slot, int64_t* __restrict__ is_big) {
+// Classes 1..3: one block per wavefront, four per workgroup.
+template <typename T, int Q>
+__global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_aca_wave(AcaArgs<T> A) {
+  constexpr int c = Q == 4 ? 1 : (Q == 2 ? 2 : 3);
+  const int wave = threadIdx.x >> 6;
+  const int64_t ng = (A.cnt[c] + kAcaWaves - 1) / kAcaWaves;
+  for (int64_t t = blockIdx.x; t < ng; t += gridDim.x) {
+    const int64_t k = t * kAcaWaves + wave;
+    if (k < A.cnt[c]) aca_wave<T, Q>(A, A.list[c][k]);
+  }
+}
+
+// Class of every block: 0 workgroup (max(m, n) > 256), 1 wavefront with
+// Q = 4, 2 with Q = 2, 3 with Q = 1; flags[c * nb + b] = (class == c).
+__global__ void k_aca_classes(const int2* __restrict__ blk, int64_t nb,
+                              const Cluster* __restrict__ cl, int64_t* __restrict__ flags) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
     const Cluster t = cl[ts.x], s = cl[ts.y];
-    const int64_t m = t.y - t.x, n = s.y - s.x;
-    const int64_t kcap = min((int64_t)kmax, min(m, n));
-    const int64_t flag_elems = (m + (int64_t)sizeof(T) - 1) / (int64_t)sizeof(T);
-    slot[b] = ((kcap * (m + n) + flag_elems) + 3) & ~(int64_t)3;
-    is_big[b] = (m > 64 || n > 64) ? 1 : 0;
+    const int64_t mx = max(t.y - t.x, s.y - s.x);
+    const int c = mx > 256 ? 0 : (mx > 128 ? 1 : (mx > 64 ? 2 : 3));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) flags[k * nb + b] = (k == c) ? 1 : 0;
   }
 }
 
-__global__ void k_split_lists(const int64_t* __restrict__ is_big, const int64_t* __restrict__ ob,
-                              int64_t nb, int32_t* __restrict__ big, int32_t* __restrict__ small) {
+// list_c[offs_c[b]] = b for the class c of block b.
+__global__ void k_split_lists(const int64_t* __restrict__ flags, const int64_t* __restrict__ offs,
+                              int64_t nb, int32_t* __restrict__ lists) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
-    if (is_big[b])
-      big[ob[b]] = (int32_t)b;
-    else
-      small[b - ob[b]] = (int32_t)b;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (flags[k * nb + b]) lists[k * nb + offs[k * nb + b]] = (int32_t)b;
   }
 }
 
@@ -619,8 +719,9 @@ __global__ void k_runs(const int64_t* __restrict__ col0, const int64_t* __restri
 
 // ------------------------------------------------------------------ packing
 // U slice of every sorted U item: the rows of leaf lf of block b, ld x r
-// column-major, at its place in the leaf panel.
-template <typename T>
+// column-major, at its place in the leaf panel, converted to the factor
+// storage type TL (divided by the term's scale when su is given).
+template <typename T, typename TL>
 __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx,
                                                 const int32_t* __restrict__ ib,
                                                 const int32_t* __restrict__ ilf, int64_t np,
@@ -628,36 +729,65 @@ __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx
                                                 const Cluster* __restrict__ cl, LeafTab L,
                                                 const int32_t* __restrict__ rank,
                                                 const int64_t* __restrict__ slot, int64_t slot0,
-                                                const T* __restrict__ pool, int kmax,
+                                                const T* __restrict__ pool,
                                                 const int64_t* __restrict__ offI,
-                                                T* __restrict__ arena) {
+                                                const float* __restrict__ su,
+                                                const int64_t* __restrict__ toff, int64_t tbase,
+                                                TL* __restrict__ arena) {
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     const int32_t u = sidx[p];
     const int b = ib[u], lf = ilf[u];
     const int2 ts = blk[b];
-    const Cluster tau = cl[ts.x], sig = cl[ts.y];
-    const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
-    const int kcap = min(kmax, min(m, n));
+    const Cluster tau = cl[ts.x];
+    const int m = tau.y - tau.x, r = rank[b];
     const T* U = pool + (slot[b] - slot0);
     const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - tau.x;
-    T* d = arena + offI[p];
+    TL* d = arena + offI[p];
     for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
       const int i = e % ld, l = e / ld;
-      d[e] = (i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
+      T v = (i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
+      if (su) v = v / (T)su[tbase + toff[b] + l];
+      d[e] = (TL)v;
     }
-    (void)kcap;
   }
 }
 
-// V factor of every block, contiguous: its column-leaf slices in leaf order.
+// Per-term scale of the U factors stored in FP16: max_i |U[i][l]| (1 for a
+// zero column).  One wavefront per block.
 template <typename T>
+__global__ __launch_bounds__(256) void k_u_scales(const int2* __restrict__ blk, int64_t nb,
+                                                  const Cluster* __restrict__ cl,
+                                                  const int32_t* __restrict__ rank,
+                                                  const int64_t* __restrict__ slot, int64_t slot0,
+                                                  const T* __restrict__ pool,
+                                                  const int64_t* __restrict__ toff, int64_t tbase,
+                                                  float* __restrict__ su) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += nw) {
+    const Cluster tau = cl[blk[b].x];
+    const int m = tau.y - tau.x, r = rank[b];
+    const T* U = pool + (slot[b] - slot0);
+    for (int l = 0; l < r; ++l) {
+      float mx = 0.f;
+      for (int i = lane; i < m; i += 64) mx = fmaxf(mx, fabsf((float)U[(int64_t)l * m + i]));
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, 64));
+      if (lane == 0) su[tbase + toff[b] + l] = mx > 0.f ? mx : 1.f;
+    }
+  }
+}
+
+// V factor of every block, contiguous: its column-leaf slices in leaf order,
+// converted to TL (|v| <= 1 by the pivot normalisation, so no scale).
+template <typename T, typename TL>
 __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, int64_t nb,
                                                 const Cluster* __restrict__ cl, LeafTab L,
                                                 const int32_t* __restrict__ rank,
                                                 const int64_t* __restrict__ slot, int64_t slot0,
                                                 const T* __restrict__ pool, int kmax,
                                                 const int64_t* __restrict__ voff,
-                                                T* __restrict__ varena,
+                                                TL* __restrict__ varena,
                                                 uint64_t* __restrict__ vptr) {
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const int2 ts = blk[b];
@@ -665,15 +795,15 @@ __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, in
     const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
     const int kcap = min(kmax, min(m, n));
     const T* Vw = pool + (slot[b] - slot0) + (int64_t)kcap * m;
-    T* dst = varena + voff[b];
+    TL* dst = varena + voff[b];
     if (threadIdx.x == 0) vptr[b] = (uint64_t)(uintptr_t)dst;
     const int2 ls = L.cl_leaves[ts.y];
     for (int lf = ls.x; lf <= ls.y; ++lf) {
       const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - sig.x;
-      T* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
+      TL* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
       for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
         const int i = e % ld, l = e / ld;
-        d[e] = (i < ml) ? Vw[(int64_t)l * n + off + i] : (T)0;
+        d[e] = (TL)((i < ml) ? Vw[(int64_t)l * n + off + i] : (T)0);
       }
     }
   }
@@ -708,9 +838,10 @@ __global__ void k_urec(const int32_t* __restrict__ sidx, const int32_t* __restri
 }
 
 __global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* __restrict__ cl_leaves,
-                          const int32_t* __restrict__ rank, const int64_t* __restrict__ toff,
-                          int64_t toff_base, const uint64_t* __restrict__ vptr,
-                          const int64_t* __restrict__ ub, LrMeta* __restrict__ meta) {
+                          const int64_t* __restrict__ ldpre, const int32_t* __restrict__ rank,
+                          const int64_t* __restrict__ toff, int64_t toff_base,
+                          const uint64_t* __restrict__ vptr, const int64_t* __restrict__ ub,
+                          LrMeta* __restrict__ meta) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
@@ -724,6 +855,11 @@ __global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* 
     M.tf = lt.x;
     M.tl = lt.y;
     M.ub = ub[b];
+    const int64_t ld0 = ldpre[ls.x + 1] - ldpre[ls.x];
+    bool uni = true;
+    for (int lf = ls.x + 1; lf <= ls.y && uni; ++lf) uni = (ldpre[lf + 1] - ldpre[lf]) == ld0;
+    M.vld = uni ? (int32_t)ld0 : 0;
+    M.pad = 0;
     meta[b] = M;
   }
 }
@@ -783,10 +919,17 @@ __global__ void k_gather_titems(const TItem* __restrict__ in, const int32_t* __r
     out[k] = in[idx[k]];
 }
 
-__global__ void k_leaf_counts(const uint64_t* __restrict__ keys, int64_t n, int64_t* __restrict__ cnt) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd((unsigned long long*)&cnt[keys[k]], 1ull);
+// beg[c] = first position p of the sorted keys with key[p] >= c, for
+// c = 0..nleaf (beg[nleaf] = n): each position fills the leaves between its
+// predecessor's key and its own.
+__global__ void k_seg_begins(const uint64_t* __restrict__ keys, int64_t n, int64_t nleaf,
+                             int64_t* __restrict__ beg) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p <= n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t prev = p > 0 ? (int64_t)keys[p - 1] : -1;
+    const int64_t cur = p < n ? (int64_t)keys[p] : nleaf;
+    for (int64_t c = prev + 1; c <= cur; ++c) beg[c] = p;
+  }
 }
 
 __global__ void k_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __restrict__ out) {
@@ -795,11 +938,13 @@ __global__ void k_to_i32(const int64_t* __restrict__ a, int64_t n, int32_t* __re
     out[e] = (int32_t)a[e];
 }
 
-// Unpack one factorised block back into plain column-major U (m x r), V (n x r).
-template <typename T>
+// Unpack one factorised block back into plain column-major U (m x r), V (n x r),
+// scales applied.
+template <typename TL, typename TO>
 __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* __restrict__ cl,
                          LeafTab L, const LrMeta* __restrict__ meta,
-                         const uint64_t* __restrict__ uptr, T* __restrict__ out) {
+                         const uint64_t* __restrict__ uptr, const float* __restrict__ su,
+                         TO* __restrict__ out) {
   const int2 ts = lr[b];
   const Cluster tau = cl[ts.x], sig = cl[ts.y];
   const LrMeta M = meta[b];
@@ -814,42 +959,84 @@ __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* 
     const int lf0 = isu ? M.tf : M.sf, lf1 = isu ? M.tl : M.sl;
     int lf = lf0;
     while (lf < lf1 && L.lo[lf + 1] <= pos) ++lf;
-    const T* sl;
+    const TL* sl;
     if (isu)
-      sl = reinterpret_cast<const T*>((uintptr_t)uptr[M.ub + (lf - lf0)]);
+      sl = reinterpret_cast<const TL*>((uintptr_t)uptr[M.ub + (lf - lf0)]);
     else
-      sl = reinterpret_cast<const T*>((uintptr_t)M.vptr) + (int64_t)r * (L.ldpre[lf] - L.ldpre[lf0]);
-    out[e] = sl[(int64_t)l * leaf_ld(L, lf) + (pos - L.lo[lf])];
+      sl = reinterpret_cast<const TL*>((uintptr_t)M.vptr) + (int64_t)r * (L.ldpre[lf] - L.ldpre[lf0]);
+    TO v = (TO)sl[(int64_t)l * leaf_ld(L, lf) + (pos - L.lo[lf])];
+    if (isu && su) v *= (TO)su[M.toff + l];
+    out[e] = v;
   }
 }
 
 // ------------------------------------------------------------------ ACA launchers
+// Runs the batched ACA on the blocks blk[0..nb): classes, task lists, one
+// launch.  flags, offs: 4 * nb int64 scratch; lists: 4 * nb int32 scratch.
 template <typename T>
-void launch_aca_slots(const int2* blk, int64_t nb, const Cluster* cl, int kmax, int64_t* slot,
-                      int64_t* is_big, hipStream_t s) {
-  k_aca_slots<T><<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, kmax, slot, is_big);
+void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl, const int64_t* slot,
+             int64_t slot0, T* pool, int kmax, double eps, int64_t* flags, int64_t* offs,
+             int32_t* lists, int32_t* rank, int32_t* info, int64_t* tmp, hipStream_t s) {
+  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, flags);
   HM_LAUNCH_CHECK();
-}
-
-void launch_split_lists(const int64_t* is_big, const int64_t* ob, int64_t nb, int32_t* big,
-                        int32_t* small, hipStream_t s) {
-  k_split_lists<<<grid_for(nb, 256), 256, 0, s>>>(is_big, ob, nb, big, small);
+  for (int k = 0; k < 4; ++k) scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
+  int64_t cnt[4];
+  HM_HIP(hipMemcpyAsync(cnt, tmp, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  k_split_lists<<<grid_for(nb, 256), 256, 0, s>>>(flags, offs, nb, lists);
   HM_LAUNCH_CHECK();
-}
-
-template <typename T>
-void launch_aca(const Geom<T>& g, const int2* blk, const Cluster* cl, const int64_t* slot,
-                int64_t slot0, T* pool, const int32_t* big, int64_t nbig, const int32_t* small,
-                int64_t nsmall, int kmax, double eps, int32_t* rank, int32_t* info, hipStream_t s) {
-  AcaArgs<T> A{g, blk, cl, slot, slot0, pool, big, nbig, small, nsmall, kmax, eps, rank, info};
-  const int64_t ntask = nbig + ceil_div(nsmall, kAcaWaves);
-  if (ntask == 0) return;
+  AcaArgs<T> A{g, blk, cl, slot, slot0, pool, {}, {}, kmax, eps, rank, info};
+  for (int k = 0; k < 4; ++k) {
+    A.list[k] = lists + k * nb;
+    A.cnt[k] = cnt[k];
+  }
   int dev = 0, ncu = 0;
   HM_HIP(hipGetDevice(&dev));
   HM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t grid = std::min<int64_t>(ntask, (int64_t)std::max(ncu, 1) * 16);
-  k_aca<T><<<(unsigned)grid, kAcaThreads, 0, s>>>(A);
-  HM_LAUNCH_CHECK();
+  const int64_t cap = (int64_t)std::max(ncu, 1) * 32;
+  // largest blocks first: one workgroup each, then the wavefront classes
+  if (cnt[0] > 0) {
+    k_aca_wg<T><<<(unsigned)std::min<int64_t>(cnt[0], cap), kAcaThreads, 0, s>>>(A);
+    HM_LAUNCH_CHECK();
+  }
+  if (cnt[1] > 0) {
+    k_aca_wave<T, 4><<<(unsigned)std::min<int64_t>(ceil_div(cnt[1], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    HM_LAUNCH_CHECK();
+  }
+  if (cnt[2] > 0) {
+    k_aca_wave<T, 2><<<(unsigned)std::min<int64_t>(ceil_div(cnt[2], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    HM_LAUNCH_CHECK();
+  }
+  if (cnt[3] > 0) {
+    k_aca_wave<T, 1><<<(unsigned)std::min<int64_t>(ceil_div(cnt[3], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    HM_LAUNCH_CHECK();
+  }
+}
+
+// Largest possible rank of every block: min(kmax, m, n).
+__global__ void k_term_caps(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
+                            int kmax, int64_t* __restrict__ kc) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = blk[b];
+    const Cluster t = cl[ts.x], s = cl[ts.y];
+    kc[b] = min((int64_t)kmax, (int64_t)min(t.y - t.x, s.y - s.x));
+  }
+}
+
+// Working-slot sizes of all blocks (the class flags are recomputed per chunk).
+template <typename T>
+__global__ void k_slot_sizes(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
+                             int kmax, int64_t* __restrict__ slot) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = blk[b];
+    const Cluster t = cl[ts.x], s = cl[ts.y];
+    const int64_t m = t.y - t.x, n = s.y - s.x;
+    const int64_t kcap = min((int64_t)kmax, min(m, n));
+    const int64_t flag_elems = (m + (int64_t)sizeof(T) - 1) / (int64_t)sizeof(T);
+    slot[b] = ((kcap * (m + n) + flag_elems) + 3) & ~(int64_t)3;
+  }
 }
 
 __global__ void k_widen_i32(const int32_t* __restrict__ a, int64_t n, int64_t* __restrict__ out) {
@@ -938,12 +1125,9 @@ void panel_layout(const int2* blk, int64_t nb, const Cluster* cl, const int2* cl
   k_item_width<<<grid_for(P.np, 256), 256, 0, s>>>(P.sidx, P.ib, P.np, blk, cl, rank, P.wid);
   HM_LAUNCH_CHECK();
   P.cols = scan_total(P.wid, P.gcol, P.np, tmp, s);
-  int64_t* lc = T.get<int64_t>(nleaf + 1);
   int64_t* ibeg = T.get<int64_t>(nleaf + 1);
-  HM_HIP(hipMemsetAsync(lc, 0, (nleaf + 1) * sizeof(int64_t), s));
-  k_leaf_counts<<<grid_for(P.np, 256), 256, 0, s>>>(key, P.np, lc);
+  k_seg_begins<<<grid_for(P.np + 1, 256), 256, 0, s>>>(key, P.np, nleaf, ibeg);
   HM_LAUNCH_CHECK();
-  scan_excl_i64(lc, ibeg, nleaf + 1, nullptr, s);
   P.col0 = T.get<int64_t>(nleaf);
   P.W = T.get<int64_t>(nleaf);
   int64_t* psize = T.get<int64_t>(nleaf);
@@ -960,11 +1144,13 @@ void panel_layout(const int2* blk, int64_t nb, const Cluster* cl, const int2* cl
 }
 }  // namespace
 
-template <typename T>
+template <typename T, typename TL>
 void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Alloc& alloc,
                    hipStream_t s) {
   const LeafTab L{in.leaf_lo, in.leaf_m, in.ldpre, in.cl_leaves};
   const int esize = (int)sizeof(T);
+  const int lsize = (int)sizeof(TL);
+  constexpr bool scaled = !std::is_same<T, TL>::value;
   const int64_t n = in.n, nleaf = in.nleaf;
   Temps keep{s, {}};       // lives until the product plan is complete
   int64_t* tmp = keep.get<int64_t>(4);
@@ -1031,8 +1217,8 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     Temps ta{s, {}};
     int64_t* slot = ta.get<int64_t>(nl);
     int64_t* slot_off = ta.get<int64_t>(nl + 1);
-    int64_t* isbig = ta.get<int64_t>(nl);
-    launch_aca_slots<T>(in.lr, nl, in.cl, kmax, slot, isbig, s);
+    k_slot_sizes<T><<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl, kmax, slot);
+    HM_LAUNCH_CHECK();
     scan_excl_i64(slot, slot_off, nl, slot_off + nl, s);
     std::vector<int64_t> hoff(nl + 1);
     HM_HIP(hipMemcpyAsync(hoff.data(), slot_off, (nl + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1042,9 +1228,18 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     for (int64_t b = 0; b < nl; ++b) maxslot = std::max(maxslot, hoff[b + 1] - hoff[b]);
     pool_elems = std::max(pool_elems, maxslot);
     T* pool = static_cast<T*>(dalloc((size_t)pool_elems * esize, s));
-    int64_t* ob = ta.get<int64_t>(nl + 1);
-    int32_t* big = ta.get<int32_t>(nl);
-    int32_t* small = ta.get<int32_t>(nl);
+    if (scaled) {
+      // at most min(kmax, m, n) terms per block
+      int64_t* kc = ta.get<int64_t>(nl);
+      int64_t* ko = ta.get<int64_t>(nl + 1);
+      k_term_caps<<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl, kmax, kc);
+      HM_LAUNCH_CHECK();
+      const int64_t maxterms = scan_total(kc, ko, nl, tmp, s);
+      out.su = static_cast<float*>(alloc((size_t)(maxterms + 1) * sizeof(float)));
+    }
+    int64_t* cflags = ta.get<int64_t>(4 * nl);
+    int64_t* coffs = ta.get<int64_t>(4 * nl);
+    int32_t* clists = ta.get<int32_t>(4 * nl);
     int64_t* toffc = ta.get<int64_t>(nl + 1);
     int64_t* rk64 = ta.get<int64_t>(nl);
     int64_t* vsz = ta.get<int64_t>(nl);
@@ -1056,10 +1251,8 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       int64_t b1 = b0 + 1;
       while (b1 < nl && hoff[b1 + 1] - hoff[b0] <= pool_elems) ++b1;
       const int64_t nb = b1 - b0;
-      const int64_t nbig = scan_total(isbig + b0, ob, nb, tmp, s);
-      launch_split_lists(isbig + b0, ob, nb, big, small, s);
-      launch_aca<T>(g, in.lr + b0, in.cl, slot_off + b0, hoff[b0], pool, big, nbig, small,
-                    nb - nbig, kmax, in.eps, out.rank + b0, out.info + b0, s);
+      run_aca<T>(g, in.lr + b0, nb, in.cl, slot_off + b0, hoff[b0], pool, kmax, in.eps, cflags,
+                 coffs, clists, out.rank + b0, out.info + b0, tmp, s);
       HM_HIP(hipStreamSynchronize(s));
       const auto tp = clk::now();
       // term offsets in t
@@ -1070,24 +1263,31 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       k_v_sizes<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, out.rank + b0, L, vsz);
       HM_LAUNCH_CHECK();
       const int64_t velems = scan_total(vsz, voff, nb, tmp, s);
-      T* varena = static_cast<T*>(alloc((size_t)velems * esize));
-      k_pack_v<T><<<grid_for(nb, 1, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
+      TL* varena = static_cast<TL*>(alloc((size_t)velems * lsize));
+      k_pack_v<T, TL><<<grid_for(nb, 1, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
                                                           slot_off + b0, hoff[b0], pool, kmax, voff,
                                                           varena, vptr);
       HM_LAUNCH_CHECK();
-      k_lr_meta<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, out.rank + b0,
-                                                  toffc, toff_base, vptr, ub + b0, out.meta + b0);
+      k_lr_meta<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, in.ldpre,
+                                                  out.rank + b0, toffc, toff_base, vptr, ub + b0,
+                                                  out.meta + b0);
       HM_LAUNCH_CHECK();
       // U slices in row-leaf panels
       Temps tu{s, {}};
       PanelSet PU;
       panel_layout(in.lr + b0, nb, in.cl, in.cl_leaves, in.ldpre, nleaf, out.rank + b0, oU, PU,
                    tu, tmp, s);
-      T* uarena = static_cast<T*>(alloc((size_t)PU.elems * esize));
+      TL* uarena = static_cast<TL*>(alloc((size_t)PU.elems * lsize));
+      if (scaled && nb > 0) {
+        k_u_scales<T><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(
+            in.lr + b0, nb, in.cl, out.rank + b0, slot_off + b0, hoff[b0], pool, toffc,
+            toff_base, out.su);
+        HM_LAUNCH_CHECK();
+      }
       if (PU.np > 0) {
-        k_pack_u<T><<<grid_for(PU.np, 1, 1 << 20), 256, 0, s>>>(
+        k_pack_u<T, TL><<<grid_for(PU.np, 1, 1 << 20), 256, 0, s>>>(
             PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0, in.cl, L, out.rank + b0, slot_off + b0,
-            hoff[b0], pool, kmax, PU.offI, uarena);
+            hoff[b0], pool, PU.offI, scaled ? out.su : nullptr, toffc, toff_base, uarena);
         HM_LAUNCH_CHECK();
       }
       const int64_t colbase = out.dense_cols + ucols;
@@ -1098,12 +1298,12 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       colmap_parts.push_back({cm, PU.cols});
       Run* rc = keep.get<Run>(nleaf);
       k_runs<<<grid_for(nleaf, 256), 256, 0, s>>>(PU.col0, PU.W, PU.poff, nleaf,
-                                                  (uint64_t)(uintptr_t)uarena, esize, colbase, rc);
+                                                  (uint64_t)(uintptr_t)uarena, lsize, colbase, rc);
       HM_LAUNCH_CHECK();
       run_parts.push_back(rc);
       k_urec<<<grid_for(PU.np, 256), 256, 0, s>>>(PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0,
                                                   in.cl_leaves, ub + b0, PU.gcol, colbase, PU.offI,
-                                                  (uint64_t)(uintptr_t)uarena, esize, out.ucol,
+                                                  (uint64_t)(uintptr_t)uarena, lsize, out.ucol,
                                                   out.uptr);
       HM_LAUNCH_CHECK();
       HM_HIP(hipStreamSynchronize(s));
@@ -1153,18 +1353,15 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     uint64_t* key = tt.get<uint64_t>(out.ntitems);
     int32_t* idx = tt.get<int32_t>(out.ntitems);
     k_titem_expand<<<grid_for(nb_all, 64), 64, 0, s>>>(in.dns, in.nd, nl, in.cl, L, off, invD, oD,
-                                                       gcolD, out.meta, esize, raw, key, idx);
+                                                       gcolD, out.meta, lsize, raw, key, idx);
     HM_LAUNCH_CHECK();
     radix_sort_u64_i32(key, idx, out.ntitems, bits_for(nleaf), s);
     out.titems = static_cast<TItem*>(alloc((out.ntitems + 1) * sizeof(TItem)));
     k_gather_titems<<<grid_for(out.ntitems, 256), 256, 0, s>>>(raw, idx, out.ntitems, out.titems);
     HM_LAUNCH_CHECK();
-    int64_t* lc = tt.get<int64_t>(nleaf + 1);
     int64_t* lb = tt.get<int64_t>(nleaf + 1);
-    HM_HIP(hipMemsetAsync(lc, 0, (nleaf + 1) * sizeof(int64_t), s));
-    k_leaf_counts<<<grid_for(out.ntitems, 256), 256, 0, s>>>(key, out.ntitems, lc);
+    k_seg_begins<<<grid_for(out.ntitems + 1, 256), 256, 0, s>>>(key, out.ntitems, nleaf, lb);
     HM_LAUNCH_CHECK();
-    scan_excl_i64(lc, lb, nleaf + 1, nullptr, s);
     out.tbeg = static_cast<int32_t*>(alloc((nleaf + 1) * sizeof(int32_t)));
     k_to_i32<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(lb, nleaf + 1, out.tbeg);
     HM_LAUNCH_CHECK();
@@ -1173,24 +1370,29 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   out.ms_pack = ms_pack + ms_since(t0);
   keep.release();
 }
-template void build_storage<float>(const Geom<float>&, const SetupIn&, Storage&, const Alloc&,
-                                   hipStream_t);
-template void build_storage<double>(const Geom<double>&, const SetupIn&, Storage&, const Alloc&,
-                                    hipStream_t);
+template void build_storage<float, float>(const Geom<float>&, const SetupIn&, Storage&,
+                                          const Alloc&, hipStream_t);
+template void build_storage<double, double>(const Geom<double>&, const SetupIn&, Storage&,
+                                            const Alloc&, hipStream_t);
+template void build_storage<float, _Float16>(const Geom<float>&, const SetupIn&, Storage&,
+                                             const Alloc&, hipStream_t);
 
-template <typename T>
+template <typename TL, typename TO>
 void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,
-                   const LrMeta* meta, const uint64_t* uptr, T* out, int64_t total, hipStream_t s) {
+                   const LrMeta* meta, const uint64_t* uptr, const float* su, TO* out,
+                   int64_t total, hipStream_t s) {
   LeafTab L{leaf_lo, leaf_m, ldpre, cl_leaves};
-  k_unpack<T><<<grid_for(total, 256), 256, 0, s>>>(lr, b, cl, L, meta, uptr, out);
+  k_unpack<TL, TO><<<grid_for(total, 256), 256, 0, s>>>(lr, b, cl, L, meta, uptr, su, out);
   HM_LAUNCH_CHECK();
 }
-template void launch_unpack<float>(const int2*, int64_t, const Cluster*, const int32_t*,
-                                   const int32_t*, const int64_t*, const int2*, const LrMeta*,
-                                   const uint64_t*, float*, int64_t, hipStream_t);
-template void launch_unpack<double>(const int2*, int64_t, const Cluster*, const int32_t*,
-                                    const int32_t*, const int64_t*, const int2*, const LrMeta*,
-                                    const uint64_t*, double*, int64_t, hipStream_t);
+#define HM_UNPACK(TL, TO)                                                                          \
+  template void launch_unpack<TL, TO>(const int2*, int64_t, const Cluster*, const int32_t*,        \
+                                      const int32_t*, const int64_t*, const int2*, const LrMeta*, \
+                                      const uint64_t*, const float*, TO*, int64_t, hipStream_t);
+HM_UNPACK(float, float)
+HM_UNPACK(double, double)
+HM_UNPACK(_Float16, float)
+#undef HM_UNPACK
 
 }  // namespace hm
