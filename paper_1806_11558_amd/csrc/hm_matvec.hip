@@ -105,6 +105,16 @@ __device__ inline A seg_sum(A v, int g, int R) {
   return v;
 }
 
+// Workgroup w runs on XCD w mod 8 (8 XCDs, each with its own L2).  Logical
+// index li -> item (li mod 8) * per + li / 8 gives every XCD a contiguous
+// range of leaves, so neighbouring leaves, which
+// gather mostly the same x and t values, share one L2.  A bijection of
+// [0, 8 per) onto itself; items >= the count are skipped.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_item(int64_t li, int64_t per) {
+  return (li % kXcds) * per + li / kXcds;
+}
+
 // ------------------------------------------------------------------ gather
 template <typename VT, typename A>
 __global__ void k_gather(const VT* __restrict__ x, int nrhs, int k0, int nr,
@@ -144,16 +154,21 @@ __device__ inline void fwd1_flush(A (&p)[NR], int g, int R, int j0, int C, int r
 }
 
 template <typename T, typename A, int NR>
-__global__ __launch_bounds__(256) void k_fwd1(const LrMeta* __restrict__ meta, int64_t nl,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_fwd1(const LrMeta* __restrict__ meta, int64_t nl,
                                               MvLeaves L, A* __restrict__ z, int64_t n,
                                               const float* __restrict__ su) {
   constexpr int G = Gran<T>::G;
   constexpr int PMAX = NR == 1 ? 4 : (NR <= 4 ? 2 : 1);
   const int lane = threadIdx.x & 63;
-  const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // wave-uniform block index: descriptors and leaf data come in by scalar loads
+  const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
+  // the next block's descriptor is loaded one iteration ahead
+  LrMeta Mn;
+  if (wid < nl) Mn = meta[wid];
   for (int64_t b = wid; b < nl; b += nw) {
-    const LrMeta M = meta[b];
+    const LrMeta M = Mn;
+    if (b + nw < nl) Mn = meta[b + nw];
     const int r = M.r;
     if (r == 0) continue;
     A tl[NR];
@@ -178,10 +193,15 @@ __global__ __launch_bounds__(256) void k_fwd1(const LrMeta* __restrict__ meta, i
         A xg[G][NR];
 #pragma unroll
         for (int e = 0; e < G; ++e) {
+          // unconditional load of a clamped row, zeroed outside the slice
           const int row = g * G + e;
+          const bool in = act && row < m;
+          const A* zr = z + (int64_t)(lo + (in ? row : 0)) * NR;
 #pragma unroll
-          for (int k = 0; k < NR; ++k)
-            xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
+          for (int k = 0; k < NR; ++k) {
+            const A v = zr[k];
+            xg[e][k] = in ? v : (A)0;
+          }
         }
 #pragma unroll
         for (int q = 0; q < PMAX; ++q) {
@@ -243,6 +263,77 @@ __global__ __launch_bounds__(256) void k_fwd1(const LrMeta* __restrict__ meta, i
   }
 }
 
+// Several right-hand sides (NR >= 4): lane = (term j, right-hand-side group
+// kg) with JG terms per pass and KPL = NR JG / 64 right-hand sides per lane,
+// so every lane owns complete sums and no cross-lane reduction is needed.
+// All lanes walk the same rows; a lane reads its term's granule (shared by the
+// lanes of other groups) and its KPL values of each x row.
+template <typename T, typename A, int NR, int JG>
+__device__ inline void fwd1m_block(const LrMeta& M, const MvLeaves& L, A* __restrict__ z,
+                                   int64_t n, const float* __restrict__ su, int lane) {
+  constexpr int G = Gran<T>::G;
+  constexpr int KPL = NR * JG / 64;
+  static_assert(KPL >= 1 && KPL * (64 / JG) == NR, "lane layout must cover NR");
+  const int r = M.r;
+  const int jl = lane % JG, k0 = (lane / JG) * KPL;
+  const A sc0 = (A)1;
+  for (int jp = 0; jp < r; jp += JG) {
+    const int j = jp + jl;
+    const bool ok = j < r;
+    const int jc = ok ? j : r - 1;
+    A acc[KPL];
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) acc[k] = 0;
+    const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
+    for (int lf = M.sf; lf <= M.sl; ++lf) {
+      const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+      const int m = L.m[lf], lo = L.lo[lf];
+      const T* col = S + (int64_t)jc * ld;
+      const A* zr = z + (int64_t)lo * NR + k0;
+      for (int i0 = 0; i0 < m; i0 += G) {
+        typename Gran<T>::E sv[G];
+        Gran<T>::load(col + i0, sv);
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+          if (i0 + e < m) {                              // uniform over the wavefront
+            A xv[KPL];
+            load_row<A, KPL>(zr + (int64_t)(i0 + e) * NR, xv);
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) acc[k] += (A)sv[e] * xv[k];
+          }
+        }
+      }
+      S += (int64_t)ld * r;
+    }
+    if (ok) {
+      const A sc = su ? (A)su[M.toff + j] : sc0;
+#pragma unroll
+      for (int k = 0; k < KPL; ++k) z[(n + M.toff + j) * NR + k0 + k] = acc[k] * sc;
+    }
+  }
+}
+
+template <typename T, typename A, int NR>
+__global__ __launch_bounds__(256) void k_fwd1m(const LrMeta* __restrict__ meta, int64_t nl,
+                                               MvLeaves L, A* __restrict__ z, int64_t n,
+                                               const float* __restrict__ su) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform block index: descriptors and leaf data come in by scalar loads
+  const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t b = wid; b < nl; b += nw) {
+    const LrMeta M = meta[b];
+    if (M.r == 0) continue;
+    if constexpr (NR >= 8) {
+      if (M.r <= 8) {
+        fwd1m_block<T, A, NR, 8>(M, L, z, n, su, lane);
+        continue;
+      }
+    }
+    fwd1m_block<T, A, NR, 16>(M, L, z, n, su, lane);
+  }
+}
+
 // ------------------------------------------------------------------ forward, phase 2
 // Per row leaf: y_c = sum over its panels of P z[colmap], then scattered to
 // application order.  Panel 0 of a leaf holds dense slices (type TD), the
@@ -295,7 +386,10 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int 
   constexpr int G = Gran<TD>::G;
   __shared__ A ybuf[4][kMaxLeaf][NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+  const int64_t per = (L.nleaf + kXcds - 1) / kXcds;
+  for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
+    const int64_t c = xcd_item(li, per);
+    if (c >= L.nleaf) continue;                         // uniform over the workgroup
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
     const int R = ld / G, C = 64 / R;
     const int cg = lane / R, g = lane % R;
@@ -387,7 +481,10 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, int n
                                              const A* __restrict__ z, A* __restrict__ w) {
   constexpr int G = Gran<TD>::G;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+  const int64_t per = (L.nleaf + kXcds - 1) / kXcds;
+  for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
+    const int64_t c = xcd_item(li, per);
+    if (c >= L.nleaf) continue;                         // uniform over the workgroup
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
     const int R = ld / G, C = 64 / R;
     const int cg = lane / R, g = lane % R;
@@ -424,7 +521,8 @@ __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta
                                                  const A* __restrict__ w, A* __restrict__ z,
                                                  int64_t n, const float* __restrict__ su) {
   const int lane = threadIdx.x & 63;
-  const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6);
+  // wave-uniform block index: descriptors and leaf data come in by scalar loads
+  const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
   for (int64_t b = wid; b < nl; b += nw) {
     const LrMeta M = meta[b];
@@ -456,7 +554,10 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
   constexpr int G = Gran<T>::G;
   __shared__ A ybuf[4][kMaxLeaf][NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+  const int64_t per = (L.nleaf + kXcds - 1) / kXcds;
+  for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
+    const int64_t c = xcd_item(li, per);
+    if (c >= L.nleaf) continue;                         // uniform over the workgroup
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
     const int R = ld / G, C = 64 / R;
     const int cg = lane / R, g = lane % R;
@@ -540,11 +641,18 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   k_gather<VT, A><<<grid_for(P.n * NR, 256, 4096), 256, 0, s>>>(x, nrhs, k0, NR, P.perm, P.n, z);
   HM_LAUNCH_CHECK();
   if (pr) HM_HIP(hipEventRecord(pr->ev[1], s));
-  const unsigned gl = (unsigned)std::min<int64_t>(P.L.nleaf, P.grid);
+  // leaves carry similar work: the per-leaf grids cover the XCD-ordered
+  // index range (a multiple of kXcds)
+  const unsigned gl = (unsigned)std::min<int64_t>(ceil_div(P.L.nleaf, kXcds) * kXcds, P.grid);
+  // blocks differ widely in size and come largest first, so they stay
+  // round-robin over the XCDs
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
     if (P.nlr > 0) {
-      k_fwd1<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
+      if constexpr (NR >= 4)
+        k_fwd1m<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
+      else
+        k_fwd1<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
       HM_LAUNCH_CHECK();
     }
     if (pr) {

@@ -572,7 +572,8 @@ __global__ __launch_bounds__(kAcaThreads, 4) void k_aca_wg(AcaArgs<T> A) {
 template <typename T, int Q>
 __global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_aca_wave(AcaArgs<T> A) {
   constexpr int c = Q == 4 ? 1 : (Q == 2 ? 2 : 3);
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform: the block's descriptors come in by scalar loads
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ng = (A.cnt[c] + kAcaWaves - 1) / kAcaWaves;
   for (int64_t t = blockIdx.x; t < ng; t += gridDim.x) {
     const int64_t k = t * kAcaWaves + wave;
