@@ -178,3 +178,36 @@ def test_edge_sizes(level, nsub, leaf):
     yT = H.matvec_T(torch.tensor(x, device=DEV)).cpu().numpy()
     assert rel2(y, A @ x) <= 1e-7 and rel2(yT, A.T @ x) <= 1e-7
     H.free()
+
+
+def test_zonal_harmonic_solves_n81920_fp32():
+    """f = Y_l (l = 0..8, nine right-hand sides in one solve) at N = 81,920,
+    FP32 form, eps 1e-5, GMRES to 1e-6.  The continuous solution is
+    (2l+1) Y_l; the discrete one differs by the discretisation error, which
+    must fall under half of the dense oracle's error at N = 5,120 (first order
+    in h would give a quarter)."""
+    import paper_1806_11558_amd as hm
+    from oracle import bem, sphere
+    from synthetic import icosphere
+    say("zonal harmonics N=81920 f32")
+    ls = list(range(9))
+
+    def errors(sig, x):
+        out = []
+        for k, l in enumerate(ls):
+            ex = (2 * l + 1) * sphere.zonal_harmonic(l, x)
+            out.append(rel2(sig[:, k], ex))
+        return np.array(out)
+    V4, T4 = icosphere(4)
+    op4 = bem.Operator(V4, T4)
+    F4 = np.stack([sphere.zonal_harmonic(l, op4.x) for l in ls], axis=1)
+    e4 = errors(np.linalg.solve(op4.dense(), F4), op4.x)
+    V, T = icosphere(6)
+    x6 = bem.centroids(V, T.astype(np.int64))
+    F = np.stack([sphere.zonal_harmonic(l, x6) for l in ls], axis=1)
+    H = hm.HMatrix(V, T, leaf_size=64, eta=1.0, eps=1e-5, precision="f32")
+    sig, info, status = H.solve(torch.tensor(F, device=DEV), tol=1e-6, restart=100, max_iter=1000)
+    H.free()
+    assert status == 0 and info.converged
+    e6 = errors(sig.cpu().numpy(), x6)
+    assert np.all(e6 <= 0.5 * e4), (e6, e4)
