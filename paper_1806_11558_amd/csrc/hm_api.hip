@@ -92,7 +92,7 @@ struct hm_handle {
   int2 *dns = nullptr, *lr = nullptr;
   Storage sto;
 
-  void *z = nullptr, *w = nullptr;
+  void *z = nullptr, *w = nullptr, *ypart = nullptr;
   int max_nr_t = 1;
   int grid = 1024;
 
@@ -128,6 +128,11 @@ struct hm_handle {
     MvPlan P;
     P.runs = sto.runs;
     P.nruns = sto.nruns;
+    P.units = sto.units;
+    P.nunits = sto.nunits;
+    P.ubeg = sto.ubeg;
+    P.ypart = ypart;
+    P.ldmax = sto.ldmax;
     P.colmap = sto.colmap;
     P.meta = sto.meta;
     P.nlr = nl;
@@ -317,6 +322,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   // ---- product workspace: z = [x ; t] with 16 columns, w for the
   // transposed product sized to at most 2 GB (fewer columns per pass)
   h->z = h->alloc((size_t)(n + h->sto.toff_total + 1) * kMaxNr * sizeof(double));
+  h->ypart = h->alloc((size_t)(h->sto.nunits + 1) * h->sto.ldmax * kMaxNr * sizeof(double));
   {
     const int64_t cols = h->sto.ncols + 1;
     int nrt = kMaxNr;

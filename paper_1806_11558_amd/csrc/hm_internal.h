@@ -107,9 +107,22 @@ struct MvProfile {
   double ms[8];
   double launches[8];
 };
+// Unit of the per-row-leaf product kernels: columns [a, a + w) of run `run`
+// of row leaf `leaf` (at most kUnitCols columns), so that a leaf with a wide
+// panel is shared by several workgroups.  Units of a leaf are consecutive.
+struct Unit {
+  int32_t leaf, run, a, w;
+};
+constexpr int kUnitCols = 2048;
+
 struct MvPlan {
   const Run* runs;          // [nruns][nleaf]
   int nruns;
+  const Unit* units;        // nunits, grouped by leaf
+  int64_t nunits;
+  const int32_t* ubeg;      // leaf -> first unit (nleaf + 1)
+  void* ypart;              // workspace: per-unit partial rows, ldmax x 16 each
+  int ldmax;
   const int32_t* colmap;
   const LrMeta* meta;
   int64_t nlr;
@@ -154,6 +167,10 @@ struct Storage {
   int64_t lr_elems = 0, toff_total = 0, nchunks = 0, u_items = 0;
   Run* runs = nullptr;
   int nruns = 0;
+  Unit* units = nullptr;
+  int64_t nunits = 0;
+  int32_t* ubeg = nullptr;
+  int ldmax = 0;
   float* su = nullptr;       // per-term scales when the factors are FP16
   int32_t* colmap = nullptr;
   int64_t ncols = 0;

@@ -339,14 +339,14 @@ __global__ __launch_bounds__(256) void k_fwd1m(const LrMeta* __restrict__ meta, 
 // application order.  Panel 0 of a leaf holds dense slices (type TD), the
 // others U slices (type TL); both share the lane layout.
 template <typename T, typename A, int NR, int G>
-__device__ inline void fwd2_run(const Run& rn, int ld, int C, int cg, int g, bool act, int wave,
-                                const int32_t* __restrict__ colmap, const A* __restrict__ z,
-                                A (&acc)[G][NR]) {
+__device__ inline void fwd2_run(const Run& rn, int a, int uw, int ld, int C, int cg, int g, bool act,
+                                int wave, const int32_t* __restrict__ colmap,
+                                const A* __restrict__ z, A (&acc)[G][NR]) {
   constexpr int UNR = 4;
   static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
-  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
-  const int32_t* map = colmap + rn.col0;
-  const int ngrp = (rn.w + C - 1) / C;
+  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
+  const int32_t* map = colmap + rn.col0 + a;
+  const int ngrp = (uw + C - 1) / C;
   // Loads are unconditional: a lane without a column of its own reads the
   // panel's last column and contributes zero, so the compiler keeps all
   // UNR loads in flight instead of waiting inside divergent branches.
@@ -358,8 +358,8 @@ __device__ inline void fwd2_run(const Run& rn, int ld, int C, int cg, int g, boo
     for (int u = 0; u < UNR; ++u) {
       const int q = q0 + 4 * u;
       const int j = q * C + cg;
-      ok[u] = act && q < ngrp && j < rn.w;
-      const int jj = ok[u] ? j : rn.w - 1;
+      ok[u] = act && q < ngrp && j < uw;
+      const int jj = ok[u] ? j : uw - 1;
       Gran<T>::load(S + (int64_t)jj * ld, s[u]);
       zi[u] = map[jj];
     }
@@ -377,40 +377,96 @@ __device__ inline void fwd2_run(const Run& rn, int ld, int C, int cg, int g, boo
   }
 }
 
-template <typename TD, typename TL, typename A, typename VT, int NR>
-__global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int nruns, MvLeaves L,
+// Few right-hand sides: the workgroup first gathers the z values of a tile
+// of kZTile panel columns into LDS (one load per column instead of one per
+// lane, and no map -> z dependency inside the streaming loop), then streams
+// the tile's columns.  Same column order per lane as fwd2_run.
+constexpr int kZTile = 1024;
+
+template <typename T, typename A, int NR, int G>
+__device__ inline void fwd2_run_lds(const Run& rn, int a, int uw, int ld, int C, int cg, int g,
+                                    bool act, int wave, const int32_t* __restrict__ colmap,
+                                    const A* __restrict__ z, A* __restrict__ zt,
+                                    A (&acc)[G][NR]) {
+  constexpr int UNR = 4;
+  static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
+  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
+  const int32_t* map = colmap + rn.col0 + a;
+  for (int t0 = 0; t0 < uw; t0 += kZTile) {
+    const int tw = min(kZTile, uw - t0);
+    __syncthreads();                                   // the previous tile is consumed
+    for (int c = threadIdx.x; c < tw; c += blockDim.x) {
+      A v[NR];
+      load_row<A, NR>(z + (int64_t)map[t0 + c] * NR, v);
+#pragma unroll
+      for (int k = 0; k < NR; ++k) zt[c * NR + k] = v[k];
+    }
+    __syncthreads();
+    const T* St = S + (int64_t)t0 * ld;
+    const int ngrp = (tw + C - 1) / C;
+    for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
+      typename Gran<T>::E s[UNR][G];
+      int jl[UNR];
+      bool ok[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int q = q0 + 4 * u;
+        const int j = q * C + cg;
+        ok[u] = act && q < ngrp && j < tw;
+        jl[u] = ok[u] ? j : tw - 1;
+        Gran<T>::load(St + (int64_t)jl[u] * ld, s[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+        for (int e = 0; e < G; ++e) {
+          const A sv = ok[u] ? (A)s[u][e] : (A)0;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc[e][k] += sv * zt[jl[u] * NR + k];
+        }
+      }
+    }
+  }
+}
+
+template <typename TD, typename TL, typename A, int NR>
+__global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, MvLeaves L,
+                                              const Unit* __restrict__ units, int64_t nunits,
                                               const int32_t* __restrict__ colmap,
-                                              const A* __restrict__ z,
-                                              const int32_t* __restrict__ perm, VT* __restrict__ y,
-                                              int nrhs, int k0) {
+                                              const A* __restrict__ z, A* __restrict__ ypart,
+                                              int ldmax) {
   constexpr int G = Gran<TD>::G;
+  constexpr bool kLds = NR <= 2;
   __shared__ A ybuf[4][kMaxLeaf][NR];
+  __shared__ A zt[kLds ? kZTile * NR : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t per = (L.nleaf + kXcds - 1) / kXcds;
+  const int64_t per = (nunits + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
-    const int64_t c = xcd_item(li, per);
-    if (c >= L.nleaf) continue;                         // uniform over the workgroup
+    const int64_t u = xcd_item(li, per);
+    if (u >= nunits) continue;                          // uniform over the workgroup
+    const Unit U = units[u];
+    const int64_t c = U.leaf;
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
     const int R = ld / G, C = 64 / R;
     const int cg = lane / R, g = lane % R;
     const bool act = cg < C;
-    const int m = L.m[c], lo = L.lo[c];
+    const int m = L.m[c];
     A acc[G][NR];
 #pragma unroll
     for (int e = 0; e < G; ++e)
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[e][k] = 0;
-    for (int kr = 0; kr < nruns; ++kr) {
-      const Run rn = runs[(int64_t)kr * L.nleaf + c];
-      if (rn.w == 0) continue;
-      if constexpr (std::is_same<TD, TL>::value) {
-        fwd2_run<TD, A, NR, G>(rn, ld, C, cg, g, act, wave, colmap, z, acc);
-      } else {
-        if (kr == 0)
-          fwd2_run<TD, A, NR, G>(rn, ld, C, cg, g, act, wave, colmap, z, acc);
-        else
-          fwd2_run<TL, A, NR, G>(rn, ld, C, cg, g, act, wave, colmap, z, acc);
-      }
+    const Run rn = runs[(int64_t)U.run * L.nleaf + c];
+    if constexpr (kLds) {
+      if (std::is_same<TD, TL>::value || U.run == 0)
+        fwd2_run_lds<TD, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, zt, acc);
+      else
+        fwd2_run_lds<TL, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, zt, acc);
+    } else {
+      if (std::is_same<TD, TL>::value || U.run == 0)
+        fwd2_run<TD, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, acc);
+      else
+        fwd2_run<TL, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, acc);
     }
     // combine the column groups (tree over cg, stride R), then the waves
 #pragma unroll
@@ -434,32 +490,52 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, int 
       }
     }
     __syncthreads();
+    A* yp = ypart + u * ldmax * NR;
     for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
       const int row = e / NR, k = e % NR;
-      const A v = ((ybuf[0][row][k] + ybuf[1][row][k]) + ybuf[2][row][k]) + ybuf[3][row][k];
-      y[(int64_t)perm[lo + row] * nrhs + k0 + k] = (VT)v;
+      yp[e] = ((ybuf[0][row][k] + ybuf[1][row][k]) + ybuf[2][row][k]) + ybuf[3][row][k];
     }
     __syncthreads();
+  }
+}
+
+// y rows of every leaf = sum of its units' partial rows (in unit order),
+// scattered to application order.
+template <typename A, typename VT, int NR>
+__global__ __launch_bounds__(256) void k_fwd2_sum(MvLeaves L, const int32_t* __restrict__ ubeg,
+                                                  const A* __restrict__ ypart, int ldmax,
+                                                  const int32_t* __restrict__ perm,
+                                                  VT* __restrict__ y, int nrhs, int k0) {
+  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+    const int m = L.m[c], lo = L.lo[c];
+    const int u0 = ubeg[c], u1 = ubeg[c + 1];
+    for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
+      const int row = e / NR, k = e % NR;
+      A v = 0;
+      for (int u = u0; u < u1; ++u) v += ypart[(int64_t)u * ldmax * NR + e];
+      y[(int64_t)perm[lo + row] * nrhs + k0 + k] = (VT)v;
+    }
   }
 }
 
 // ------------------------------------------------------------------ transposed, phase 1
 // Per row leaf: w[col0 + j] = sum_i P[i][j] x_c[i] for every panel column.
 template <typename T, typename A, int NR, int G>
-__device__ inline void tr1_run(const Run& rn, int ld, int R, int C, int cg, int g, bool act,
-                               int wave, const A (&xg)[G][NR], A* __restrict__ w) {
+__device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int C, int cg, int g,
+                               bool act, int wave, const A (&xg)[G][NR], A* __restrict__ w) {
   static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
-  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + g * G;
-  const int ngrp = (rn.w + C - 1) / C;
+  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
+  const int64_t col0 = rn.col0 + a;
+  const int ngrp = (uw + C - 1) / C;
   for (int q = wave; q < ngrp; q += 4) {
     const int j = q * C + cg;
     A p[NR];
 #pragma unroll
     for (int k = 0; k < NR; ++k) p[k] = 0;
-    const bool ok = act && j < rn.w;
+    const bool ok = act && j < uw;
     {
       typename Gran<T>::E sv[G];
-      Gran<T>::load(S + (int64_t)(ok ? j : rn.w - 1) * ld, sv);
+      Gran<T>::load(S + (int64_t)(ok ? j : uw - 1) * ld, sv);
 #pragma unroll
       for (int e = 0; e < G; ++e) {
         const A a = ok ? (A)sv[e] : (A)0;
@@ -469,22 +545,25 @@ __device__ inline void tr1_run(const Run& rn, int ld, int R, int C, int cg, int 
     }
 #pragma unroll
     for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
-    if (act && g == 0 && j < rn.w) {
+    if (act && g == 0 && j < uw) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k) w[(rn.col0 + j) * NR + k] = p[k];
+      for (int k = 0; k < NR; ++k) w[(col0 + j) * NR + k] = p[k];
     }
   }
 }
 
 template <typename TD, typename TL, typename A, int NR>
-__global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, int nruns, MvLeaves L,
+__global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, MvLeaves L,
+                                             const Unit* __restrict__ units, int64_t nunits,
                                              const A* __restrict__ z, A* __restrict__ w) {
   constexpr int G = Gran<TD>::G;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t per = (L.nleaf + kXcds - 1) / kXcds;
+  const int64_t per = (nunits + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
-    const int64_t c = xcd_item(li, per);
-    if (c >= L.nleaf) continue;                         // uniform over the workgroup
+    const int64_t u = xcd_item(li, per);
+    if (u >= nunits) continue;
+    const Unit U = units[u];
+    const int64_t c = U.leaf;
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
     const int R = ld / G, C = 64 / R;
     const int cg = lane / R, g = lane % R;
@@ -498,18 +577,11 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, int n
       for (int k = 0; k < NR; ++k)
         xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
     }
-    for (int kr = 0; kr < nruns; ++kr) {
-      const Run rn = runs[(int64_t)kr * L.nleaf + c];
-      if (rn.w == 0) continue;
-      if constexpr (std::is_same<TD, TL>::value) {
-        tr1_run<TD, A, NR, G>(rn, ld, R, C, cg, g, act, wave, xg, w);
-      } else {
-        if (kr == 0)
-          tr1_run<TD, A, NR, G>(rn, ld, R, C, cg, g, act, wave, xg, w);
-        else
-          tr1_run<TL, A, NR, G>(rn, ld, R, C, cg, g, act, wave, xg, w);
-      }
-    }
+    const Run rn = runs[(int64_t)U.run * L.nleaf + c];
+    if (std::is_same<TD, TL>::value || U.run == 0)
+      tr1_run<TD, A, NR, G>(rn, U.a, U.w, ld, R, C, cg, g, act, wave, xg, w);
+    else
+      tr1_run<TL, A, NR, G>(rn, U.a, U.w, ld, R, C, cg, g, act, wave, xg, w);
   }
 }
 
@@ -659,12 +731,21 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
       HM_HIP(hipEventRecord(pr->ev[2], s));
       HM_HIP(hipEventRecord(pr->ev[3], s));
     }
-    k_fwd2<TD, TL, A, VT, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, P.colmap, z, P.perm, y,
-                                                  nrhs, k0);
+    const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(P.nunits, kXcds) * kXcds, P.grid);
+    if (P.nunits > 0) {
+      k_fwd2<TD, TL, A, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, P.colmap, z,
+                                               static_cast<A*>(P.ypart), P.ldmax);
+      HM_LAUNCH_CHECK();
+    }
+    k_fwd2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(P.L.nleaf, P.grid), 256, 0, s>>>(
+        P.L, P.ubeg, static_cast<const A*>(P.ypart), P.ldmax, P.perm, y, nrhs, k0);
     HM_LAUNCH_CHECK();
   } else {
-    k_tr1<TD, TL, A, NR><<<gl, 256, 0, s>>>(P.runs, P.nruns, P.L, z, w);
-    HM_LAUNCH_CHECK();
+    if (P.nunits > 0) {
+      const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(P.nunits, kXcds) * kXcds, P.grid);
+      k_tr1<TD, TL, A, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, z, w);
+      HM_LAUNCH_CHECK();
+    }
     if (pr) HM_HIP(hipEventRecord(pr->ev[2], s));
     if (P.nlr > 0) {
       k_tr_sums<A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.ucol, w, z, P.n, P.su);

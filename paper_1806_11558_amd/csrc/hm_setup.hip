@@ -1330,6 +1330,37 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   for (int k = 0; k < out.nruns; ++k)
     HM_HIP(hipMemcpyAsync(out.runs + (int64_t)k * nleaf, run_parts[k], nleaf * sizeof(Run),
                           hipMemcpyDeviceToDevice, s));
+  // work units: every run of every leaf cut into pieces of at most kUnitCols
+  {
+    std::vector<Run> hr((size_t)out.nruns * nleaf);
+    std::vector<int64_t> hld(nleaf + 1);
+    if (!hr.empty())
+      HM_HIP(hipMemcpyAsync(hr.data(), out.runs, hr.size() * sizeof(Run), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipMemcpyAsync(hld.data(), in.ldpre, (nleaf + 1) * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    std::vector<Unit> hu;
+    std::vector<int32_t> hb(nleaf + 1);
+    out.ldmax = 1;
+    for (int64_t c = 0; c < nleaf; ++c) {
+      hb[c] = (int32_t)hu.size();
+      out.ldmax = std::max(out.ldmax, (int)(hld[c + 1] - hld[c]));
+      for (int k = 0; k < out.nruns; ++k) {
+        const int64_t w = hr[(size_t)k * nleaf + c].w;
+        for (int64_t a = 0; a < w; a += kUnitCols)
+          hu.push_back(Unit{(int32_t)c, k, (int32_t)a, (int32_t)std::min<int64_t>(kUnitCols, w - a)});
+      }
+    }
+    if (hu.size() >= (size_t)INT32_MAX) throw Error{HM_ERR_STATE, "too many product units"};
+    hb[nleaf] = (int32_t)hu.size();
+    out.nunits = (int64_t)hu.size();
+    out.units = static_cast<Unit*>(alloc((hu.size() + 1) * sizeof(Unit)));
+    out.ubeg = static_cast<int32_t*>(alloc(hb.size() * sizeof(int32_t)));
+    if (!hu.empty())
+      HM_HIP(hipMemcpyAsync(out.units, hu.data(), hu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(out.ubeg, hb.data(), hb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HM_HIP(hipStreamSynchronize(s));
+  }
   out.ncols = out.dense_cols + ucols;
   out.colmap = static_cast<int32_t*>(alloc((out.ncols + 1) * sizeof(int32_t)));
   {
