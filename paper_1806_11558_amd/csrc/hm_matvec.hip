@@ -178,7 +178,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     const int R0 = M.vld / G, C0 = R0 > 0 ? 64 / R0 : 1;
     if (M.vld > 0 && r <= PMAX * C0) {
       const int ld = M.vld, R = R0, C = C0;
-      const int cg = lane / R, g = lane % R;
+      // lane / R by a multiply and shift (exact for lane < 64, R <= 64)
+      const unsigned mul = (unsigned)(65536.0f / (float)R) + 1u;
+      const int cg = (int)(((unsigned)lane * mul) >> 16), g = lane - cg * R;
       const bool act = cg < C;
       const int P = (r + C - 1) / C;
       A acc[PMAX][NR];
@@ -186,10 +188,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       for (int q = 0; q < PMAX; ++q)
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[q][k] = 0;
-      const int64_t sstride = (int64_t)ld * r;
-      const T* S0 = S + g * G;
-      for (int lf = M.sf; lf <= M.sl; ++lf, S0 += sstride) {
-        const int m = L.m[lf], lo = L.lo[lf];
+      // 32-bit element offsets of the lane's granule in each pass; columns
+      // past r read column r - 1 into accumulators that are never flushed
+      int off[PMAX];
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) off[q] = min(q * C + cg, r - 1) * ld + g * G;
+      const int sstride = ld * r;
+      const T* Sl = S;
+      int lo = L.lo[M.sf];                   // the leaves of sigma are consecutive
+      for (int lf = M.sf; lf <= M.sl; ++lf, Sl += sstride) {
+        const int m = L.m[lf];
         A xg[G][NR];
 #pragma unroll
         for (int e = 0; e < G; ++e) {
@@ -206,18 +214,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 #pragma unroll
         for (int q = 0; q < PMAX; ++q) {
           if (q < P) {                                  // uniform over the wavefront
-            const int j = q * C + cg;
-            const bool ok = act && j < r;
             typename Gran<T>::E sv[G];
-            Gran<T>::load(S0 + (int64_t)(ok ? j : r - 1) * ld, sv);
+            Gran<T>::load(Sl + off[q], sv);
 #pragma unroll
-            for (int e = 0; e < G; ++e) {
-              const A a = ok ? (A)sv[e] : (A)0;
+            for (int e = 0; e < G; ++e)
 #pragma unroll
-              for (int k = 0; k < NR; ++k) acc[q][k] += a * xg[e][k];
-            }
+              for (int k = 0; k < NR; ++k) acc[q][k] += (A)sv[e] * xg[e][k];
           }
         }
+        lo += m;
       }
 #pragma unroll
       for (int q = 0; q < PMAX; ++q)
@@ -721,10 +726,11 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
     if (P.nlr > 0) {
-      if constexpr (NR >= 4)
+      if constexpr (NR >= 4) {
         k_fwd1m<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
-      else
+      } else {
         k_fwd1<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
+      }
       HM_LAUNCH_CHECK();
     }
     if (pr) {
