@@ -96,6 +96,7 @@ struct hm_handle {
   int max_nr_t = 1;
   int grid = 1024;
 
+  hipStream_t alloc_stream = nullptr;   // stream of the build (owned allocations)
   hm_stats st{};
   double ms[HM_NPHASE] = {0};
   MvProfile prof{};
@@ -106,11 +107,8 @@ struct hm_handle {
     if (p.mem_limit_bytes > 0 && bytes + (int64_t)b > p.mem_limit_bytes)
       throw Error{HM_ERR_OOM, "mem_limit_bytes exceeded (" + std::to_string(bytes + b) + " > " +
                                   std::to_string(p.mem_limit_bytes) + ")"};
-    void* q = nullptr;
-    if (hipMalloc(&q, b) != hipSuccess || !q) {
-      (void)hipGetLastError();
-      throw Error{HM_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
-    }
+    // stream-ordered from the library's pool (on the stream of the build)
+    void* q = dalloc(b, alloc_stream);
     owned.push_back(q);
     bytes += (int64_t)b;
     return q;
@@ -122,7 +120,10 @@ struct hm_handle {
   ~hm_handle() {
     if (profiling)
       for (auto& e : prof.ev) (void)hipEventDestroy(e);
-    for (void* q : owned) (void)hipFree(q);
+    // callers free handles after their work is done (hm_free synchronises
+    // the device first); the build stream may no longer exist
+    for (void* q : owned) (void)hipFreeAsync(q, nullptr);
+    (void)hipStreamSynchronize(nullptr);
   }
   MvPlan plan() const {
     MvPlan P;
@@ -159,16 +160,12 @@ double ms_since(clk::time_point t0) {
   return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
-// The setup's temporaries come from the stream-ordered allocator; return the
-// memory it keeps cached to the device so that later allocations (of this or
-// another handle, or of the caller) do not compete with it.
+// The setup's temporaries come from the library's pool; return what it
+// caches beyond its keep size to the device, so that later allocations of
+// the caller do not compete with it.
 void release_cached_memory(hipStream_t s) {
   HM_HIP(hipStreamSynchronize(s));
-  int dev = 0;
-  HM_HIP(hipGetDevice(&dev));
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
-  (void)hipGetLastError();
+  trim_pool();
 }
 
 template <typename F>
@@ -452,6 +449,7 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
       h->profiling = true;
     }
     hipStream_t s = as_stream(stream);
+    h->alloc_stream = s;
     if (h->form == HM_F32_F16)
       build_impl<float, _Float16>(h.get(), vertices, n_vertices, triangles, s);
     else if (h->form == HM_F32)
@@ -686,11 +684,7 @@ void hm_free(hm_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   delete h;
-  int dev = 0;
-  hipMemPool_t pool;
-  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
-    (void)hipMemPoolTrimTo(pool, 0);
-  (void)hipGetLastError();
+  trim_pool();
 }
 
 hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int64_t* needed) {

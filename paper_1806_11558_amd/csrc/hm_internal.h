@@ -206,6 +206,10 @@ void radix_sort_u64_i32(uint64_t* keys, int32_t* vals, int64_t n, int bits,
 // Stream-ordered temporary allocation (throws HM_ERR_OOM).
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
+// The library's memory pool on the current device; trim_pool() returns what
+// it caches beyond its keep size to the device.
+hipMemPool_t lib_pool();
+void trim_pool();
 template <typename T>
 T* dalloc_t(size_t count, hipStream_t s) {
   return static_cast<T*>(dalloc(count * sizeof(T) + 16, s));

@@ -6,15 +6,55 @@
 // written here for wave64: the sort ranks keys inside a wavefront with
 // ballots (no atomics on the ranking path), so it is stable and
 // deterministic.
+#include <mutex>
+
 #include "hm_internal.h"
 
 namespace hm {
 
 // ------------------------------------------------------------------ memory
+// All device memory of the library comes from one stream-ordered pool per
+// device, created on first use.  Up to kPoolKeep bytes of freed memory stay
+// cached in it across synchronisations, so a rebuild does not go back to the
+// driver for every temporary; trim_pool() hands the rest back.
+namespace {
+constexpr uint64_t kPoolKeep = uint64_t(1) << 30;
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[64] = {};
+}  // namespace
+
+hipMemPool_t lib_pool() {
+  int dev = 0;
+  HM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error{HM_ERR_HIP, "device index out of range"};
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (!g_pool[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    HM_HIP(hipMemPoolCreate(&pool, &props));
+    uint64_t keep = kPoolKeep;
+    HM_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+    g_pool[dev] = pool;
+  }
+  return g_pool[dev];
+}
+
+void trim_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pool[dev]) (void)hipMemPoolTrimTo(g_pool[dev], kPoolKeep);
+  (void)hipGetLastError();
+}
+
 void* dalloc(size_t bytes, hipStream_t s) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
-  hipError_t e = hipMallocAsync(&p, bytes, s);
+  hipError_t e = hipMallocFromPoolAsync(&p, bytes, lib_pool(), s);
   if (e != hipSuccess || p == nullptr) {
     (void)hipGetLastError();
     throw Error{HM_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
