@@ -117,6 +117,30 @@ hm_status hm_build(const double* vertices, int64_t n_vertices,
                    const hm_params* p, void* stream, hm_handle** out);
 
 /*
+ * hm_build_batch -- one handle for several independent meshes, set up in the
+ * same batched launches (the batching of Sec. 3.3 carried over many surfaces
+ * at once).  Every geometry gets its own Morton box, cluster tree and block
+ * partition (Algorithm 1 starts from each geometry's root pair); geometries
+ * do not interact, so the operator is block diagonal over them and a product
+ * or solve treats all of them together.
+ *   vertices     host, double[vtx_offsets[n_geom]][3], all geometries
+ *                concatenated
+ *   vtx_offsets  host, int64[n_geom + 1], starts at 0, at least 3 vertices
+ *                per geometry
+ *   triangles    host, int32[tri_offsets[n_geom]][3]; the indices of
+ *                geometry g are local to its vertex range
+ *   tri_offsets  host, int64[n_geom + 1], starts at 0, at least 1 triangle
+ *                per geometry
+ *   n_geom       1..65536
+ * Unknowns are the triangles in concatenated order (N = tri_offsets[n_geom]);
+ * products and solves take vectors of that length.  Other arguments,
+ * ownership and errors as hm_build; n_geom = 1 builds the same handle.
+ */
+hm_status hm_build_batch(const double* vertices, const int64_t* vtx_offsets,
+                         const int32_t* triangles, const int64_t* tri_offsets, int32_t n_geom,
+                         const hm_params* p, void* stream, hm_handle** out);
+
+/*
  * hm_matvec -- y = H x, the approximate product of Sec. 2.3: dense leaves
  * apply their stored block, admissible leaves apply U (V^T x).
  *   x, y   device, [n, nrhs] row-major, dtype `dtype` (HM_F64 or HM_F32);
@@ -216,6 +240,7 @@ typedef struct {
   int64_t device_bytes;    /* device memory held by the handle               */
   int64_t precision;
   int64_t aca_chunks;
+  int64_t n_geom;           /* geometries in the handle                      */
 } hm_stats;
 
 /*

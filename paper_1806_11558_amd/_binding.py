@@ -56,7 +56,7 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "n_clusters", "n_leaves", "n_dense", "n_lr", "depth", "dense_entries",
         "lr_entries", "lr_u_entries", "stored_bytes", "rank_sum", "rank_max", "cap_hits", "aca_entry_evals",
-        "n_panel_cols", "n_titems", "device_bytes", "precision", "aca_chunks")]
+        "n_panel_cols", "n_titems", "device_bytes", "precision", "aca_chunks", "n_geom")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -83,6 +83,7 @@ def lib():
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hm_params_default.argtypes = [C.POINTER(Params)]
     L.hm_build.argtypes = [vp, i64, vp, i64, C.POINTER(Params), vp, C.POINTER(vp)]
+    L.hm_build_batch.argtypes = [vp, vp, vp, vp, i32, C.POINTER(Params), vp, C.POINTER(vp)]
     L.hm_matvec.argtypes = [vp, vp, vp, i32, i32, vp]
     L.hm_matvec_T.argtypes = [vp, vp, vp, i32, i32, vp]
     L.hm_solve.argtypes = [vp, vp, vp, i32, i32, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]
@@ -92,7 +93,7 @@ def lib():
     L.hm_entries.argtypes = [vp, vp, vp, i64, vp]
     L.hm_last_error.restype = C.c_char_p
     L.hm_last_error.argtypes = []
-    for f in ("hm_params_default", "hm_build", "hm_matvec", "hm_matvec_T", "hm_solve",
+    for f in ("hm_params_default", "hm_build", "hm_build_batch", "hm_matvec", "hm_matvec_T", "hm_solve",
               "hm_query", "hm_entries"):
         getattr(L, f).restype = C.c_int
     _LIB = L
@@ -134,6 +135,24 @@ def hm_build(vertices: np.ndarray, triangles: np.ndarray, params: Params, stream
     h = C.c_void_p()
     _check(lib().hm_build(v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], C.byref(params),
                           _stream_ptr(stream), C.byref(h)))
+    return h.value
+
+
+def hm_build_batch(meshes, params: Params, stream=None) -> int:
+    """meshes: sequence of (vertices [nv, 3], triangles [nt, 3]) with indices
+    local to each mesh."""
+    vs = [np.ascontiguousarray(v, dtype=np.float64) for v, _ in meshes]
+    ts = [np.ascontiguousarray(t, dtype=np.int32) for _, t in meshes]
+    for v, t in zip(vs, ts):
+        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+            raise HMError(HM_ERR_ARG, "vertices and triangles must be [*, 3]")
+    voff = np.concatenate([[0], np.cumsum([v.shape[0] for v in vs])]).astype(np.int64)
+    toff = np.concatenate([[0], np.cumsum([t.shape[0] for t in ts])]).astype(np.int64)
+    V = np.ascontiguousarray(np.concatenate(vs))
+    T = np.ascontiguousarray(np.concatenate(ts))
+    h = C.c_void_p()
+    _check(lib().hm_build_batch(V.ctypes.data, voff.ctypes.data, T.ctypes.data, toff.ctypes.data,
+                                len(meshes), C.byref(params), _stream_ptr(stream), C.byref(h)))
     return h.value
 
 
@@ -211,6 +230,28 @@ class HMatrix:
                  eps: float = 1e-6, max_rank: int = 64, precision: str = "f64",
                  strict: bool = False, profile: bool = False, mem_limit_bytes: int = 0,
                  stream=None):
+        p = self._params(leaf_size, eta, eps, max_rank, precision, strict, profile,
+                         mem_limit_bytes)
+        self.n = int(np.asarray(triangles).shape[0])
+        self.offsets = np.array([0, self.n], dtype=np.int64)
+        self._h = hm_build(vertices, triangles, p, stream)
+
+    @classmethod
+    def batch(cls, meshes, *, leaf_size: int = 32, eta: float = 1.0, eps: float = 1e-6,
+              max_rank: int = 64, precision: str = "f64", strict: bool = False,
+              profile: bool = False, mem_limit_bytes: int = 0, stream=None):
+        """One handle for several meshes [(vertices, triangles), ...]
+        (hm_build_batch); unknowns are the triangles in concatenated order."""
+        self = cls.__new__(cls)
+        p = self._params(leaf_size, eta, eps, max_rank, precision, strict, profile,
+                         mem_limit_bytes)
+        sizes = [int(np.asarray(t).shape[0]) for _, t in meshes]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+        self._h = hm_build_batch(meshes, p, stream)
+        return self
+
+    def _params(self, leaf_size, eta, eps, max_rank, precision, strict, profile, mem_limit_bytes):
         p = hm_params_default()
         p.leaf_size = leaf_size
         p.eta = eta
@@ -220,9 +261,9 @@ class HMatrix:
         p.flags = (HM_STRICT if strict else 0) | (HM_PROFILE if profile else 0)
         p.mem_limit_bytes = mem_limit_bytes
         self.params = p
-        self.n = int(np.asarray(triangles).shape[0])
         self.storage_dtype = np.float64 if precision == "f64" else np.float32
-        self._h = hm_build(vertices, triangles, p, stream)
+        self._h = None
+        return p
 
     # products -------------------------------------------------------------
     def matvec(self, x, out=None, stream=None, transpose: bool = False):

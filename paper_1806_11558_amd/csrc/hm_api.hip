@@ -15,13 +15,14 @@ namespace hm {
 
 // ---- launchers defined in the other translation units
 void launch_centroids(const double* V, const int32_t* T, int64_t n, double* C, hipStream_t s);
-void launch_minmax(const double* C, int64_t n, double* out6, hipStream_t s);
-void launch_morton(const double* C, int64_t n, const double* a, double scale, uint64_t* keys,
-                   int32_t* idx, hipStream_t s);
+void launch_minmax(const double* C, int64_t n, int64_t off, int64_t cnt, double* out6,
+                   hipStream_t s);
+void launch_morton(const double* C, int64_t n, int64_t off, int64_t cnt, const double* a,
+                   double scale, uint64_t* keys, int32_t* idx, hipStream_t s);
 template <typename T>
 void launch_geom_sorted(const double* V, const int32_t* Tri, const int32_t* perm, int64_t n,
                         double* c, T* o, T* aw, T* sf, hipStream_t s);
-int64_t build_cluster_tree(int64_t n, int leaf, Cluster* cl, int64_t cap,
+int64_t build_cluster_tree(const std::vector<int64_t>& goff, int leaf, Cluster* cl, int64_t cap,
                            std::vector<int64_t>& level_beg, hipStream_t s);
 void launch_leaf_marks(const Cluster* cl, int64_t ncl, int64_t* mark, hipStream_t s);
 void launch_pos_leaf(const int64_t* mark, const int64_t* excl, int64_t n, int32_t* pos_leaf,
@@ -31,8 +32,9 @@ void launch_leaf_table(const Cluster* cl, int64_t ncl, const int32_t* pos_leaf, 
                        hipStream_t s);
 void launch_boxes(const Cluster* cl, const std::vector<int64_t>& level_beg, const int32_t* leaf_cl,
                   int64_t nleaf, const double* c, int64_t n, double* box, hipStream_t s);
-void build_block_tree(const Cluster* cl, const double* box, double eta, int leaf, int2** adm_out,
-                      int64_t* nadm, int2** dns_out, int64_t* ndns, int64_t* depth, hipStream_t s);
+void build_block_tree(const Cluster* cl, int64_t nroots, const double* box, double eta, int leaf,
+                      int2** adm_out, int64_t* nadm, int2** dns_out, int64_t* ndns,
+                      int64_t* depth, hipStream_t s);
 template <typename T>
 void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
                     int64_t cnt, double* out, hipStream_t s);
@@ -56,6 +58,7 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 
 constexpr int kMaxNr = 16;   // right-hand sides per product pass
+constexpr int kMaxGeoms = 65536;
 
 }  // namespace hm
 
@@ -97,6 +100,7 @@ struct hm_handle {
   int grid = 1024;
 
   hipStream_t alloc_stream = nullptr;   // stream of the build (owned allocations)
+  std::vector<int64_t> goff;            // triangle offsets of the geometries (G + 1)
   hm_stats st{};
   double ms[HM_NPHASE] = {0};
   MvProfile prof{};
@@ -200,6 +204,8 @@ int64_t scan_total(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hip
 template <typename T, typename TL>
 void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T_host,
                 hipStream_t s) {
+  const std::vector<int64_t>& goff = h->goff;   // triangle offsets of the geometries
+  const int64_t G = (int64_t)goff.size() - 1;
   const int64_t n = h->n;
   const hm_params& p = h->p;
   const auto t_start = clk::now();
@@ -218,21 +224,27 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
 
   // ---- Morton codes and sort
   t0 = clk::now();
-  double* mm = dalloc_t<double>(6, s);
-  launch_minmax(Capp, n, mm, s);
-  double mmh[6];
-  HM_HIP(hipMemcpyAsync(mmh, mm, sizeof(mmh), hipMemcpyDeviceToHost, s));
+  // every geometry has its own cube box and is sorted within its own range
+  double* mm = dalloc_t<double>(6 * G, s);
+  for (int64_t g = 0; g < G; ++g) launch_minmax(Capp, n, goff[g], goff[g + 1] - goff[g], mm + 6 * g, s);
+  std::vector<double> mmh(6 * G);
+  HM_HIP(hipMemcpyAsync(mmh.data(), mm, 6 * G * sizeof(double), hipMemcpyDeviceToHost, s));
   HM_HIP(hipStreamSynchronize(s));
-  double ext = 0.0;
-  for (int d = 0; d < 3; ++d) ext = std::max(ext, mmh[3 + d] - mmh[d]);
-  const double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
   h->keys = h->alloc_t<uint64_t>(n);
   h->perm = h->alloc_t<int32_t>(n);
   h->inv = h->alloc_t<int32_t>(n);
   uint64_t* ksort = dalloc_t<uint64_t>(n, s);
-  launch_morton(Capp, n, mmh, scale, h->keys, h->perm, s);
+  for (int64_t g = 0; g < G; ++g) {
+    const double* mg = mmh.data() + 6 * g;
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) ext = std::max(ext, mg[3 + d] - mg[d]);
+    const double scale = ext > 0.0 ? 2097152.0 / ext : 0.0;
+    launch_morton(Capp, n, goff[g], goff[g + 1] - goff[g], mg, scale, h->keys, h->perm, s);
+  }
   HM_HIP(hipMemcpyAsync(ksort, h->keys, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-  radix_sort_u64_i32(ksort, h->perm, n, 3 * kMortonBits, s);
+  for (int64_t g = 0; g < G; ++g)
+    radix_sort_u64_i32(ksort + goff[g], h->perm + goff[g], goff[g + 1] - goff[g],
+                       3 * kMortonBits, s);
   launch_inverse_perm(h->perm, n, h->inv, s);
   dfree(ksort, s);
   dfree(mm, s);
@@ -252,10 +264,10 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
 
   // ---- cluster tree, leaves, boxes
   t0 = clk::now();
-  const int64_t cap = 2 * n + 2;
+  const int64_t cap = 2 * n + 2 * G;
   Cluster* cltmp = dalloc_t<Cluster>(cap, s);
   std::vector<int64_t> level_beg;
-  h->ncl = build_cluster_tree(n, p.leaf_size, cltmp, cap, level_beg, s);
+  h->ncl = build_cluster_tree(goff, p.leaf_size, cltmp, cap, level_beg, s);
   h->cl = h->alloc_t<Cluster>(h->ncl);
   HM_HIP(hipMemcpyAsync(h->cl, cltmp, h->ncl * sizeof(Cluster), hipMemcpyDeviceToDevice, s));
   dfree(cltmp, s);
@@ -287,7 +299,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   // ---- block cluster tree (Algorithm 1, level-wise)
   t0 = clk::now();
   int2 *adm = nullptr, *dns = nullptr;
-  build_block_tree(h->cl, h->box, p.eta, p.leaf_size, &adm, &h->nl, &dns, &h->nd, &h->depth, s);
+  build_block_tree(h->cl, G, h->box, p.eta, p.leaf_size, &adm, &h->nl, &dns, &h->nd, &h->depth, s);
   h->lr = h->alloc_t<int2>(h->nl);
   h->dns = h->alloc_t<int2>(h->nd);
   if (h->nl) HM_HIP(hipMemcpyAsync(h->lr, adm, h->nl * sizeof(int2), hipMemcpyDeviceToDevice, s));
@@ -376,6 +388,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   st.device_bytes = h->bytes;
   st.precision = h->form;
   st.aca_chunks = h->sto.nchunks;
+  st.n_geom = (int64_t)h->goff.size() - 1;
   h->ms[7] = ms_since(t_start);
   if ((p.flags & HM_STRICT) && st.cap_hits > 0)
     throw Error{HM_ERR_ACA, std::to_string(st.cap_hits) + " blocks reached max_rank"};
@@ -403,28 +416,30 @@ hm_status hm_params_default(hm_params* p) {
   return HM_OK;
 }
 
-hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* triangles,
-                   int64_t n_triangles, const hm_params* p, void* stream, hm_handle** out) {
-  if (!out) return arg_error("hm_build: out is NULL");
-  *out = nullptr;
-  if (!vertices || !triangles || !p) return arg_error("hm_build: NULL argument");
-  if (n_triangles < 1 || n_triangles > (int64_t)INT32_MAX / 2)
-    return arg_error("hm_build: n_triangles out of range");
-  if (n_vertices < 3 || n_vertices > (int64_t)INT32_MAX) return arg_error("hm_build: n_vertices out of range");
-  if (p->leaf_size < 1 || p->leaf_size > kMaxLeaf) return arg_error("hm_build: leaf_size must be in 1..64");
-  if (p->max_rank < 0 || p->max_rank > kMaxRank) return arg_error("hm_build: max_rank must be in 0..256");
+namespace {
+hm_status check_params(const hm_params* p, const char* who) {
+  const std::string w(who);
+  if (p->leaf_size < 1 || p->leaf_size > kMaxLeaf) return arg_error(w + ": leaf_size must be in 1..64");
+  if (p->max_rank < 0 || p->max_rank > kMaxRank) return arg_error(w + ": max_rank must be in 0..256");
   if (p->precision != HM_F64 && p->precision != HM_F32 && p->precision != HM_F32_F16)
-    return arg_error("hm_build: bad precision");
-  if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return arg_error("hm_build: eta must be finite and >= 0");
-  if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps)) return arg_error("hm_build: aca_eps must be finite and >= 0");
-  if (p->mem_limit_bytes < 0) return arg_error("hm_build: mem_limit_bytes < 0");
-  if (p->flags & ~(HM_STRICT | HM_PROFILE)) return arg_error("hm_build: unknown flag");
-  for (int64_t i = 0; i < 3 * n_vertices; ++i)
-    if (!std::isfinite(vertices[i])) return arg_error("hm_build: non-finite vertex coordinate");
-  for (int64_t t = 0; t < n_triangles; ++t) {
+    return arg_error(w + ": bad precision");
+  if (!(p->eta >= 0.0) || !std::isfinite(p->eta)) return arg_error(w + ": eta must be finite and >= 0");
+  if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps))
+    return arg_error(w + ": aca_eps must be finite and >= 0");
+  if (p->mem_limit_bytes < 0) return arg_error(w + ": mem_limit_bytes < 0");
+  if (p->flags & ~(HM_STRICT | HM_PROFILE)) return arg_error(w + ": unknown flag");
+  return HM_OK;
+}
+
+// Checks one geometry's vertices and triangles (indices local to it).
+hm_status check_mesh(const double* vertices, int64_t nv, const int32_t* triangles, int64_t nt,
+                     const std::string& w) {
+  for (int64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(vertices[i])) return arg_error(w + ": non-finite vertex coordinate");
+  for (int64_t t = 0; t < nt; ++t) {
     const int32_t a = triangles[3 * t], b = triangles[3 * t + 1], c = triangles[3 * t + 2];
-    if (a < 0 || b < 0 || c < 0 || a >= n_vertices || b >= n_vertices || c >= n_vertices)
-      return arg_error("hm_build: triangle " + std::to_string(t) + " has a vertex index out of range");
+    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
+      return arg_error(w + ": triangle " + std::to_string(t) + " has a vertex index out of range");
     const double* A = vertices + 3 * (int64_t)a;
     const double* B = vertices + 3 * (int64_t)b;
     const double* C = vertices + 3 * (int64_t)c;
@@ -433,13 +448,22 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
     const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
                           e1[0] * e2[1] - e1[1] * e2[0]};
     if (!(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] > 0.0))
-      return arg_error("hm_build: triangle " + std::to_string(t) + " is degenerate");
+      return arg_error(w + ": triangle " + std::to_string(t) + " is degenerate");
   }
+  return HM_OK;
+}
+
+// Builds a handle from validated, concatenated input; `tri` holds global
+// vertex indices and goff the triangle offsets of the geometries.
+hm_status build_handle(const double* vertices, int64_t n_vertices, const int32_t* tri,
+                       std::vector<int64_t> goff, const hm_params* p, void* stream,
+                       hm_handle** out) {
   return guarded([&]() -> hm_status {
     std::unique_ptr<hm_handle> h(new hm_handle());
     h->p = *p;
     if (h->p.max_rank == 0) h->p.max_rank = 64;
-    h->n = n_triangles;
+    h->n = goff.back();
+    h->goff = std::move(goff);
     h->form = p->precision;
     h->f32 = (p->precision != HM_F64) ? 1 : 0;
     h->ts = h->f32 ? 4 : 8;
@@ -451,14 +475,63 @@ hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* tr
     hipStream_t s = as_stream(stream);
     h->alloc_stream = s;
     if (h->form == HM_F32_F16)
-      build_impl<float, _Float16>(h.get(), vertices, n_vertices, triangles, s);
+      build_impl<float, _Float16>(h.get(), vertices, n_vertices, tri, s);
     else if (h->form == HM_F32)
-      build_impl<float, float>(h.get(), vertices, n_vertices, triangles, s);
+      build_impl<float, float>(h.get(), vertices, n_vertices, tri, s);
     else
-      build_impl<double, double>(h.get(), vertices, n_vertices, triangles, s);
+      build_impl<double, double>(h.get(), vertices, n_vertices, tri, s);
     *out = h.release();
     return HM_OK;
   });
+}
+}  // namespace
+
+hm_status hm_build(const double* vertices, int64_t n_vertices, const int32_t* triangles,
+                   int64_t n_triangles, const hm_params* p, void* stream, hm_handle** out) {
+  if (!out) return arg_error("hm_build: out is NULL");
+  *out = nullptr;
+  if (!vertices || !triangles || !p) return arg_error("hm_build: NULL argument");
+  if (n_triangles < 1 || n_triangles > (int64_t)INT32_MAX / 2)
+    return arg_error("hm_build: n_triangles out of range");
+  if (n_vertices < 3 || n_vertices > (int64_t)INT32_MAX) return arg_error("hm_build: n_vertices out of range");
+  hm_status st = check_params(p, "hm_build");
+  if (st != HM_OK) return st;
+  st = check_mesh(vertices, n_vertices, triangles, n_triangles, "hm_build");
+  if (st != HM_OK) return st;
+  return build_handle(vertices, n_vertices, triangles, {0, n_triangles}, p, stream, out);
+}
+
+hm_status hm_build_batch(const double* vertices, const int64_t* vtx_offsets,
+                         const int32_t* triangles, const int64_t* tri_offsets, int32_t n_geom,
+                         const hm_params* p, void* stream, hm_handle** out) {
+  if (!out) return arg_error("hm_build_batch: out is NULL");
+  *out = nullptr;
+  if (!vertices || !vtx_offsets || !triangles || !tri_offsets || !p)
+    return arg_error("hm_build_batch: NULL argument");
+  if (n_geom < 1 || n_geom > kMaxGeoms) return arg_error("hm_build_batch: n_geom must be in 1..65536");
+  if (vtx_offsets[0] != 0 || tri_offsets[0] != 0)
+    return arg_error("hm_build_batch: offsets must start at 0");
+  for (int32_t g = 0; g < n_geom; ++g) {
+    if (tri_offsets[g + 1] - tri_offsets[g] < 1)
+      return arg_error("hm_build_batch: geometry " + std::to_string(g) + " has no triangle");
+    if (vtx_offsets[g + 1] - vtx_offsets[g] < 3)
+      return arg_error("hm_build_batch: geometry " + std::to_string(g) + " has fewer than 3 vertices");
+  }
+  const int64_t nt = tri_offsets[n_geom], nv = vtx_offsets[n_geom];
+  if (nt > (int64_t)INT32_MAX / 2) return arg_error("hm_build_batch: too many triangles");
+  if (nv > (int64_t)INT32_MAX) return arg_error("hm_build_batch: too many vertices");
+  hm_status st = check_params(p, "hm_build_batch");
+  if (st != HM_OK) return st;
+  std::vector<int32_t> tri((size_t)3 * nt);
+  for (int32_t g = 0; g < n_geom; ++g) {
+    const int64_t t0 = tri_offsets[g], t1 = tri_offsets[g + 1], v0 = vtx_offsets[g];
+    st = check_mesh(vertices + 3 * v0, vtx_offsets[g + 1] - v0, triangles + 3 * t0, t1 - t0,
+                    "hm_build_batch: geometry " + std::to_string(g));
+    if (st != HM_OK) return st;
+    for (int64_t e = 3 * t0; e < 3 * t1; ++e) tri[e] = (int32_t)(triangles[e] + v0);
+  }
+  return build_handle(vertices, nv, tri.data(),
+                      std::vector<int64_t>(tri_offsets, tri_offsets + n_geom + 1), p, stream, out);
 }
 
 static hm_status matvec_common(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,

@@ -26,10 +26,11 @@ __global__ void k_centroids(const double* __restrict__ V, const int32_t* __restr
 
 // Per-block partial min/max of the centroids: out[blk][6].
 __global__ __launch_bounds__(256) void k_minmax_partial(const double* __restrict__ C, int64_t n,
+                                                        int64_t off, int64_t cnt,
                                                         double* __restrict__ out) {
   __shared__ double lds[6][256];
   double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+  for (int64_t t = off + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < off + cnt;
        t += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -79,13 +80,15 @@ __device__ inline uint64_t spread3(uint64_t x) {
   return x;
 }
 
-// Morton code of every collocation point (Sec. 3.1 "Spatial data structure"):
+// Morton code of the collocation points of one geometry, positions
+// [off, off + cnt) of the SoA array C (Sec. 3.1 "Spatial data structure"):
 // q_d = min(floor((c_d - a_d) * scale), 2^21 - 1); x is the most significant
 // bit of every triple.  Also initialises the value array of the sort.
-__global__ void k_morton(const double* __restrict__ C, int64_t n, double ax, double ay, double az,
-                         double scale, uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+__global__ void k_morton(const double* __restrict__ C, int64_t n, int64_t off, int64_t cnt,
+                         double ax, double ay, double az, double scale,
+                         uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
   const double a[3] = {ax, ay, az};
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+  for (int64_t t = off + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < off + cnt;
        t += (int64_t)gridDim.x * blockDim.x) {
     uint64_t q[3];
 #pragma unroll
@@ -346,19 +349,20 @@ void launch_centroids(const double* V, const int32_t* T, int64_t n, double* C, h
   HM_LAUNCH_CHECK();
 }
 
-void launch_minmax(const double* C, int64_t n, double* out6, hipStream_t s) {
-  const int nblk = (int)std::min<int64_t>(grid_for(n, kT), 1024);
+void launch_minmax(const double* C, int64_t n, int64_t off, int64_t cnt, double* out6,
+                   hipStream_t s) {
+  const int nblk = (int)std::min<int64_t>(grid_for(cnt, kT), 1024);
   double* part = dalloc_t<double>(6 * (size_t)nblk, s);
-  k_minmax_partial<<<nblk, kT, 0, s>>>(C, n, part);
+  k_minmax_partial<<<nblk, kT, 0, s>>>(C, n, off, cnt, part);
   HM_LAUNCH_CHECK();
   k_minmax_final<<<1, 64, 0, s>>>(part, nblk, out6);
   HM_LAUNCH_CHECK();
   dfree(part, s);
 }
 
-void launch_morton(const double* C, int64_t n, const double* a, double scale, uint64_t* keys,
-                   int32_t* idx, hipStream_t s) {
-  k_morton<<<grid_for(n, kT), kT, 0, s>>>(C, n, a[0], a[1], a[2], scale, keys, idx);
+void launch_morton(const double* C, int64_t n, int64_t off, int64_t cnt, const double* a,
+                   double scale, uint64_t* keys, int32_t* idx, hipStream_t s) {
+  k_morton<<<grid_for(cnt, kT), kT, 0, s>>>(C, n, off, cnt, a[0], a[1], a[2], scale, keys, idx);
   HM_LAUNCH_CHECK();
 }
 
@@ -375,12 +379,17 @@ template void launch_geom_sorted<double>(const double*, const int32_t*, const in
 
 // Builds the CBC tree level by level on the device.  Returns the number of
 // clusters; level_beg receives the first cluster of every level (plus end).
-int64_t build_cluster_tree(int64_t n, int leaf, Cluster* cl, int64_t cap,
+int64_t build_cluster_tree(const std::vector<int64_t>& goff, int leaf, Cluster* cl, int64_t cap,
                            std::vector<int64_t>& level_beg, hipStream_t s) {
-  const Cluster root = make_int4(0, (int)n, -1, 0);
-  HM_HIP(hipMemcpyAsync(cl, &root, sizeof(Cluster), hipMemcpyHostToDevice, s));
+  // one root per geometry, [goff[g], goff[g + 1]), all at level 0
+  const int64_t G = (int64_t)goff.size() - 1;
+  std::vector<Cluster> roots(G);
+  for (int64_t g = 0; g < G; ++g) roots[g] = make_int4((int)goff[g], (int)goff[g + 1], -1, 0);
+  if (G > cap) throw Error{HM_ERR_STATE, "cluster capacity exceeded"};
+  HM_HIP(hipMemcpyAsync(cl, roots.data(), G * sizeof(Cluster), hipMemcpyHostToDevice, s));
+  HM_HIP(hipStreamSynchronize(s));
   level_beg.assign(1, 0);
-  int64_t beg = 0, cnt = 1;
+  int64_t beg = 0, cnt = G;
   int64_t* flag = dalloc_t<int64_t>(cap, s);
   int64_t* off = dalloc_t<int64_t>(cap, s);
   int64_t* tot = dalloc_t<int64_t>(1, s);
@@ -431,16 +440,21 @@ void launch_boxes(const Cluster* cl, const std::vector<int64_t>& level_beg, cons
   }
 }
 
-// Level-wise Algorithm 1.  Returns the admissible and dense leaf lists
-// (device, owned by the caller) in level order.
-void build_block_tree(const Cluster* cl, const double* box, double eta, int leaf, int2** adm_out,
-                      int64_t* nadm, int2** dns_out, int64_t* ndns, int64_t* depth,
-                      hipStream_t s) {
+// Level-wise Algorithm 1, started from the root pair of every geometry.
+// Returns the admissible and dense leaf lists (device, owned by the caller)
+// in level order.
+void build_block_tree(const Cluster* cl, int64_t nroots, const double* box, double eta, int leaf,
+                      int2** adm_out, int64_t* nadm, int2** dns_out, int64_t* ndns,
+                      int64_t* depth, hipStream_t s) {
   std::vector<std::pair<int2*, int64_t>> adm_lv, dns_lv;
-  int2* cand = dalloc_t<int2>(1, s);
-  const int2 root = make_int2(0, 0);
-  HM_HIP(hipMemcpyAsync(cand, &root, sizeof(int2), hipMemcpyHostToDevice, s));
-  int64_t ncand = 1;
+  // traversal from (root_g, root_g) of every geometry: geometries never
+  // interact, so the operator is block diagonal over them
+  int2* cand = dalloc_t<int2>(nroots, s);
+  std::vector<int2> rp(nroots);
+  for (int64_t g = 0; g < nroots; ++g) rp[g] = make_int2((int)g, (int)g);
+  HM_HIP(hipMemcpyAsync(cand, rp.data(), nroots * sizeof(int2), hipMemcpyHostToDevice, s));
+  HM_HIP(hipStreamSynchronize(s));
+  int64_t ncand = nroots;
   const double eta2 = eta * eta;
   int64_t* tot = dalloc_t<int64_t>(3, s);
   int64_t lv = 0;

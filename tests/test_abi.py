@@ -30,7 +30,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(hm.Params) == 40
     assert ctypes.sizeof(hm.SolveParams) == 24
     assert ctypes.sizeof(hm.SolveInfo) == 24
-    assert ctypes.sizeof(hm.Stats) == 19 * 8
+    assert ctypes.sizeof(hm.Stats) == 20 * 8
 
 
 def test_defaults():
@@ -81,3 +81,43 @@ def test_null_handle_calls():
 def test_null_build_out():
     L = hm.lib()
     assert L.hm_build(None, 3, None, 1, None, None, None) == -1
+
+
+def _raw_batch(V, voff, T, toff, n_geom, p=None):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    T = np.ascontiguousarray(T, dtype=np.int32)
+    voff = np.ascontiguousarray(voff, dtype=np.int64)
+    toff = np.ascontiguousarray(toff, dtype=np.int64)
+    p = p or hm.hm_params_default()
+    h = ctypes.c_void_p()
+    st = hm.lib().hm_build_batch(V.ctypes.data, voff.ctypes.data, T.ctypes.data, toff.ctypes.data,
+                                 n_geom, ctypes.byref(p), None, ctypes.byref(h))
+    return st, h.value
+
+
+@pytest.mark.parametrize("case,what", [
+    ("n_geom0", "n_geom"), ("offsets", "start at 0"), ("empty", "no triangle"),
+    ("local_index", "out of range"), ("degenerate_second", "geometry 1"),
+])
+def test_invalid_batches_rejected(case, what):
+    V1, T1 = _tri()
+    V = np.concatenate([V1, V1 + 5.0])
+    T = np.concatenate([T1, T1])          # indices local to each mesh
+    voff, toff, G = [0, 3, 6], [0, 1, 2], 2
+    if case == "n_geom0":
+        G = 0
+    elif case == "offsets":
+        toff = [1, 1, 2]
+    elif case == "empty":
+        toff = [0, 1, 1]
+    elif case == "local_index":
+        T = np.concatenate([T1, T1 + 3])  # global instead of local indices
+    elif case == "degenerate_second":
+        V = np.concatenate([V1, np.zeros((3, 3))])
+    st, h = _raw_batch(V, voff, T, toff, G)
+    assert st == -1 and h is None and what in hm.hm_last_error()
+
+
+def test_null_build_batch_arguments():
+    L = hm.lib()
+    assert L.hm_build_batch(None, None, None, None, 1, None, None, None) == -1
