@@ -166,7 +166,16 @@ typedef struct {
   int32_t max_iter;    /* total Arnoldi steps allowed, >= 1                 */
   int32_t transpose;   /* 1: solve H^T s = f (adjoint), 0: H s = f          */
   int32_t use_x0;      /* 1: sigma holds the initial guess on entry         */
+  int32_t flags;       /* HM_SOLVE_GRAPH or 0                               */
+  int32_t pad;
 } hm_solve_params;
+
+/* hm_solve_params.flags: replay one captured HIP graph per Arnoldi step
+   (product, two Gram-Schmidt passes, norm) instead of launching its kernels
+   one by one.  The graph and the solve workspace ((restart + 1) basis
+   vectors) stay with the handle until the next solve with another nrhs,
+   restart or direction, or hm_free.  Results are bitwise those of flags = 0. */
+#define HM_SOLVE_GRAPH 1
 
 typedef struct {
   int32_t iters;          /* Arnoldi steps taken (max over right-hand sides) */

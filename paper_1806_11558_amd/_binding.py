@@ -11,6 +11,7 @@ import numpy as np
 HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE = -1, -2, -3, -4, -5
 HM_F64, HM_F32, HM_F32_F16 = 0, 1, 2
+HM_SOLVE_GRAPH = 1
 HM_STRICT = 1
 HM_PROFILE = 2
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
@@ -44,7 +45,8 @@ class Params(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("transpose", C.c_int32), ("use_x0", C.c_int32)]
+                ("transpose", C.c_int32), ("use_x0", C.c_int32), ("flags", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -276,10 +278,11 @@ class HMatrix:
         return self.matvec(x, out, stream, transpose=True)
 
     def solve(self, f, *, tol: float = 1e-8, restart: int = 100, max_iter: int = 1000,
-              transpose: bool = False, x0=None, stream=None):
+              transpose: bool = False, x0=None, graph: bool = False, stream=None):
         import torch
         sp = SolveParams(tol=tol, restart=restart, max_iter=max_iter,
-                         transpose=1 if transpose else 0, use_x0=0 if x0 is None else 1)
+                         transpose=1 if transpose else 0, use_x0=0 if x0 is None else 1,
+                         flags=HM_SOLVE_GRAPH if graph else 0)
         sigma = torch.empty_like(f) if x0 is None else x0.clone()
         st, info = hm_solve(self._h, f, sigma, sp, stream)
         return sigma, info, st

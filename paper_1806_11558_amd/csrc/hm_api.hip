@@ -50,6 +50,53 @@ void gmres_combine(const double* Q, int64_t ldq, const double* y, int nk, int64_
 void gmres_scale_cols(const double* a, const double* sc, int64_t n, int nr, double* out,
                       hipStream_t s);
 void gmres_sub(const double* a, const double* b, int64_t tot, double* out, hipStream_t s);
+void gmres_dots_dev(const double* Q, int64_t ldq, const int* jd, int nkmax, const double* w,
+                    int64_t n, int nr, double* part, double* out, hipStream_t s);
+void gmres_orth_update_dev(const double* Q, int64_t ldq, const double* h, const int* jd,
+                           int64_t n, int nr, double* w, hipStream_t s);
+void gmres_copy_col(const double* Q, int64_t ldq, const int* jd, double* out, hipStream_t s);
+
+// Device workspace of a solve.  With HM_SOLVE_GRAPH it stays with the handle
+// together with the instantiated graph of one Arnoldi step (product of the
+// current basis vector, two Gram-Schmidt passes, norm), which is replayed
+// for every step; the step index is read from device memory (jd).
+struct SolveWs {
+  int nr = 0, m = 0;
+  bool tr = false;
+  int64_t n = 0;
+  double *Q = nullptr, *fd = nullptr, *x = nullptr, *w = nullptr, *hdev = nullptr,
+         *part = nullptr, *scl = nullptr, *ydev = nullptr, *xin = nullptr;
+  int* jd = nullptr;
+  std::vector<void*> mem;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t free_stream = nullptr;
+  void alloc(int64_t n_, int nr_, int m_, bool tr_, hipStream_t s) {
+    n = n_, nr = nr_, m = m_, tr = tr_;
+    const int64_t nv = n * nr;
+    auto A = [&](size_t cnt) {
+      double* q = (double*)dalloc(cnt * sizeof(double), s);
+      mem.push_back(q);
+      return q;
+    };
+    Q = A((size_t)(m + 1) * nv);
+    fd = A(nv);
+    x = A(nv);
+    w = A(nv);
+    xin = A(nv);
+    hdev = A((size_t)(m + 2) * nr * 2 + nr);
+    part = A((size_t)(m + 2) * gmres_tiles(n) * nr);
+    scl = A(nr);
+    ydev = A((size_t)(m + 1) * nr);
+    jd = (int*)A(1);
+  }
+  ~SolveWs() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* q : mem) (void)hipFreeAsync(q, free_stream);
+    (void)hipStreamSynchronize(free_stream);
+  }
+};
 void convert_f32_to_f64(const float* a, int64_t tot, double* out, hipStream_t s);
 void convert_f64_to_f32(const double* a, int64_t tot, float* out, hipStream_t s);
 
@@ -96,6 +143,7 @@ struct hm_handle {
   Storage sto;
 
   void *z = nullptr, *w = nullptr, *ypart = nullptr;
+  std::unique_ptr<SolveWs> sws;         // graph-replay solve workspace
   int max_nr_t = 1;
   int grid = 1024;
 
@@ -582,28 +630,49 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
     auto apply = [&](const double* in, double* out) {
       matvec_dispatch(P, h->form, in, out, nr, 0, tr, s);
     };
-    // device workspace (freed at return)
-    std::vector<void*> tmp;
-    auto A = [&](size_t cnt) {
-      double* q = (double*)dalloc(cnt * sizeof(double), s);
-      tmp.push_back(q);
-      return q;
-    };
-    double* Q = A((size_t)(m + 1) * nv);
-    double* fd = A(nv);
-    double* x = A(nv);
-    double* w = A(nv);
-    double* hdev = A((size_t)(m + 2) * nr * 2);
-    double* part = A((size_t)(m + 2) * gmres_tiles(n) * nr);
-    double* scl = A(nr);
-    double* ydev = A((size_t)(m + 1) * nr);
-    struct Free {
-      std::vector<void*>& v;
-      hipStream_t s;
-      ~Free() {
-        for (void* q : v) dfree(q, s);
+    // device workspace: per call, or kept with the handle for graph replays
+    const bool use_graph = (sp->flags & HM_SOLVE_GRAPH) != 0;
+    std::unique_ptr<SolveWs> local;
+    SolveWs* ws = nullptr;
+    if (use_graph) {
+      if (!h->sws || h->sws->nr != nr || h->sws->m != m || h->sws->tr != tr) {
+        if (h->sws) h->sws->free_stream = s;
+        h->sws.reset(new SolveWs());
+        h->sws->alloc(n, nr, m, tr, s);
       }
-    } fr{tmp, s};
+      ws = h->sws.get();
+    } else {
+      local.reset(new SolveWs());
+      local->free_stream = s;
+      local->alloc(n, nr, m, tr, s);
+      ws = local.get();
+    }
+    double *Q = ws->Q, *fd = ws->fd, *x = ws->x, *w = ws->w, *hdev = ws->hdev, *part = ws->part,
+           *scl = ws->scl, *ydev = ws->ydev;
+    double* hnorm = hdev + (size_t)(m + 2) * nr * 2;   // |w| of the current step
+    if (use_graph && !ws->exec) {
+      // capture one Arnoldi step on a private stream (the caller's may be the
+      // null stream, which cannot capture); no profiling events inside
+      MvPlan Pg = P;
+      Pg.prof = nullptr;
+      hipStream_t cs = nullptr;
+      HM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      struct StreamGuard {
+        hipStream_t st;
+        ~StreamGuard() { (void)hipStreamDestroy(st); }
+      } sgd{cs};
+      HM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+      gmres_copy_col(Q, nv, ws->jd, ws->xin, cs);
+      matvec_dispatch(Pg, h->form, ws->xin, w, nr, 0, tr, cs);
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hp = hdev + (size_t)pass * (m + 2) * nr;
+        gmres_dots_dev(Q, nv, ws->jd, m + 1, w, n, nr, part, hp, cs);
+        gmres_orth_update_dev(Q, nv, hp, ws->jd, n, nr, w, cs);
+      }
+      gmres_dots(w, 0, 1, w, n, nr, part, hnorm, cs);
+      HM_HIP(hipStreamEndCapture(cs, &ws->graph));
+      HM_HIP(hipGraphInstantiate(&ws->exec, ws->graph, nullptr, nullptr, 0));
+    }
 
     if (dtype == HM_F32) {
       convert_f32_to_f64((const float*)f, nv, fd, s);
@@ -614,7 +683,7 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
     }
     if (!sp->use_x0) HM_HIP(hipMemsetAsync(x, 0, nv * sizeof(double), s));
 
-    std::vector<double> hv((size_t)(m + 2) * nr * 2);
+    std::vector<double> hv((size_t)(m + 2) * nr * 2 + nr);
     auto norms = [&](const double* v, std::vector<double>& out) {
       gmres_dots(v, 0, 1, v, n, nr, part, hdev, s);
       out.resize(nr);
@@ -658,21 +727,26 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
       }
       int j = 0;
       for (; j < m && total_it < sp->max_iter; ++j) {
-        double* qj = Q + (size_t)j * nv;
-        apply(qj, w);
-        // classical Gram-Schmidt, twice
-        for (int pass = 0; pass < 2; ++pass) {
-          gmres_dots(Q, nv, j + 1, w, n, nr, part, hdev + (size_t)pass * (m + 2) * nr, s);
-          gmres_orth_update(Q, nv, hdev + (size_t)pass * (m + 2) * nr, j + 1, n, nr, w, s);
+        if (use_graph) {
+          const int jh = j;
+          HM_HIP(hipMemcpyAsync(ws->jd, &jh, sizeof(int), hipMemcpyHostToDevice, s));
+          HM_HIP(hipGraphLaunch(ws->exec, s));
+        } else {
+          double* qj = Q + (size_t)j * nv;
+          apply(qj, w);
+          // classical Gram-Schmidt, twice
+          for (int pass = 0; pass < 2; ++pass) {
+            gmres_dots(Q, nv, j + 1, w, n, nr, part, hdev + (size_t)pass * (m + 2) * nr, s);
+            gmres_orth_update(Q, nv, hdev + (size_t)pass * (m + 2) * nr, j + 1, n, nr, w, s);
+          }
+          gmres_dots(w, 0, 1, w, n, nr, part, hnorm, s);
         }
-        gmres_dots(w, 0, 1, w, n, nr, part, hdev + (size_t)(j + 1) * nr, s);
-        HM_HIP(hipMemcpyAsync(hv.data(), hdev, (size_t)(m + 2) * nr * 2 * sizeof(double),
-                              hipMemcpyDeviceToHost, s));
+        HM_HIP(hipMemcpyAsync(hv.data(), hdev, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HM_HIP(hipStreamSynchronize(s));
         ++total_it;
         bool any = false;
         for (int c = 0; c < nr; ++c) {
-          const double hn = std::sqrt(std::max(hv[(size_t)(j + 1) * nr + c], 0.0));
+          const double hn = std::sqrt(std::max(hv[(size_t)(m + 2) * nr * 2 + c], 0.0));
           sc[c] = 0.0;
           if (!active[c]) continue;
           double* Hc = H.data() + (size_t)c * (m + 1) * m;

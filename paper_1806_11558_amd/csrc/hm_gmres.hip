@@ -102,7 +102,87 @@ __global__ void k_convert(const S* __restrict__ a, int64_t tot, D* __restrict__ 
     out[e] = (D)a[e];
 }
 
+// Variants for graph replays: the Arnoldi step j is read from device memory
+// (jd[0]); the grids cover the largest step, blocks past it return at once.
+__global__ __launch_bounds__(kGT) void k_dots_dev(const double* __restrict__ Q, int64_t ldq,
+                                                  const int* __restrict__ jd,
+                                                  const double* __restrict__ w, int64_t n, int nr,
+                                                  int tiles, double* __restrict__ part) {
+  if ((int)blockIdx.y > jd[0]) return;               // uniform over the block
+  __shared__ double lds[kGT];
+  const int tile = blockIdx.x, k = blockIdx.y;
+  const double* q = Q + (int64_t)k * ldq;
+  const int per = kGT / nr;
+  const int c = threadIdx.x % nr, r0 = threadIdx.x / nr;
+  double acc = 0.0;
+  if (r0 < per) {
+    const int64_t beg = (int64_t)tile * kRowsPerTile;
+    const int64_t end = min(beg + kRowsPerTile, n);
+    for (int64_t i = beg + r0; i < end; i += per) acc += q[i * nr + c] * w[i * nr + c];
+  }
+  lds[threadIdx.x] = (r0 < per) ? acc : 0.0;
+  __syncthreads();
+  if (threadIdx.x < nr) {
+    double s = 0.0;
+    for (int t = 0; t < per; ++t) s += lds[t * nr + threadIdx.x];
+    part[((int64_t)k * tiles + tile) * nr + threadIdx.x] = s;
+  }
+}
+
+__global__ void k_dots_final_dev(const double* __restrict__ part, const int* __restrict__ jd,
+                                 int nkmax, int tiles, int nr, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nk = jd[0] + 1;
+  if (e >= nk * nr || e >= nkmax * nr) return;
+  const int k = e / nr, c = e % nr;
+  double s = 0.0;
+  for (int t = 0; t < tiles; ++t) s += part[((int64_t)k * tiles + t) * nr + c];
+  out[e] = s;
+}
+
+__global__ void k_orth_update_dev(const double* __restrict__ Q, int64_t ldq,
+                                  const double* __restrict__ h, const int* __restrict__ jd,
+                                  int64_t n, int nr, double* __restrict__ w) {
+  const int nk = jd[0] + 1;
+  const int64_t tot = n * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nr);
+    double v = w[e];
+    for (int k = 0; k < nk; ++k) v -= Q[(int64_t)k * ldq + e] * h[k * nr + c];
+    w[e] = v;
+  }
+}
+
+// out = Q[jd[0]] (the Arnoldi vector of step j, into a fixed buffer)
+__global__ void k_copy_col(const double* __restrict__ Q, int64_t ldq, const int* __restrict__ jd,
+                           double* __restrict__ out) {
+  const double* q = Q + (int64_t)jd[0] * ldq;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ldq;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = q[e];
+}
+
 // ------------------------------------------------------------------ launchers
+void gmres_dots_dev(const double* Q, int64_t ldq, const int* jd, int nkmax, const double* w,
+                    int64_t n, int nr, double* part, double* out, hipStream_t s) {
+  const int tiles = gmres_tiles(n);
+  dim3 grid(tiles, nkmax);
+  k_dots_dev<<<grid, kGT, 0, s>>>(Q, ldq, jd, w, n, nr, tiles, part);
+  HM_LAUNCH_CHECK();
+  k_dots_final_dev<<<(unsigned)ceil_div(nkmax * nr, 256), 256, 0, s>>>(part, jd, nkmax, tiles, nr,
+                                                                        out);
+  HM_LAUNCH_CHECK();
+}
+void gmres_orth_update_dev(const double* Q, int64_t ldq, const double* h, const int* jd,
+                           int64_t n, int nr, double* w, hipStream_t s) {
+  k_orth_update_dev<<<grid_for(n * nr, 256, 8192), 256, 0, s>>>(Q, ldq, h, jd, n, nr, w);
+  HM_LAUNCH_CHECK();
+}
+void gmres_copy_col(const double* Q, int64_t ldq, const int* jd, double* out, hipStream_t s) {
+  k_copy_col<<<grid_for(ldq, 256, 8192), 256, 0, s>>>(Q, ldq, jd, out);
+  HM_LAUNCH_CHECK();
+}
 void gmres_dots(const double* Q, int64_t ldq, int nk, const double* w, int64_t n, int nr,
                 double* part, double* out, hipStream_t s) {
   const int tiles = gmres_tiles(n);

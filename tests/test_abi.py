@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(hm.Params) == 40
-    assert ctypes.sizeof(hm.SolveParams) == 24
+    assert ctypes.sizeof(hm.SolveParams) == 32
     assert ctypes.sizeof(hm.SolveInfo) == 24
     assert ctypes.sizeof(hm.Stats) == 20 * 8
 
