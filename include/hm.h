@@ -79,13 +79,17 @@ typedef enum {
 #define HM_PROFILE 2      /* products record HIP events around each kernel on
                              the caller's stream and synchronise it at the
                              end of the call; totals via HM_Q_KERNEL_TIMES   */
+#define HM_AUTOTUNE 4     /* the build times the one-column product with
+                             each column-unit width of its schedule
+                             (512 .. 8192) on its own storage and keeps the
+                             fastest; measurements via HM_Q_TUNE             */
 
 typedef struct {
   int32_t leaf_size;        /* C_leaf of (C3); 1..64.  Paper: 32             */
   int32_t max_rank;         /* ACA rank cap k_max; 1..256; 0 => 64.  The cap
                                is also limited by min(m, n) of each block     */
   int32_t precision;        /* hm_precision                                   */
-  int32_t flags;            /* HM_STRICT | HM_PROFILE                         */
+  int32_t flags;            /* HM_STRICT | HM_PROFILE | HM_AUTOTUNE           */
   double eta;               /* admissibility parameter eta >= 0.  Paper: 1.0 */
   double aca_eps;           /* relative Frobenius stopping tolerance of ACA;
                                0 => fixed-rank mode (every block gets
@@ -221,13 +225,16 @@ typedef enum {
   HM_Q_LR_FACTORS = 9,    /* for LR block b = *(int64*)dst on entry: the
                              dense factors U (m x r) then V (n x r), both
                              column-major, in the build's storage type        */
-  HM_Q_KERNEL_TIMES = 10  /* double[2][HM_NKERNEL]: accumulated milliseconds
+  HM_Q_KERNEL_TIMES = 10, /* double[2][HM_NKERNEL]: accumulated milliseconds
                              and launch counts of the product stages since
                              the build or the last query (reset on read);
                              needs HM_PROFILE.  Stages: forward gather,
                              forward V^T x, (unused), forward panels, then
                              transposed gather, transposed panel dots,
                              transposed block sums, transposed column leaves */
+  HM_Q_TUNE = 11          /* double[k][2] (unit columns, ms per one-column
+                             product) of every width the autotuner timed;
+                             k = 0 without HM_AUTOTUNE                       */
 } hm_query_kind;
 
 #define HM_NPHASE 8        /* geometry, morton+sort, tree+boxes, partition,
@@ -250,6 +257,7 @@ typedef struct {
   int64_t precision;
   int64_t aca_chunks;
   int64_t n_geom;           /* geometries in the handle                      */
+  int64_t unit_cols;        /* column-unit width of the product schedule     */
 } hm_stats;
 
 /*

@@ -12,10 +12,12 @@ HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE = -1, -2, -3, -4, -5
 HM_F64, HM_F32, HM_F32_F16 = 0, 1, 2
 HM_SOLVE_GRAPH = 1
+HM_AUTOTUNE = 4
 HM_STRICT = 1
 HM_PROFILE = 2
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
- HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES) = range(11)
+ HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES,
+ HM_Q_TUNE) = range(12)
 HM_NPHASE = 8
 HM_NKERNEL = 8
 KERNELS = ("fwd_gather", "fwd_vtx", "fwd_unused", "fwd_panels",
@@ -58,7 +60,8 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n", "n_clusters", "n_leaves", "n_dense", "n_lr", "depth", "dense_entries",
         "lr_entries", "lr_u_entries", "stored_bytes", "rank_sum", "rank_max", "cap_hits", "aca_entry_evals",
-        "n_panel_cols", "n_titems", "device_bytes", "precision", "aca_chunks", "n_geom")]
+        "n_panel_cols", "n_titems", "device_bytes", "precision", "aca_chunks", "n_geom",
+        "unit_cols")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -81,6 +84,12 @@ def lib():
     if not os.path.exists(path):
         raise HMLibraryMissing(
             f"{path} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    try:
+        # load torch's HIP runtime first, so that the library and torch share
+        # one runtime (same soname) and device pointers move freely between them
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.hm_params_default.argtypes = [C.POINTER(Params)]
@@ -231,9 +240,9 @@ class HMatrix:
     def __init__(self, vertices, triangles, *, leaf_size: int = 32, eta: float = 1.0,
                  eps: float = 1e-6, max_rank: int = 64, precision: str = "f64",
                  strict: bool = False, profile: bool = False, mem_limit_bytes: int = 0,
-                 stream=None):
+                 autotune: bool = False, stream=None):
         p = self._params(leaf_size, eta, eps, max_rank, precision, strict, profile,
-                         mem_limit_bytes)
+                         mem_limit_bytes, autotune)
         self.n = int(np.asarray(triangles).shape[0])
         self.offsets = np.array([0, self.n], dtype=np.int64)
         self._h = hm_build(vertices, triangles, p, stream)
@@ -241,26 +250,29 @@ class HMatrix:
     @classmethod
     def batch(cls, meshes, *, leaf_size: int = 32, eta: float = 1.0, eps: float = 1e-6,
               max_rank: int = 64, precision: str = "f64", strict: bool = False,
-              profile: bool = False, mem_limit_bytes: int = 0, stream=None):
+              profile: bool = False, mem_limit_bytes: int = 0, autotune: bool = False,
+              stream=None):
         """One handle for several meshes [(vertices, triangles), ...]
         (hm_build_batch); unknowns are the triangles in concatenated order."""
         self = cls.__new__(cls)
         p = self._params(leaf_size, eta, eps, max_rank, precision, strict, profile,
-                         mem_limit_bytes)
+                         mem_limit_bytes, autotune)
         sizes = [int(np.asarray(t).shape[0]) for _, t in meshes]
         self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         self.n = int(self.offsets[-1])
         self._h = hm_build_batch(meshes, p, stream)
         return self
 
-    def _params(self, leaf_size, eta, eps, max_rank, precision, strict, profile, mem_limit_bytes):
+    def _params(self, leaf_size, eta, eps, max_rank, precision, strict, profile, mem_limit_bytes,
+                autotune=False):
         p = hm_params_default()
         p.leaf_size = leaf_size
         p.eta = eta
         p.aca_eps = eps
         p.max_rank = max_rank
         p.precision = {"f64": HM_F64, "f32": HM_F32, "f16": HM_F32_F16}[precision]
-        p.flags = (HM_STRICT if strict else 0) | (HM_PROFILE if profile else 0)
+        p.flags = ((HM_STRICT if strict else 0) | (HM_PROFILE if profile else 0)
+                   | (HM_AUTOTUNE if autotune else 0))
         p.mem_limit_bytes = mem_limit_bytes
         self.params = p
         self.storage_dtype = np.float64 if precision == "f64" else np.float32
@@ -297,6 +309,15 @@ class HMatrix:
         t = np.zeros(HM_NPHASE, dtype=np.float64)
         hm_query(self._h, HM_Q_TIMINGS, t)
         return dict(zip(PHASES, t.tolist()))
+
+    def tune_results(self) -> np.ndarray:
+        """[k, 2] (unit columns, ms per one-column product) timed by the
+        autotuner (empty without autotune=True)."""
+        need = hm_query(self._h, HM_Q_TUNE)
+        out = np.zeros(need // 8, dtype=np.float64)
+        if need:
+            hm_query(self._h, HM_Q_TUNE, out)
+        return out.reshape(-1, 2)
 
     def kernel_times(self) -> dict:
         """Accumulated product-kernel milliseconds and launch counts since the

@@ -2,6 +2,7 @@
 // clustering, level-wise block tree, batched near field, batched ACA), the
 // products and the GMRES loop.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -106,6 +107,8 @@ void set_error(const std::string& msg) { g_err = msg; }
 
 constexpr int kMaxNr = 16;   // right-hand sides per product pass
 constexpr int kMaxGeoms = 65536;
+// unit widths the product autotuner tries, the smallest first
+constexpr int kTuneCols[] = {512, 1024, 2048, 4096, 8192};
 
 }  // namespace hm
 
@@ -144,6 +147,7 @@ struct hm_handle {
 
   void *z = nullptr, *w = nullptr, *ypart = nullptr;
   std::unique_ptr<SolveWs> sws;         // graph-replay solve workspace
+  std::vector<std::array<double, 2>> tune;   // autotuner: (unit columns, ms)
   int max_nr_t = 1;
   int grid = 1024;
 
@@ -249,6 +253,55 @@ int64_t scan_total(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hip
 }
 
 // ---------------------------------------------------------------- the build
+// Autotuner of the product schedule: the width of the column units of the
+// per-leaf kernels decides how evenly the panels spread over the CUs
+// against how many partial rows are summed.  Every candidate is timed on
+// this handle's own storage (one untimed and three timed one-column
+// products of a zero vector; the work does not depend on the values) and the
+// fastest is kept.
+void autotune_units(hm_handle* h, hipStream_t s) {
+  const int64_t n = h->n;
+  double* xt = dalloc_t<double>(n, s);
+  double* yt = dalloc_t<double>(n, s);
+  HM_HIP(hipMemsetAsync(xt, 0, n * sizeof(double), s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HM_HIP(hipEventCreate(&e0));
+  HM_HIP(hipEventCreate(&e1));
+  struct Guard {
+    hipEvent_t a, b;
+    ~Guard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } gd{e0, e1};
+  const bool prof = h->profiling;
+  h->profiling = false;
+  h->tune.clear();
+  int best = h->sto.unit_cols;
+  float best_ms = 0.f;
+  for (int ucols : kTuneCols) {
+    make_units(h->sto, h->ldpre, h->nleaf, ucols, [h](size_t b) { return h->alloc(b); }, s);
+    const MvPlan P = h->plan();
+    matvec_dispatch(P, h->form, xt, yt, 1, 0, false, s);
+    HM_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) matvec_dispatch(P, h->form, xt, yt, 1, 0, false, s);
+    HM_HIP(hipEventRecord(e1, s));
+    HM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms /= 3.f;
+    h->tune.push_back({(double)ucols, (double)ms});
+    if (best_ms == 0.f || ms < best_ms) {
+      best_ms = ms;
+      best = ucols;
+    }
+  }
+  make_units(h->sto, h->ldpre, h->nleaf, best, [h](size_t b) { return h->alloc(b); }, s);
+  h->profiling = prof;
+  dfree(xt, s);
+  dfree(yt, s);
+}
+
 template <typename T, typename TL>
 void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T_host,
                 hipStream_t s) {
@@ -379,7 +432,13 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   // ---- product workspace: z = [x ; t] with 16 columns, w for the
   // transposed product sized to at most 2 GB (fewer columns per pass)
   h->z = h->alloc((size_t)(n + h->sto.toff_total + 1) * kMaxNr * sizeof(double));
-  h->ypart = h->alloc((size_t)(h->sto.nunits + 1) * h->sto.ldmax * kMaxNr * sizeof(double));
+  {
+    // partial rows for the most units any unit size of the tuner produces
+    int64_t nu = h->sto.nunits;
+    if (p.flags & HM_AUTOTUNE)
+      nu = std::max(nu, count_units(h->sto, h->nleaf, kTuneCols[0], s));
+    h->ypart = h->alloc((size_t)(nu + 1) * h->sto.ldmax * kMaxNr * sizeof(double));
+  }
   {
     const int64_t cols = h->sto.ncols + 1;
     int nrt = kMaxNr;
@@ -393,6 +452,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   h->grid = std::max(ncu, 1) * 32;
   HM_HIP(hipStreamSynchronize(s));
   h->ms[6] += ms_since(t0);
+  if (p.flags & HM_AUTOTUNE) autotune_units(h, s);
   dfree(tmp, s);
   release_cached_memory(s);
 
@@ -437,6 +497,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   st.precision = h->form;
   st.aca_chunks = h->sto.nchunks;
   st.n_geom = (int64_t)h->goff.size() - 1;
+  st.unit_cols = h->sto.unit_cols;
   h->ms[7] = ms_since(t_start);
   if ((p.flags & HM_STRICT) && st.cap_hits > 0)
     throw Error{HM_ERR_ACA, std::to_string(st.cap_hits) + " blocks reached max_rank"};
@@ -475,7 +536,7 @@ hm_status check_params(const hm_params* p, const char* who) {
   if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps))
     return arg_error(w + ": aca_eps must be finite and >= 0");
   if (p->mem_limit_bytes < 0) return arg_error(w + ": mem_limit_bytes < 0");
-  if (p->flags & ~(HM_STRICT | HM_PROFILE)) return arg_error(w + ": unknown flag");
+  if (p->flags & ~(HM_STRICT | HM_PROFILE | HM_AUTOTUNE)) return arg_error(w + ": unknown flag");
   return HM_OK;
 }
 
@@ -867,6 +928,16 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
           o[HM_NKERNEL + k] = h->prof.launches[k];
           h->prof.ms[k] = 0;
           h->prof.launches[k] = 0;
+        }
+        return HM_OK;
+      }
+      case HM_Q_TUNE: {
+        const int64_t b = (int64_t)h->tune.size() * 16;
+        if (!check(b)) return arg_error("hm_query: destination too small");
+        double* o = (double*)dst;
+        for (size_t k = 0; k < h->tune.size(); ++k) {
+          o[2 * k] = h->tune[k][0];
+          o[2 * k + 1] = h->tune[k][1];
         }
         return HM_OK;
       }

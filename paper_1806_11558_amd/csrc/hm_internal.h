@@ -113,7 +113,7 @@ struct MvProfile {
 struct Unit {
   int32_t leaf, run, a, w;
 };
-constexpr int kUnitCols = 2048;
+constexpr int kUnitCols = 1024;
 
 struct MvPlan {
   const Run* runs;          // [nruns][nleaf]
@@ -169,6 +169,7 @@ struct Storage {
   int nruns = 0;
   Unit* units = nullptr;
   int64_t nunits = 0;
+  int unit_cols = 0;
   int32_t* ubeg = nullptr;
   int ldmax = 0;
   float* su = nullptr;       // per-term scales when the factors are FP16
@@ -185,6 +186,9 @@ using Alloc = std::function<void*(size_t)>;
 template <typename T, typename TL>
 void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Alloc& alloc,
                    hipStream_t s);
+void make_units(Storage& out, const int64_t* ldpre, int64_t nleaf, int ucols, const Alloc& alloc,
+                hipStream_t s);
+int64_t count_units(const Storage& out, int64_t nleaf, int ucols, hipStream_t s);
 template <typename TL, typename TO>
 void launch_unpack(const int2* lr, int64_t b, const Cluster* cl, const int32_t* leaf_lo,
                    const int32_t* leaf_m, const int64_t* ldpre, const int2* cl_leaves,

@@ -1145,6 +1145,51 @@ void panel_layout(const int2* blk, int64_t nb, const Cluster* cl, const int2* cl
 }
 }  // namespace
 
+// Work units of the per-row-leaf product kernels: every run of every leaf
+// cut into pieces of at most ucols columns, grouped by leaf.
+void make_units(Storage& out, const int64_t* ldpre, int64_t nleaf, int ucols, const Alloc& alloc,
+                hipStream_t s) {
+  std::vector<Run> hr((size_t)out.nruns * nleaf);
+  std::vector<int64_t> hld(nleaf + 1);
+  if (!hr.empty())
+    HM_HIP(hipMemcpyAsync(hr.data(), out.runs, hr.size() * sizeof(Run), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipMemcpyAsync(hld.data(), ldpre, (nleaf + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  std::vector<Unit> hu;
+  std::vector<int32_t> hb(nleaf + 1);
+  out.ldmax = 1;
+  for (int64_t c = 0; c < nleaf; ++c) {
+    hb[c] = (int32_t)hu.size();
+    out.ldmax = std::max(out.ldmax, (int)(hld[c + 1] - hld[c]));
+    for (int k = 0; k < out.nruns; ++k) {
+      const int64_t w = hr[(size_t)k * nleaf + c].w;
+      for (int64_t a = 0; a < w; a += ucols)
+        hu.push_back(Unit{(int32_t)c, k, (int32_t)a, (int32_t)std::min<int64_t>(ucols, w - a)});
+    }
+  }
+  if (hu.size() >= (size_t)INT32_MAX) throw Error{HM_ERR_STATE, "too many product units"};
+  hb[nleaf] = (int32_t)hu.size();
+  out.nunits = (int64_t)hu.size();
+  out.unit_cols = ucols;
+  out.units = static_cast<Unit*>(alloc((hu.size() + 1) * sizeof(Unit)));
+  out.ubeg = static_cast<int32_t*>(alloc(hb.size() * sizeof(int32_t)));
+  if (!hu.empty())
+    HM_HIP(hipMemcpyAsync(out.units, hu.data(), hu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
+  HM_HIP(hipMemcpyAsync(out.ubeg, hb.data(), hb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HM_HIP(hipStreamSynchronize(s));
+}
+
+// Number of units make_units would produce for ucols.
+int64_t count_units(const Storage& out, int64_t nleaf, int ucols, hipStream_t s) {
+  std::vector<Run> hr((size_t)out.nruns * nleaf);
+  if (!hr.empty())
+    HM_HIP(hipMemcpyAsync(hr.data(), out.runs, hr.size() * sizeof(Run), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  int64_t cnt = 0;
+  for (const Run& r : hr) cnt += (r.w + ucols - 1) / ucols;
+  return cnt;
+}
+
 template <typename T, typename TL>
 void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Alloc& alloc,
                    hipStream_t s) {
@@ -1330,37 +1375,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   for (int k = 0; k < out.nruns; ++k)
     HM_HIP(hipMemcpyAsync(out.runs + (int64_t)k * nleaf, run_parts[k], nleaf * sizeof(Run),
                           hipMemcpyDeviceToDevice, s));
-  // work units: every run of every leaf cut into pieces of at most kUnitCols
-  {
-    std::vector<Run> hr((size_t)out.nruns * nleaf);
-    std::vector<int64_t> hld(nleaf + 1);
-    if (!hr.empty())
-      HM_HIP(hipMemcpyAsync(hr.data(), out.runs, hr.size() * sizeof(Run), hipMemcpyDeviceToHost, s));
-    HM_HIP(hipMemcpyAsync(hld.data(), in.ldpre, (nleaf + 1) * sizeof(int64_t),
-                          hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
-    std::vector<Unit> hu;
-    std::vector<int32_t> hb(nleaf + 1);
-    out.ldmax = 1;
-    for (int64_t c = 0; c < nleaf; ++c) {
-      hb[c] = (int32_t)hu.size();
-      out.ldmax = std::max(out.ldmax, (int)(hld[c + 1] - hld[c]));
-      for (int k = 0; k < out.nruns; ++k) {
-        const int64_t w = hr[(size_t)k * nleaf + c].w;
-        for (int64_t a = 0; a < w; a += kUnitCols)
-          hu.push_back(Unit{(int32_t)c, k, (int32_t)a, (int32_t)std::min<int64_t>(kUnitCols, w - a)});
-      }
-    }
-    if (hu.size() >= (size_t)INT32_MAX) throw Error{HM_ERR_STATE, "too many product units"};
-    hb[nleaf] = (int32_t)hu.size();
-    out.nunits = (int64_t)hu.size();
-    out.units = static_cast<Unit*>(alloc((hu.size() + 1) * sizeof(Unit)));
-    out.ubeg = static_cast<int32_t*>(alloc(hb.size() * sizeof(int32_t)));
-    if (!hu.empty())
-      HM_HIP(hipMemcpyAsync(out.units, hu.data(), hu.size() * sizeof(Unit), hipMemcpyHostToDevice, s));
-    HM_HIP(hipMemcpyAsync(out.ubeg, hb.data(), hb.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    HM_HIP(hipStreamSynchronize(s));
-  }
+  make_units(out, in.ldpre, nleaf, kUnitCols, alloc, s);
   out.ncols = out.dense_cols + ucols;
   out.colmap = static_cast<int32_t*>(alloc((out.ncols + 1) * sizeof(int32_t)));
   {
