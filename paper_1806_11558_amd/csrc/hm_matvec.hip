@@ -382,11 +382,13 @@ __device__ inline void fwd2_run(const Run& rn, int a, int uw, int ld, int C, int
   }
 }
 
-// Few right-hand sides: the workgroup first gathers the z values of a tile
-// of kZTile panel columns into LDS (one load per column instead of one per
-// lane, and no map -> z dependency inside the streaming loop), then streams
-// the tile's columns.  Same column order per lane as fwd2_run.
-constexpr int kZTile = 1024;
+// The workgroup first gathers the z values of a tile of panel columns into
+// LDS (one load per column instead of one per lane, and no map -> z
+// dependency inside the streaming loop), then streams the tile's columns.
+// Same column order per lane as fwd2_run.  A tile holds kZTileBytes of z.
+constexpr int kZTileBytes = 8192;
+template <typename A, int NR>
+constexpr int z_tile() { return kZTileBytes / (int)(NR * sizeof(A)); }
 
 template <typename T, typename A, int NR, int G>
 __device__ inline void fwd2_run_lds(const Run& rn, int a, int uw, int ld, int C, int cg, int g,
@@ -397,8 +399,9 @@ __device__ inline void fwd2_run_lds(const Run& rn, int a, int uw, int ld, int C,
   static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
   const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
   const int32_t* map = colmap + rn.col0 + a;
-  for (int t0 = 0; t0 < uw; t0 += kZTile) {
-    const int tw = min(kZTile, uw - t0);
+  constexpr int kTile = z_tile<A, NR>();
+  for (int t0 = 0; t0 < uw; t0 += kTile) {
+    const int tw = min(kTile, uw - t0);
     __syncthreads();                                   // the previous tile is consumed
     for (int c = threadIdx.x; c < tw; c += blockDim.x) {
       A v[NR];
@@ -441,9 +444,9 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, MvLe
                                               const A* __restrict__ z, A* __restrict__ ypart,
                                               int ldmax) {
   constexpr int G = Gran<TD>::G;
-  constexpr bool kLds = NR <= 2;
+  constexpr bool kLds = true;
   __shared__ A ybuf[4][kMaxLeaf][NR];
-  __shared__ A zt[kLds ? kZTile * NR : 1];
+  __shared__ A zt[kLds ? z_tile<A, NR>() * NR : 1];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t per = (nunits + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
