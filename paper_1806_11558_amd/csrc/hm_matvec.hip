@@ -526,6 +526,160 @@ __global__ __launch_bounds__(256) void k_fwd2_sum(MvLeaves L, const int32_t* __r
   }
 }
 
+// ------------------------------------------------------------------ many right-hand sides on MFMA
+// With 8 or 16 right-hand sides in double, both forward phases are small
+// dense products with a long inner dimension: phase 1 is T_b = V_b^T X
+// (terms x right-hand sides, inner dimension = rows of sigma), phase 2 is
+// Y_c += P Z (rows of the leaf x right-hand sides, inner dimension = panel
+// columns).  Both run on v_mfma_f64_16x16x4: C[16][16] += A[16][4] B[4][16]
+// with, for lane l, a = A[l % 16][l / 16], b = B[l / 16][l % 16], and item
+// j of the accumulator = C[4 j + l / 16][l % 16].  Stored values are
+// widened to double; accumulation is in double as on the vector path.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline double widen(T v) { return (double)v; }
+
+// Phase 1: one wavefront per admissible block, term tiles of 16 (up to four
+// per pass), rows in quads.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, int64_t nl,
+                                               MvLeaves L, const double* __restrict__ zx,
+                                               double* __restrict__ zt, int64_t n,
+                                               const float* __restrict__ su) {
+  static_assert(NR == 8 || NR == 16, "MFMA phase 1 takes 8 or 16 right-hand sides");
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lq = lane >> 4;     // a: term lr, row lq; b: row lq, rhs lr
+  const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t b = wid; b < nl; b += nw) {
+    const LrMeta M = meta[b];
+    const int r = M.r;
+    if (r == 0) continue;
+    for (int tg = 0; tg < r; tg += 64) {
+      const int ntile = min(4, (r - tg + 15) / 16);
+      f64x4 acc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+      const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
+      int lo = L.lo[M.sf];                  // the leaves of sigma are consecutive
+      for (int lf = M.sf; lf <= M.sl; ++lf) {
+        const int m = L.m[lf];
+        const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+        for (int i0 = 0; i0 < m; i0 += 4) {
+          const int i = i0 + lq;               // < ld: ld is m rounded up to 4
+          const double bv = (i < m && lr < NR) ? zx[(int64_t)(lo + i) * NR + lr] : 0.0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (t < ntile) {                   // uniform over the wavefront
+              const int term = tg + t * 16 + lr;
+              const double av = term < r ? widen(S[(int64_t)term * ld + i]) : 0.0;
+              acc[t] = mfma16(av, bv, acc[t]);
+            }
+          }
+        }
+        S += (int64_t)ld * r;
+        lo += m;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < ntile) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int term = tg + t * 16 + 4 * j + lq;
+            if (term < r && lr < NR) {
+              const double sc = su ? (double)su[M.toff + term] : 1.0;
+              zt[(n + M.toff + term) * NR + lr] = acc[t][j] * sc;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Phase 2: one workgroup per work unit; the unit's z values are staged in
+// LDS per tile, each wavefront takes column quads round-robin and keeps one
+// accumulator per 16-row tile of the leaf; the four wavefronts are added in
+// LDS in a fixed order.
+template <typename TD, typename TL, int NR>
+__global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvLeaves L,
+                                               const Unit* __restrict__ units, int64_t nunits,
+                                               const int32_t* __restrict__ colmap,
+                                               const double* __restrict__ z,
+                                               double* __restrict__ ypart, int ldmax) {
+  static_assert(NR == 8 || NR == 16, "MFMA phase 2 takes 8 or 16 right-hand sides");
+  constexpr int kTile = z_tile<double, NR>();
+  __shared__ double zs[kTile * NR];
+  __shared__ double ybuf[4][kMaxLeaf][NR];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lq = lane >> 4;     // a: row lr, column lq; b: column lq, rhs lr
+  const int64_t per = (nunits + kXcds - 1) / kXcds;
+  for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
+    const int64_t u = xcd_item(li, per);
+    if (u >= nunits) continue;                          // uniform over the workgroup
+    const Unit U = units[u];
+    const int64_t c = U.leaf;
+    const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
+    const int m = L.m[c];
+    const int nrt = (ld + 15) / 16;                     // 16-row tiles, at most 4
+    const Run rn = runs[(int64_t)U.run * L.nleaf + c];
+    const bool dense = std::is_same<TD, TL>::value || U.run == 0;
+    const int32_t* map = colmap + rn.col0 + U.a;
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < U.w; t0 += kTile) {
+      const int tw = min(kTile, U.w - t0);
+      __syncthreads();                                  // the previous tile is consumed
+      for (int e = threadIdx.x; e < tw * NR; e += blockDim.x) {
+        const int col = e / NR, k = e % NR;
+        zs[e] = z[(int64_t)map[t0 + col] * NR + k];
+      }
+      __syncthreads();
+      const int64_t cbase = (int64_t)U.a + t0;          // first panel column of the tile
+      for (int q = wave; q * 4 < tw; q += 4) {
+        const int col = q * 4 + lq;
+        const bool okc = col < tw;
+        const double bv = (okc && lr < NR) ? zs[col * NR + lr] : 0.0;
+        const int64_t coff = (cbase + (okc ? col : 0)) * ld;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (t < nrt) {                                // uniform over the wavefront
+            const int row = t * 16 + lr;
+            double av = 0.0;
+            if (okc && row < ld)
+              av = dense ? widen(reinterpret_cast<const TD*>((uintptr_t)rn.data)[coff + row])
+                         : widen(reinterpret_cast<const TL*>((uintptr_t)rn.data)[coff + row]);
+            acc[t] = mfma16(av, bv, acc[t]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < nrt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = t * 16 + 4 * j + lq;
+          if (row < kMaxLeaf && lr < NR) ybuf[wave][row][lr] = acc[t][j];
+        }
+      }
+    }
+    __syncthreads();
+    double* yp = ypart + u * ldmax * NR;
+    for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
+      const int row = e / NR, k = e % NR;
+      yp[e] = ((ybuf[0][row][k] + ybuf[1][row][k]) + ybuf[2][row][k]) + ybuf[3][row][k];
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ transposed, phase 1
 // Per row leaf: w[col0 + j] = sum_i P[i][j] x_c[i] for every panel column.
 template <typename T, typename A, int NR, int G>
@@ -729,7 +883,9 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
     if (P.nlr > 0) {
-      if constexpr (NR >= 4) {
+      if constexpr (std::is_same<A, double>::value && (NR == 8 || NR == 16)) {
+        k_fwd1x<TL, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, z, P.n, P.su);
+      } else if constexpr (NR >= 4) {
         k_fwd1m<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
       } else {
         k_fwd1<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
@@ -742,8 +898,12 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
     }
     const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(P.nunits, kXcds) * kXcds, P.grid);
     if (P.nunits > 0) {
-      k_fwd2<TD, TL, A, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, P.colmap, z,
+      if constexpr (std::is_same<A, double>::value && (NR == 8 || NR == 16))
+        k_fwd2x<TD, TL, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, P.colmap, z,
                                                static_cast<A*>(P.ypart), P.ldmax);
+      else
+        k_fwd2<TD, TL, A, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, P.colmap, z,
+                                                 static_cast<A*>(P.ypart), P.ldmax);
       HM_LAUNCH_CHECK();
     }
     k_fwd2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(P.L.nleaf, P.grid), 256, 0, s>>>(
