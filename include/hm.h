@@ -204,8 +204,17 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs,
                    int32_t dtype, const hm_solve_params* sp,
                    hm_solve_info* info, void* stream);
 
-/* Release every resource of h (NULL-safe); waits for work in flight. */
+/* Release every resource of h (NULL-safe); waits for work in flight.  The
+   handle's device memory goes back to the library's memory pool on that
+   device, which keeps it for later builds (allocating recently freed device
+   memory from the driver again costs seconds per tens of GB);
+   hm_release_memory returns it to the device. */
 void hm_free(hm_handle* h);
+
+/* Return the device memory cached in the library's pool of the current
+   device (memory of freed handles and build temporaries) to the device.
+   Memory of live handles is not affected.  Synchronises the device. */
+hm_status hm_release_memory(void);
 
 /* ---- introspection (tests, benchmarks) --------------------------------- */
 

@@ -10,7 +10,7 @@ from ._binding import (  # noqa: F401
     HM_STRICT,
     HMError, HMLibraryMissing, HMatrix, Params, SolveInfo, SolveParams, Stats,
     hm_build, hm_build_batch, hm_entries, hm_free, hm_last_error, hm_matvec, hm_matvec_T,
-    hm_params_default, hm_query, hm_solve, lib, library_path,
+    hm_params_default, hm_query, hm_solve, lib, library_path, release_memory,
 )
 
 

@@ -104,7 +104,8 @@ def lib():
     L.hm_entries.argtypes = [vp, vp, vp, i64, vp]
     L.hm_last_error.restype = C.c_char_p
     L.hm_last_error.argtypes = []
-    for f in ("hm_params_default", "hm_build", "hm_build_batch", "hm_matvec", "hm_matvec_T", "hm_solve",
+    L.hm_release_memory.argtypes = []
+    for f in ("hm_params_default", "hm_build", "hm_build_batch", "hm_release_memory", "hm_matvec", "hm_matvec_T", "hm_solve",
               "hm_query", "hm_entries"):
         getattr(L, f).restype = C.c_int
     _LIB = L
@@ -147,6 +148,12 @@ def hm_build(vertices: np.ndarray, triangles: np.ndarray, params: Params, stream
     _check(lib().hm_build(v.ctypes.data, v.shape[0], t.ctypes.data, t.shape[0], C.byref(params),
                           _stream_ptr(stream), C.byref(h)))
     return h.value
+
+
+def release_memory() -> None:
+    """Return the device memory cached in the library's pool (freed handles,
+    build temporaries) to the device (hm_release_memory)."""
+    _check(lib().hm_release_memory())
 
 
 def hm_build_batch(meshes, params: Params, stream=None) -> int:

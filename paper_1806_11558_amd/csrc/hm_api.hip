@@ -122,7 +122,7 @@ struct hm_handle {
   int form = 0;                  // hm_precision
   int f32 = 0;                   // evaluation in float
   size_t ts = 8;                 // bytes per stored value
-  std::vector<void*> owned;      // persistent allocations
+  std::vector<std::pair<void*, size_t>> owned;   // persistent allocations and sizes
   int64_t bytes = 0;
 
   double* c = nullptr;           // centroids, Morton order
@@ -163,9 +163,15 @@ struct hm_handle {
     if (p.mem_limit_bytes > 0 && bytes + (int64_t)b > p.mem_limit_bytes)
       throw Error{HM_ERR_OOM, "mem_limit_bytes exceeded (" + std::to_string(bytes + b) + " > " +
                                   std::to_string(p.mem_limit_bytes) + ")"};
-    // stream-ordered from the library's pool (on the stream of the build)
-    void* q = dalloc(b, alloc_stream);
-    owned.push_back(q);
+    // a block of a freed handle, else stream-ordered from the library's pool
+    // (on the stream of the build)
+    size_t got = b;
+    void* q = cache_take(b, &got);
+    if (!q) {
+      q = dalloc(b, alloc_stream);
+      got = b;
+    }
+    owned.push_back({q, got});
     bytes += (int64_t)b;
     return q;
   }
@@ -176,10 +182,10 @@ struct hm_handle {
   ~hm_handle() {
     if (profiling)
       for (auto& e : prof.ev) (void)hipEventDestroy(e);
-    // callers free handles after their work is done (hm_free synchronises
-    // the device first); the build stream may no longer exist
-    for (void* q : owned) (void)hipFreeAsync(q, nullptr);
-    (void)hipStreamSynchronize(nullptr);
+    // nothing may still use the blocks when they go to the cache (a failed
+    // build can leave work in flight; the build stream may no longer exist)
+    (void)hipDeviceSynchronize();
+    for (auto& q : owned) cache_put(q.first, q.second);
   }
   MvPlan plan() const {
     MvPlan P;
@@ -216,12 +222,10 @@ double ms_since(clk::time_point t0) {
   return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
-// The setup's temporaries come from the library's pool; return what it
-// caches beyond its keep size to the device, so that later allocations of
-// the caller do not compete with it.
+// The setup's temporaries go back to the library's pool, which keeps them
+// cached for the next build (hm_release_memory returns them to the device).
 void release_cached_memory(hipStream_t s) {
   HM_HIP(hipStreamSynchronize(s));
-  trim_pool();
 }
 
 template <typename F>
@@ -892,7 +896,15 @@ void hm_free(hm_handle* h) {
   if (!h) return;
   (void)hipDeviceSynchronize();
   delete h;
-  trim_pool();
+}
+
+hm_status hm_release_memory(void) {
+  return guarded([&]() -> hm_status {
+    HM_HIP(hipDeviceSynchronize());
+    cache_release();
+    trim_pool();
+    return HM_OK;
+  });
 }
 
 hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int64_t* needed) {

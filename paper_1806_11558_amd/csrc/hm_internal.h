@@ -211,9 +211,15 @@ void radix_sort_u64_i32(uint64_t* keys, int32_t* vals, int64_t n, int bits,
 void* dalloc(size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 // The library's memory pool on the current device; trim_pool() returns what
-// it caches beyond its keep size to the device.
+// it caches (memory not owned by a live handle) to the device.
 hipMemPool_t lib_pool();
 void trim_pool();
+// Cache of device blocks of freed handles on the current device: take one of
+// at least `bytes` (and at most 1/8 more; its size in *got) or nullptr; put
+// one back; free all.
+void* cache_take(size_t bytes, size_t* got);
+void cache_put(void* p, size_t bytes);
+void cache_release();
 template <typename T>
 T* dalloc_t(size_t count, hipStream_t s) {
   return static_cast<T*>(dalloc(count * sizeof(T) + 16, s));

@@ -6,6 +6,7 @@
 // written here for wave64: the sort ranks keys inside a wavefront with
 // ballots (no atomics on the ranking path), so it is stable and
 // deterministic.
+#include <map>
 #include <mutex>
 
 #include "hm_internal.h"
@@ -14,11 +15,13 @@ namespace hm {
 
 // ------------------------------------------------------------------ memory
 // All device memory of the library comes from one stream-ordered pool per
-// device, created on first use.  Up to kPoolKeep bytes of freed memory stay
-// cached in it across synchronisations, so a rebuild does not go back to the
-// driver for every temporary; trim_pool() hands the rest back.
+// device, created on first use.  Freed memory stays cached in the pool (its
+// release threshold is unlimited), so a rebuild reuses it instead of going
+// back to the driver: allocations of recently freed device memory wait for
+// the driver to clear it, which cost seconds for tens of GB.  trim_pool()
+// (hm_release_memory) hands the cache back.
 namespace {
-constexpr uint64_t kPoolKeep = uint64_t(1) << 30;
+constexpr uint64_t kPoolKeep = ~uint64_t(0);
 std::mutex g_pool_mu;
 hipMemPool_t g_pool[64] = {};
 }  // namespace
@@ -47,8 +50,45 @@ void trim_pool() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  if (g_pool[dev]) (void)hipMemPoolTrimTo(g_pool[dev], kPoolKeep);
+  if (g_pool[dev]) (void)hipMemPoolTrimTo(g_pool[dev], 0);
   (void)hipGetLastError();
+}
+
+// Blocks of freed handles, per device, by size.  A later build that asks for
+// a block of about the same size (at most 1/8 larger) takes it back, so that
+// rebuilding a problem reuses its storage instead of fresh driver memory.
+namespace {
+std::mutex g_cache_mu;
+std::multimap<size_t, void*> g_cache[64];
+}  // namespace
+
+void* cache_take(size_t bytes, size_t* got) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto& c = g_cache[dev];
+  auto it = c.lower_bound(bytes);
+  if (it == c.end() || it->first > bytes + bytes / 8) return nullptr;
+  void* p = it->second;
+  *got = it->first;
+  c.erase(it);
+  return p;
+}
+
+void cache_put(void* p, size_t bytes) {
+  int dev = 0;
+  if (!p || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache[dev].emplace(bytes, p);
+}
+
+void cache_release() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& e : g_cache[dev]) (void)hipFreeAsync(e.second, nullptr);
+  g_cache[dev].clear();
+  (void)hipStreamSynchronize(nullptr);
 }
 
 void* dalloc(size_t bytes, hipStream_t s) {

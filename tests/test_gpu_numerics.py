@@ -211,3 +211,24 @@ def test_zonal_harmonic_solves_n81920_fp32():
     assert status == 0 and info.converged
     e6 = errors(sig.cpu().numpy(), x6)
     assert np.all(e6 <= 0.5 * e4), (e6, e4)
+
+
+def test_freed_memory_cached_then_released():
+    """hm_free keeps the handle's memory in the library's pool (a rebuild
+    reuses it); release_memory returns it to the device."""
+    import paper_1806_11558_amd as hm
+    from synthetic import icosphere
+    say("memory pool")
+    V, T = icosphere(6)
+    torch.cuda.synchronize()
+    H = hm.HMatrix(V, T, leaf_size=64, eps=1e-6, precision="f64")
+    held = H.stats()["device_bytes"]
+    H.free()
+    free_cached, _ = torch.cuda.mem_get_info()
+    H = hm.HMatrix(V, T, leaf_size=64, eps=1e-6, precision="f64")   # reuses the cache
+    free_rebuilt, _ = torch.cuda.mem_get_info()
+    assert free_rebuilt >= free_cached - held // 4
+    H.free()
+    hm.release_memory()
+    free_released, _ = torch.cuda.mem_get_info()
+    assert free_released >= free_cached + held // 2
