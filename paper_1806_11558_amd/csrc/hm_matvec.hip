@@ -613,9 +613,12 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
                                                const double* __restrict__ z,
                                                double* __restrict__ ypart, int ldmax) {
   static_assert(NR == 8 || NR == 16, "MFMA phase 2 takes 8 or 16 right-hand sides");
-  constexpr int kTile = z_tile<double, NR>();
-  __shared__ double zs[kTile * NR];
-  __shared__ double ybuf[4][kMaxLeaf][NR];
+  // the z tile and the final combination of the wavefronts share one LDS
+  // buffer (the tile is consumed before the combination starts)
+  constexpr int kTile = (4 * kMaxLeaf * NR) / NR;     // columns: 256
+  __shared__ double lbuf[4 * kMaxLeaf * NR];
+  double* zs = lbuf;
+  double (*ybuf)[kMaxLeaf][NR] = reinterpret_cast<double (*)[kMaxLeaf][NR]>(lbuf);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lq = lane >> 4;     // a: row lr, column lq; b: column lq, rhs lr
   const int64_t per = (nunits + kXcds - 1) / kXcds;
@@ -660,6 +663,7 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
         }
       }
     }
+    __syncthreads();                                    // the last tile is consumed
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       if (t < nrt) {

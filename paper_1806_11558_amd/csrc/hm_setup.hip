@@ -210,6 +210,9 @@ __device__ inline int piv_index(const Piv& p) {
   return (p.k == 0 && p.ni == 0) ? -1 : (int)(~p.ni);
 }
 
+constexpr int kAcaClasses = 5;
+constexpr int kAcaBig = 4096;   // max(m, n) above which a block gets 1024 threads
+
 template <typename T>
 struct AcaArgs {
   Geom<T> g;
@@ -218,8 +221,10 @@ struct AcaArgs {
   const int64_t* slot;   // element offset of every block's working slot in pool
   int64_t slot0;         // slot offset of the chunk's first block (pool[0])
   T* pool;
-  const int32_t* list[4];  // blocks of class 0 (workgroup), 1..3 (wavefront, Q = 4, 2, 1)
-  int64_t cnt[4];
+  const int32_t* list[kAcaClasses];  // blocks of class 0 (1024-thread workgroup),
+                                     // 1 (256-thread workgroup), 2..4 (wavefront,
+                                     // Q = 4, 2, 1)
+  int64_t cnt[kAcaClasses];
   int kmax;
   double eps;
   int32_t* rank;         // out: rank per block
@@ -389,20 +394,23 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   }
 }
 
-// One block per workgroup of 256 threads (blocks larger than the wavefront
-// classes).  Cross-thread reads of the working factors happen only after a
+// One block per workgroup of NT threads (blocks larger than the wavefront
+// classes: NT = 256, and NT = 1024 for the largest blocks, whose sequential
+// steps are the critical path of their chunk).  Cross-thread reads of the working factors happen only after a
 // barrier.  The used-row flags are bytes placed after V in the slot.
-template <typename T>
+template <typename T, int NT>
 struct AcaShared {
+  static constexpr int kW = NT / 64;
   T a[kMaxRank];             // u_l[i*] or v_l[j*] of the previous terms
-  double dv[kMaxRank][kAcaWaves];  // per-wave partial dots v_l . v_r
-  double dt[kMaxRank];             // their totals
-  Piv pv[kAcaWaves];
-  double red[3][kAcaWaves];
+  double dv[kMaxRank][kW];   // per-wave partial dots v_l . v_r
+  double dt[kMaxRank];       // their totals
+  Piv pv[kW];
+  double red[3][kW];
   Piv pv_out;
   double out[3];
 };
 
+template <int NT>
 __device__ inline Piv wg_piv(Piv a, Piv* lds, Piv* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   a = wpiv(a);
@@ -410,7 +418,7 @@ __device__ inline Piv wg_piv(Piv a, Piv* lds, Piv* out) {
   __syncthreads();
   if (threadIdx.x == 0) {
     Piv r = lds[0];
-    for (int w = 1; w < kAcaWaves; ++w) piv_merge(r, lds[w].k, lds[w].ni);
+    for (int w = 1; w < (NT / 64); ++w) piv_merge(r, lds[w].k, lds[w].ni);
     *out = r;
   }
   __syncthreads();
@@ -419,8 +427,8 @@ __device__ inline Piv wg_piv(Piv a, Piv* lds, Piv* out) {
   return r;
 }
 
-template <typename T>
-__device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
+template <typename T, int NT>
+__device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int2 ts = A.blk[b];
   const Cluster tau = A.cl[ts.x], sig = A.cl[ts.y];
@@ -430,7 +438,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
   T* V = U + (int64_t)kcap * m;
   uint8_t* used = reinterpret_cast<uint8_t*>(V + (int64_t)kcap * n);
   const Geom<T>& g = A.g;
-  for (int i = tid; i < m; i += kAcaThreads) used[i] = 0;
+  for (int i = tid; i < m; i += NT) used[i] = 0;
   __syncthreads();
   int nused = 0, r = 0, istar = 0, rows_eval = 0;
   double s2 = 0.0;
@@ -440,7 +448,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     __syncthreads();
     const double xi = g.c[r0 + istar], yi = g.c[g.n + r0 + istar], zi = g.c[2 * g.n + r0 + istar];
     Piv pv{0, 0};
-    for (int j = tid; j < n; j += kAcaThreads) {
+    for (int j = tid; j < n; j += NT) {
       Src<T> s;
       load_src(g, c0 + j, s);
       T val = eval_entry(xi, yi, zi, r0 + istar, s, c0 + j);
@@ -451,7 +459,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     if (tid == 0) used[istar] = 1;
     ++rows_eval;
     ++nused;
-    const int jstar = piv_index(wg_piv(pv, sh.pv, &sh.pv_out));
+    const int jstar = piv_index(wg_piv<NT>(pv, sh.pv, &sh.pv_out));
     // every thread may read V[r][j*] now (barriers in wg_piv)
     const T delta = (jstar >= 0 && jstar < n) ? V[(int64_t)r * n + jstar] : (T)0;
     // every thread holds delta before the owner of j* overwrites that entry
@@ -459,26 +467,26 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     if (delta == (T)0) {
       if (nused >= m) break;
       Piv nx{0, 0};
-      for (int i = tid; i < m; i += kAcaThreads) {
+      for (int i = tid; i < m; i += NT) {
         if (used[i]) continue;
         const T k = (r > 0) ? (T)fabs(U[(int64_t)(r - 1) * m + i]) : (T)0;
         piv_merge(nx, key_bits(k), ~(unsigned)i);
       }
-      istar = piv_index(wg_piv(nx, sh.pv, &sh.pv_out));
+      istar = piv_index(wg_piv<NT>(nx, sh.pv, &sh.pv_out));
       if (istar < 0 || istar >= m) break;
       continue;
     }
     // v_r = v~ / delta, then the dots v_l . v_r of the previous terms.  Each
     // thread reads back only the entries of v_r it wrote itself.
     double vv = 0.0;
-    for (int j = tid; j < n; j += kAcaThreads) {
+    for (int j = tid; j < n; j += NT) {
       const T v = V[(int64_t)r * n + j] / delta;
       V[(int64_t)r * n + j] = v;
       vv += (double)v * (double)v;
     }
     for (int l = 0; l < r; ++l) {
       double pvv = 0.0;
-      for (int j = tid; j < n; j += kAcaThreads)
+      for (int j = tid; j < n; j += NT)
         pvv += (double)V[(int64_t)l * n + j] * (double)V[(int64_t)r * n + j];
       pvv = wsum(pvv);
       if (lane == 0) sh.dv[l][wave] = pvv;
@@ -487,7 +495,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     __syncthreads();
     if (tid < r) {
       double t = 0.0;
-      for (int w = 0; w < kAcaWaves; ++w) t += sh.dv[tid][w];
+      for (int w = 0; w < (NT / 64); ++w) t += sh.dv[tid][w];
       sh.dt[tid] = t;
     }
     __syncthreads();
@@ -497,7 +505,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     load_src(g, c0 + jstar, s);
     double uu = 0.0, cw = 0.0;
     Piv nx{0, 0};
-    for (int i = tid; i < m; i += kAcaThreads) {
+    for (int i = tid; i < m; i += NT) {
       T u = eval_entry(g.c[r0 + i], g.c[g.n + r0 + i], g.c[2 * g.n + r0 + i], r0 + i, s, c0 + jstar);
       double w = 0.0;
       for (int l = 0; l < r; ++l) {
@@ -524,7 +532,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
     if (tid == 0) {
       double tu = 0.0, tv = 0.0, tc = 0.0;
       Piv best = sh.pv[0];
-      for (int w = 0; w < kAcaWaves; ++w) {
+      for (int w = 0; w < (NT / 64); ++w) {
         tu += sh.red[0][w];
         tv += sh.red[1][w];
         tc += sh.red[2][w];
@@ -558,20 +566,20 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T>& sh) {
   }
 }
 
-// Class 0: one block per workgroup (largest first).
-template <typename T>
-__global__ __launch_bounds__(kAcaThreads, 4) void k_aca_wg(AcaArgs<T> A) {
-  __shared__ AcaShared<T> sh;
-  for (int64_t t = blockIdx.x; t < A.cnt[0]; t += gridDim.x) {
-    aca_wg(A, A.list[0][t], sh);
+// Classes 0 (NT = 1024) and 1 (NT = 256): one block per workgroup.
+template <typename T, int NT, int CLS>
+__global__ __launch_bounds__(NT, NT == 256 ? 4 : 1) void k_aca_wg(AcaArgs<T> A) {
+  __shared__ AcaShared<T, NT> sh;
+  for (int64_t t = blockIdx.x; t < A.cnt[CLS]; t += gridDim.x) {
+    aca_wg<T, NT>(A, A.list[CLS][t], sh);
     __syncthreads();
   }
 }
 
-// Classes 1..3: one block per wavefront, four per workgroup.
+// Classes 2..4: one block per wavefront, four per workgroup.
 template <typename T, int Q>
 __global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_aca_wave(AcaArgs<T> A) {
-  constexpr int c = Q == 4 ? 1 : (Q == 2 ? 2 : 3);
+  constexpr int c = Q == 4 ? 2 : (Q == 2 ? 3 : 4);
   // wave-uniform: the block's descriptors come in by scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ng = (A.cnt[c] + kAcaWaves - 1) / kAcaWaves;
@@ -581,8 +589,9 @@ __global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_
   }
 }
 
-// Class of every block: 0 workgroup (max(m, n) > 256), 1 wavefront with
-// Q = 4, 2 with Q = 2, 3 with Q = 1; flags[c * nb + b] = (class == c).
+// Class of every block: 0 1024-thread workgroup (max(m, n) > kAcaBig),
+// 1 256-thread workgroup (> 256), 2 wavefront with Q = 4, 3 with Q = 2,
+// 4 with Q = 1; flags[c * nb + b] = (class == c).
 __global__ void k_aca_classes(const int2* __restrict__ blk, int64_t nb,
                               const Cluster* __restrict__ cl, int64_t* __restrict__ flags) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
@@ -590,9 +599,9 @@ __global__ void k_aca_classes(const int2* __restrict__ blk, int64_t nb,
     const int2 ts = blk[b];
     const Cluster t = cl[ts.x], s = cl[ts.y];
     const int64_t mx = max(t.y - t.x, s.y - s.x);
-    const int c = mx > 256 ? 0 : (mx > 128 ? 1 : (mx > 64 ? 2 : 3));
+    const int c = mx > kAcaBig ? 0 : (mx > 256 ? 1 : (mx > 128 ? 2 : (mx > 64 ? 3 : 4)));
 #pragma unroll
-    for (int k = 0; k < 4; ++k) flags[k * nb + b] = (k == c) ? 1 : 0;
+    for (int k = 0; k < kAcaClasses; ++k) flags[k * nb + b] = (k == c) ? 1 : 0;
   }
 }
 
@@ -602,7 +611,7 @@ __global__ void k_split_lists(const int64_t* __restrict__ flags, const int64_t* 
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kAcaClasses; ++k)
       if (flags[k * nb + b]) lists[k * nb + offs[k * nb + b]] = (int32_t)b;
   }
 }
@@ -980,14 +989,15 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl, c
              int32_t* lists, int32_t* rank, int32_t* info, int64_t* tmp, hipStream_t s) {
   k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, flags);
   HM_LAUNCH_CHECK();
-  for (int k = 0; k < 4; ++k) scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
-  int64_t cnt[4];
-  HM_HIP(hipMemcpyAsync(cnt, tmp, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  for (int k = 0; k < kAcaClasses; ++k)
+    scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
+  int64_t cnt[kAcaClasses];
+  HM_HIP(hipMemcpyAsync(cnt, tmp, kAcaClasses * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HM_HIP(hipStreamSynchronize(s));
   k_split_lists<<<grid_for(nb, 256), 256, 0, s>>>(flags, offs, nb, lists);
   HM_LAUNCH_CHECK();
   AcaArgs<T> A{g, blk, cl, slot, slot0, pool, {}, {}, kmax, eps, rank, info};
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kAcaClasses; ++k) {
     A.list[k] = lists + k * nb;
     A.cnt[k] = cnt[k];
   }
@@ -997,19 +1007,23 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl, c
   const int64_t cap = (int64_t)std::max(ncu, 1) * 32;
   // largest blocks first: one workgroup each, then the wavefront classes
   if (cnt[0] > 0) {
-    k_aca_wg<T><<<(unsigned)std::min<int64_t>(cnt[0], cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wg<T, 1024, 0><<<(unsigned)std::min<int64_t>(cnt[0], cap), 1024, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[1] > 0) {
-    k_aca_wave<T, 4><<<(unsigned)std::min<int64_t>(ceil_div(cnt[1], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wg<T, 256, 1><<<(unsigned)std::min<int64_t>(cnt[1], cap), 256, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[2] > 0) {
-    k_aca_wave<T, 2><<<(unsigned)std::min<int64_t>(ceil_div(cnt[2], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wave<T, 4><<<(unsigned)std::min<int64_t>(ceil_div(cnt[2], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[3] > 0) {
-    k_aca_wave<T, 1><<<(unsigned)std::min<int64_t>(ceil_div(cnt[3], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wave<T, 2><<<(unsigned)std::min<int64_t>(ceil_div(cnt[3], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    HM_LAUNCH_CHECK();
+  }
+  if (cnt[4] > 0) {
+    k_aca_wave<T, 1><<<(unsigned)std::min<int64_t>(ceil_div(cnt[4], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
 }
@@ -1199,7 +1213,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   constexpr bool scaled = !std::is_same<T, TL>::value;
   const int64_t n = in.n, nleaf = in.nleaf;
   Temps keep{s, {}};       // lives until the product plan is complete
-  int64_t* tmp = keep.get<int64_t>(4);
+  int64_t* tmp = keep.get<int64_t>(8);   // one total per ACA class, scan scratch
 
   // ---- near field: dense slices in row-leaf panels
   auto t0 = clk::now();
@@ -1283,9 +1297,9 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       const int64_t maxterms = scan_total(kc, ko, nl, tmp, s);
       out.su = static_cast<float*>(alloc((size_t)(maxterms + 1) * sizeof(float)));
     }
-    int64_t* cflags = ta.get<int64_t>(4 * nl);
-    int64_t* coffs = ta.get<int64_t>(4 * nl);
-    int32_t* clists = ta.get<int32_t>(4 * nl);
+    int64_t* cflags = ta.get<int64_t>(kAcaClasses * nl);
+    int64_t* coffs = ta.get<int64_t>(kAcaClasses * nl);
+    int32_t* clists = ta.get<int32_t>(kAcaClasses * nl);
     int64_t* toffc = ta.get<int64_t>(nl + 1);
     int64_t* rk64 = ta.get<int64_t>(nl);
     int64_t* vsz = ta.get<int64_t>(nl);
