@@ -1280,14 +1280,28 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     k_slot_sizes<T><<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl, kmax, slot);
     HM_LAUNCH_CHECK();
     scan_excl_i64(slot, slot_off, nl, slot_off + nl, s);
-    std::vector<int64_t> hoff(nl + 1);
-    HM_HIP(hipMemcpyAsync(hoff.data(), slot_off, (nl + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
-    int64_t pool_elems = std::min<int64_t>(hoff[nl], std::max<int64_t>(in.pool_budget_bytes / esize, 1));
-    int64_t maxslot = 0;
-    for (int64_t b = 0; b < nl; ++b) maxslot = std::max(maxslot, hoff[b + 1] - hoff[b]);
-    pool_elems = std::max(pool_elems, maxslot);
-    T* pool = static_cast<T*>(dalloc((size_t)pool_elems * esize, s));
+    // all slots at once when they fit the budget; otherwise chunks of
+    // consecutive blocks, cut on the host from the slot offsets
+    const int64_t total_slots = d2h_i64(slot_off + nl, s);
+    const int64_t budget_elems = std::max<int64_t>(in.pool_budget_bytes / esize, 1);
+    std::vector<int64_t> hoff;
+    int64_t pool_elems = std::max<int64_t>(total_slots, 1);
+    if (total_slots > budget_elems) {
+      hoff.resize(nl + 1);
+      HM_HIP(hipMemcpyAsync(hoff.data(), slot_off, (nl + 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      int64_t maxslot = 0;
+      for (int64_t b = 0; b < nl; ++b) maxslot = std::max(maxslot, hoff[b + 1] - hoff[b]);
+      pool_elems = std::max(budget_elems, maxslot);
+    }
+    auto slot_at = [&](int64_t b) { return hoff.empty() ? (b == 0 ? 0 : total_slots) : hoff[b]; };
+    // the working slots come from the block cache and go back to it: handing a
+    // block of this size back to the stream-ordered pool made its next
+    // operation wait for milliseconds
+    size_t pool_bytes = (size_t)pool_elems * esize;
+    T* pool = static_cast<T*>(cache_take(pool_bytes, &pool_bytes));
+    if (!pool) pool = static_cast<T*>(dalloc(pool_bytes, s));
     if (scaled) {
       // at most min(kmax, m, n) terms per block
       int64_t* kc = ta.get<int64_t>(nl);
@@ -1308,10 +1322,11 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     int64_t* oU = ta.get<int64_t>(nl + 1);
     int64_t b0 = 0;
     while (b0 < nl) {
-      int64_t b1 = b0 + 1;
+      int64_t b1 = hoff.empty() ? nl : b0 + 1;
       while (b1 < nl && hoff[b1 + 1] - hoff[b0] <= pool_elems) ++b1;
+      const int64_t slot0 = slot_at(b0);
       const int64_t nb = b1 - b0;
-      run_aca<T>(g, in.lr + b0, nb, in.cl, slot_off + b0, hoff[b0], pool, kmax, in.eps, cflags,
+      run_aca<T>(g, in.lr + b0, nb, in.cl, slot_off + b0, slot0, pool, kmax, in.eps, cflags,
                  coffs, clists, out.rank + b0, out.info + b0, tmp, s);
       HM_HIP(hipStreamSynchronize(s));
       const auto tp = clk::now();
@@ -1325,7 +1340,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       const int64_t velems = scan_total(vsz, voff, nb, tmp, s);
       TL* varena = static_cast<TL*>(alloc((size_t)velems * lsize));
       k_pack_v<T, TL><<<grid_for(nb, 1, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
-                                                          slot_off + b0, hoff[b0], pool, kmax, voff,
+                                                          slot_off + b0, slot0, pool, kmax, voff,
                                                           varena, vptr);
       HM_LAUNCH_CHECK();
       k_lr_meta<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, in.ldpre,
@@ -1340,14 +1355,14 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       TL* uarena = static_cast<TL*>(alloc((size_t)PU.elems * lsize));
       if (scaled && nb > 0) {
         k_u_scales<T><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(
-            in.lr + b0, nb, in.cl, out.rank + b0, slot_off + b0, hoff[b0], pool, toffc,
+            in.lr + b0, nb, in.cl, out.rank + b0, slot_off + b0, slot0, pool, toffc,
             toff_base, out.su);
         HM_LAUNCH_CHECK();
       }
       if (PU.np > 0) {
         k_pack_u<T, TL><<<grid_for(PU.np, 1, 1 << 20), 256, 0, s>>>(
             PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0, in.cl, L, out.rank + b0, slot_off + b0,
-            hoff[b0], pool, PU.offI, scaled ? out.su : nullptr, toffc, toff_base, uarena);
+            slot0, pool, PU.offI, scaled ? out.su : nullptr, toffc, toff_base, uarena);
         HM_LAUNCH_CHECK();
       }
       const int64_t colbase = out.dense_cols + ucols;
@@ -1376,7 +1391,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       b0 = b1;
     }
     HM_HIP(hipStreamSynchronize(s));
-    dfree(pool, s);
+    cache_put(pool, pool_bytes);
   }
   out.toff_total = toff_base;
   if (toff_base >= INT32_MAX) throw Error{HM_ERR_STATE, "more than 2^31 low-rank terms"};
