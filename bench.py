@@ -123,6 +123,26 @@ def phase2_bytes(st, s_store, s_acc, s_vec, nrhs=1):
             + st["rank_sum"] * nrhs * s_acc + n * nrhs * s_vec + 4 * n + 4 * st["n_panel_cols"])
 
 
+# Kernel evaluations of the setup: 7 nodes x (3 sub, 3 mul/fma, rsqrt, add)
+# plus the centroid difference, weights and scale: about 66 operations per
+# entry (the rsqrt counted as one).  ACA updates are not counted.
+FLOPS_PER_ENTRY = 66
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f16": 157.3, "f64": 78.6}
+
+
+def setup_roofline(o, form):
+    """ALU roofline of the near field + ACA phases: entry evaluations (dense
+    entries + ACA rows and columns) x FLOPS_PER_ENTRY over their time."""
+    st = o["stats"]
+    ms = o["setup_phases_ms"]["near_field"] + o["setup_phases_ms"]["aca"]
+    ent = st["dense_entries"] + st["aca_entry_evals"]
+    tf = ent * FLOPS_PER_ENTRY / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "entries": ent, "entries_per_s": round(ent / (ms * 1e-3), 1),
+            "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS[form], "unit": "TFLOP/s",
+            "frac": round(tf / VALU_PEAK_TFLOPS[form], 5),
+            "phases": "near_field + aca", "ms": round(ms, 3)}
+
+
 def run_form(hm, torch, V, T, args, prec, xg, fg, keep):
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     torch.cuda.synchronize()
@@ -401,6 +421,7 @@ def main():
             "frac": round(M["phase2_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.level, args.leaf, args.eps, main_form),
         },
+        "setup_roofline": {p: setup_roofline(out[p], p) for p in out},
         "forms": out,
     }
     if cpu is not None:

@@ -110,6 +110,10 @@ __global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restri
                                               const int2* __restrict__ dns,
                                               const Cluster* __restrict__ cl, LeafTab L,
                                               const int64_t* __restrict__ offI, T* __restrict__ D) {
+  // the slice's source triangles (columns, at most a leaf) and collocation
+  // points (rows) are staged in LDS once; entries read them from there
+  __shared__ Src<T> src[kMaxLeaf];
+  __shared__ double xr[3][kMaxLeaf];
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     const int32_t u = sidx[p];
     const int b = ib[u], lf = ilf[u];
@@ -117,11 +121,31 @@ __global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restri
     const int n = sig.y - sig.x;
     const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
     T* dst = D + offI[p];
-    for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
-      const int i = e % ld, j = e / ld;
-      T v = 0;
-      if (i < m) v = entry_at(g, lo + i, sig.x + j);
-      dst[e] = v;
+    if (n <= kMaxLeaf) {                                // dense blocks are leaf pairs
+      for (int j = threadIdx.x; j < n; j += blockDim.x) load_src(g, sig.x + j, src[j]);
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        xr[0][i] = g.c[lo + i];
+        xr[1][i] = g.c[g.n + lo + i];
+        xr[2][i] = g.c[2 * g.n + lo + i];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
+        const int i = e % ld, j = e / ld;
+        T v = 0;
+        if (i < m) {
+          const Src<T> sj = src[j];
+          v = eval_entry(xr[0][i], xr[1][i], xr[2][i], lo + i, sj, sig.x + j);
+        }
+        dst[e] = v;
+      }
+      __syncthreads();                                  // before the next slice is staged
+    } else {
+      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
+        const int i = e % ld, j = e / ld;
+        T v = 0;
+        if (i < m) v = entry_at(g, lo + i, sig.x + j);
+        dst[e] = v;
+      }
     }
   }
 }
