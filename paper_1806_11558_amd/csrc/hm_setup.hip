@@ -768,7 +768,11 @@ __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx
                                                 const float* __restrict__ su,
                                                 const int64_t* __restrict__ toff, int64_t tbase,
                                                 TL* __restrict__ arena) {
-  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+  // one wavefront per item (slices are a few hundred values); wave-uniform
+  // index, so the descriptors come in by scalar loads
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int64_t p = wid; p < np; p += (int64_t)gridDim.x * 4) {
     const int32_t u = sidx[p];
     const int b = ib[u], lf = ilf[u];
     const int2 ts = blk[b];
@@ -777,7 +781,7 @@ __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx
     const T* U = pool + (slot[b] - slot0);
     const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - tau.x;
     TL* d = arena + offI[p];
-    for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
+    for (int e = lane; e < ld * r; e += 64) {
       const int i = e % ld, l = e / ld;
       T v = (i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
       if (su) v = v / (T)su[tbase + toff[b] + l];
@@ -823,19 +827,22 @@ __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, in
                                                 const int64_t* __restrict__ voff,
                                                 TL* __restrict__ varena,
                                                 uint64_t* __restrict__ vptr) {
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+  // one wavefront per block (most are a few hundred values)
+  const int lane = threadIdx.x & 63;
+  const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int64_t b = wid; b < nb; b += (int64_t)gridDim.x * 4) {
     const int2 ts = blk[b];
     const Cluster tau = cl[ts.x], sig = cl[ts.y];
     const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
     const int kcap = min(kmax, min(m, n));
     const T* Vw = pool + (slot[b] - slot0) + (int64_t)kcap * m;
     TL* dst = varena + voff[b];
-    if (threadIdx.x == 0) vptr[b] = (uint64_t)(uintptr_t)dst;
+    if (lane == 0) vptr[b] = (uint64_t)(uintptr_t)dst;
     const int2 ls = L.cl_leaves[ts.y];
     for (int lf = ls.x; lf <= ls.y; ++lf) {
       const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - sig.x;
       TL* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
-      for (int e = threadIdx.x; e < ld * r; e += blockDim.x) {
+      for (int e = lane; e < ld * r; e += 64) {
         const int i = e % ld, l = e / ld;
         d[e] = (TL)((i < ml) ? Vw[(int64_t)l * n + off + i] : (T)0);
       }
@@ -1363,7 +1370,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       HM_LAUNCH_CHECK();
       const int64_t velems = scan_total(vsz, voff, nb, tmp, s);
       TL* varena = static_cast<TL*>(alloc((size_t)velems * lsize));
-      k_pack_v<T, TL><<<grid_for(nb, 1, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
+      k_pack_v<T, TL><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
                                                           slot_off + b0, slot0, pool, kmax, voff,
                                                           varena, vptr);
       HM_LAUNCH_CHECK();
@@ -1384,7 +1391,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
         HM_LAUNCH_CHECK();
       }
       if (PU.np > 0) {
-        k_pack_u<T, TL><<<grid_for(PU.np, 1, 1 << 20), 256, 0, s>>>(
+        k_pack_u<T, TL><<<grid_for(PU.np, 4, 1 << 20), 256, 0, s>>>(
             PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0, in.cl, L, out.rank + b0, slot_off + b0,
             slot0, pool, PU.offI, scaled ? out.su : nullptr, toffc, toff_base, uarena);
         HM_LAUNCH_CHECK();
