@@ -413,7 +413,7 @@ def main():
         "matvec_pct_hbm_peak": {p: round(100 * out[p]["matvec_gbs"] / HBM_PEAK_GBS, 1) for p in out},
         "rel_err_sampled": {p: out[p].get("rel_err_sampled") for p in out},
         "roofline": {
-            "kernel": "k_fwd2 (row-leaf panels: dense blocks + U slices), " + main_form,
+            "kernel": "k_fwd2 + k_fwd2_sum (row-leaf panels: dense blocks + U slices), " + main_form,
             "bound": "hbm",
             "achieved": round(M["phase2_gbs"], 1),
             "peak": HBM_PEAK_GBS,
