@@ -27,6 +27,18 @@ struct Src {
   T aw, sf;
 };
 
+// base[k] at a byte offset of 32 bits from a wavefront-uniform base: the
+// load then takes the base in scalar registers and one vector offset, with
+// no 64-bit address arithmetic per load
+template <typename T>
+__device__ inline T ld_at(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename T>
+__device__ inline void st_at(T* base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 template <typename T>
 __device__ inline void load_src(const Geom<T>& g, int j, Src<T>& s) {
   s.cx = g.c[j];
@@ -42,7 +54,31 @@ __device__ inline void load_src(const Geom<T>& g, int j, Src<T>& s) {
   s.sf = g.sf[j];
 }
 
-__device__ inline float rsq(float x) { return rsqrtf(x); }
+// The same through uniform bases and one 32-bit offset: fewer vector
+// instructions per entry, more scalar registers held (used where one
+// column is loaded at a time)
+template <typename T>
+__device__ inline void load_src_u(const Geom<T>& g, int j, Src<T>& s) {
+  const uint32_t bd = (uint32_t)j * 8u, bt = (uint32_t)j * (uint32_t)sizeof(T);
+  s.cx = ld_at(g.c, bd);
+  s.cy = ld_at(g.c + g.n, bd);
+  s.cz = ld_at(g.c + 2 * g.n, bd);
+#pragma unroll
+  for (int q = 0; q < kNQ; ++q) {
+    s.ox[q] = ld_at(g.o + (int64_t)q * g.n, bt);
+    s.oy[q] = ld_at(g.o + (int64_t)(kNQ + q) * g.n, bt);
+    s.oz[q] = ld_at(g.o + (int64_t)(2 * kNQ + q) * g.n, bt);
+  }
+  s.aw = ld_at(g.aw, bt);
+  s.sf = ld_at(g.sf, bt);
+}
+
+// The hardware reciprocal square root.  Its argument is the squared distance
+// between a collocation point and a quadrature node of another triangle, far
+// above the subnormal range for any mesh of distinct triangles; there the
+// instruction gives the result of rsqrtf, whose extra steps only rescale
+// subnormal arguments.
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
 
 // a(i, j) = |T_j|/(4 pi) sum_q w_q / |x_i - y_jq| for i != j (seven-point
@@ -122,7 +158,7 @@ __global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restri
     const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
     T* dst = D + offI[p];
     if (n <= kMaxLeaf) {                                // dense blocks are leaf pairs
-      for (int j = threadIdx.x; j < n; j += blockDim.x) load_src(g, sig.x + j, src[j]);
+      for (int j = threadIdx.x; j < n; j += blockDim.x) load_src_u(g, sig.x + j, src[j]);
       for (int i = threadIdx.x; i < m; i += blockDim.x) {
         xr[0][i] = g.c[lo + i];
         xr[1][i] = g.c[g.n + lo + i];
@@ -279,6 +315,7 @@ constexpr int kAcaWaves = kAcaThreads / 64;
 
 template <typename T, int Q>
 __device__ void aca_wave(const AcaArgs<T>& A, int b) {
+  constexpr int KB = Q == 4 ? 4 : 8;   // previous terms per batch of loads
   const int lane = threadIdx.x & 63;
   const int2 ts = A.blk[b];
   const Cluster tau = A.cl[ts.x], sig = A.cl[ts.y];
@@ -317,12 +354,27 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
         val[q] = eval_entry(xi, yi, zi, r0 + istar, s, c0 + lane + 64 * q);
       }
     }
-    for (int l = 0; l < r; ++l) {
-      const T own = (lane + 64 * iq < m) ? U[(int64_t)l * m + lane + 64 * iq] : (T)0;
-      const T ui = rdl_v(own, il);
+    // the previous terms KB at a time: their loads are issued together (an
+    // index past r - 1 reads term r - 1 and is not used)
+    const bool ownr = lane + 64 * iq < m;
+    for (int l0 = 0; l0 < r; l0 += KB) {
+      T ub[KB], vb[KB][Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q)
-        if (hc[q]) val[q] -= ui * V[(int64_t)l * n + lane + 64 * q];
+      for (int k = 0; k < KB; ++k) {
+        const int l = min(l0 + k, r - 1);
+        ub[k] = ownr ? U[(int64_t)l * m + lane + 64 * iq] : (T)0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) vb[k][q] = hc[q] ? V[(int64_t)l * n + lane + 64 * q] : (T)0;
+      }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        if (l0 + k < r) {
+          const T ui = rdl_v(ub[k], il);
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            if (hc[q]) val[q] -= ui * vb[k][q];
+        }
+      }
     }
     ++rows_eval;
 #pragma unroll
@@ -370,21 +422,31 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
       u[q] = hr[q] ? eval_entry(px[q], py[q], pz[q], r0 + lane + 64 * q, s, c0 + jstar) : (T)0;
       wv[q] = 0.0;
     }
-    for (int l = 0; l < r; ++l) {
-      T vo[Q];
-      double pvl = 0.0;
+    for (int l0 = 0; l0 < r; l0 += KB) {
+      T vo[KB][Q], uo[KB][Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        vo[q] = hc[q] ? V[(int64_t)l * n + lane + 64 * q] : (T)0;
-        pvl += (double)vo[q] * (double)v[q];
+      for (int k = 0; k < KB; ++k) {
+        const int l = min(l0 + k, r - 1);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          vo[k][q] = hc[q] ? V[(int64_t)l * n + lane + 64 * q] : (T)0;
+          uo[k][q] = hr[q] ? U[(int64_t)l * m + lane + 64 * q] : (T)0;
+        }
       }
-      const T vj = rdl_v(pick(vo, jq), jl);
-      const double dv = wsum(pvl);
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const T ul = hr[q] ? U[(int64_t)l * m + lane + 64 * q] : (T)0;
-        u[q] -= vj * ul;
-        wv[q] += dv * (double)ul;
+      for (int k = 0; k < KB; ++k) {
+        if (l0 + k < r) {
+          double pvl = 0.0;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) pvl += (double)vo[k][q] * (double)v[q];
+          const T vj = rdl_v(pick(vo[k], jq), jl);
+          const double dv = wsum(pvl);
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            u[q] -= vj * uo[k][q];
+            wv[q] += dv * (double)uo[k][q];
+          }
+        }
       }
     }
     double uu = 0.0, cw = 0.0;
@@ -451,6 +513,11 @@ __device__ inline Piv wg_piv(Piv a, Piv* lds, Piv* out) {
   return r;
 }
 
+// previous terms per batch of loads, and columns (rows) per thread at a
+// time, in the workgroup variant
+constexpr int kTermBatch = 8;
+constexpr int kColUnroll = 1;
+
 template <typename T, int NT>
 __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -472,13 +539,40 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
     __syncthreads();
     const double xi = g.c[r0 + istar], yi = g.c[g.n + r0 + istar], zi = g.c[2 * g.n + r0 + istar];
     Piv pv{0, 0};
-    for (int j = tid; j < n; j += NT) {
-      Src<T> s;
-      load_src(g, c0 + j, s);
-      T val = eval_entry(xi, yi, zi, r0 + istar, s, c0 + j);
-      for (int l = 0; l < r; ++l) val -= sh.a[l] * V[(int64_t)l * n + j];
-      V[(int64_t)r * n + j] = val;
-      piv_merge(pv, key_bits((T)fabs(val)), ~(unsigned)j);
+    // kColUnroll columns per thread at a time, so that their loads overlap
+    // (indices past n - 1 are clamped and their results dropped)
+    for (int j0 = tid; j0 < n; j0 += kColUnroll * NT) {
+      Src<T> sj[kColUnroll];
+      T val[kColUnroll];
+      int jj[kColUnroll];
+#pragma unroll
+      for (int u = 0; u < kColUnroll; ++u) {
+        jj[u] = min(j0 + u * NT, n - 1);
+        load_src_u(g, c0 + jj[u], sj[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < kColUnroll; ++u)
+        val[u] = eval_entry(xi, yi, zi, r0 + istar, sj[u], c0 + jj[u]);
+      for (int l0 = 0; l0 < r; l0 += kTermBatch) {
+        T vb[kColUnroll][kTermBatch];
+#pragma unroll
+        for (int u = 0; u < kColUnroll; ++u)
+#pragma unroll
+          for (int k = 0; k < kTermBatch; ++k)
+            vb[u][k] = ld_at(V + (int64_t)min(l0 + k, r - 1) * n, (uint32_t)jj[u] * (uint32_t)sizeof(T));
+#pragma unroll
+        for (int k = 0; k < kTermBatch; ++k)
+          if (l0 + k < r)
+#pragma unroll
+            for (int u = 0; u < kColUnroll; ++u) val[u] -= sh.a[l0 + k] * vb[u][k];
+      }
+#pragma unroll
+      for (int u = 0; u < kColUnroll; ++u) {
+        if (j0 + u * NT < n) {
+          V[(int64_t)r * n + jj[u]] = val[u];
+          piv_merge(pv, key_bits((T)fabs(val[u])), ~(unsigned)jj[u]);
+        }
+      }
     }
     if (tid == 0) used[istar] = 1;
     ++rows_eval;
@@ -508,12 +602,26 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
       V[(int64_t)r * n + j] = v;
       vv += (double)v * (double)v;
     }
-    for (int l = 0; l < r; ++l) {
-      double pvv = 0.0;
-      for (int j = tid; j < n; j += NT)
-        pvv += (double)V[(int64_t)l * n + j] * (double)V[(int64_t)r * n + j];
-      pvv = wsum(pvv);
-      if (lane == 0) sh.dv[l][wave] = pvv;
+    for (int l0 = 0; l0 < r; l0 += kTermBatch) {
+      double pvv[kTermBatch];
+#pragma unroll
+      for (int k = 0; k < kTermBatch; ++k) pvv[k] = 0.0;
+      for (int j = tid; j < n; j += NT) {
+        const uint32_t jb = (uint32_t)j * (uint32_t)sizeof(T);
+        const double vr = (double)ld_at(V + (int64_t)r * n, jb);
+        T vb[kTermBatch];
+#pragma unroll
+        for (int k = 0; k < kTermBatch; ++k) vb[k] = ld_at(V + (int64_t)min(l0 + k, r - 1) * n, jb);
+#pragma unroll
+        for (int k = 0; k < kTermBatch; ++k) pvv[k] += (double)vb[k] * vr;
+      }
+#pragma unroll
+      for (int k = 0; k < kTermBatch; ++k) {
+        if (l0 + k < r) {
+          const double t = wsum(pvv[k]);
+          if (lane == 0) sh.dv[l0 + k][wave] = t;
+        }
+      }
     }
     if (tid < r) sh.a[tid] = V[(int64_t)tid * n + jstar];
     __syncthreads();
@@ -529,18 +637,47 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
     load_src(g, c0 + jstar, s);
     double uu = 0.0, cw = 0.0;
     Piv nx{0, 0};
-    for (int i = tid; i < m; i += NT) {
-      T u = eval_entry(g.c[r0 + i], g.c[g.n + r0 + i], g.c[2 * g.n + r0 + i], r0 + i, s, c0 + jstar);
-      double w = 0.0;
-      for (int l = 0; l < r; ++l) {
-        const T ul = U[(int64_t)l * m + i];
-        u -= sh.a[l] * ul;
-        w += sh.dt[l] * (double)ul;
+    for (int i0 = tid; i0 < m; i0 += kColUnroll * NT) {
+      T u[kColUnroll];
+      double w[kColUnroll];
+      int ii[kColUnroll];
+#pragma unroll
+      for (int q = 0; q < kColUnroll; ++q) {
+        ii[q] = min(i0 + q * NT, m - 1);
+        const int i = ii[q];
+        const uint32_t ib8 = (uint32_t)i * 8u;
+        u[q] = eval_entry(ld_at(g.c + r0, ib8), ld_at(g.c + g.n + r0, ib8),
+                          ld_at(g.c + 2 * g.n + r0, ib8), r0 + i, s, c0 + jstar);
+        w[q] = 0.0;
       }
-      U[(int64_t)r * m + i] = u;
-      uu += (double)u * (double)u;
-      cw += (double)u * w;
-      if (!used[i]) piv_merge(nx, key_bits((T)fabs(u)), ~(unsigned)i);
+      for (int l0 = 0; l0 < r; l0 += kTermBatch) {
+        T ub[kColUnroll][kTermBatch];
+#pragma unroll
+        for (int q = 0; q < kColUnroll; ++q)
+#pragma unroll
+          for (int k = 0; k < kTermBatch; ++k)
+            ub[q][k] = ld_at(U + (int64_t)min(l0 + k, r - 1) * m, (uint32_t)ii[q] * (uint32_t)sizeof(T));
+#pragma unroll
+        for (int k = 0; k < kTermBatch; ++k) {
+          if (l0 + k < r) {
+#pragma unroll
+            for (int q = 0; q < kColUnroll; ++q) {
+              u[q] -= sh.a[l0 + k] * ub[q][k];
+              w[q] += sh.dt[l0 + k] * (double)ub[q][k];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kColUnroll; ++q) {
+        if (i0 + q * NT < m) {
+          const int i = ii[q];
+          U[(int64_t)r * m + i] = u[q];
+          uu += (double)u[q] * (double)u[q];
+          cw += (double)u[q] * w[q];
+          if (!used[i]) piv_merge(nx, key_bits((T)fabs(u[q])), ~(unsigned)i);
+        }
+      }
     }
     uu = wsum(uu);
     vv = wsum(vv);
