@@ -419,9 +419,9 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     size_t freeb = 0, totb = 0;
     HM_HIP(hipMemGetInfo(&freeb, &totb));
     // ACA working pool: at most 40% of the free memory and at most
-    // kAcaPoolCap.  A larger pool means fewer chunks but a large transient
-    // allocation, and allocations of recently freed device memory wait for
-    // the driver to clear it, at a cost proportional to their size.
+    // kAcaPoolCap.  A larger pool means fewer chunks (each chunk costs host
+    // synchronisations) but a large transient allocation; it comes from the
+    // block cache when an earlier build returned one of its size.
     int64_t budget = std::min<int64_t>((int64_t)(0.40 * (double)freeb), kAcaPoolCap);
     if (p.mem_limit_bytes > 0) budget = std::min(budget, (p.mem_limit_bytes - h->bytes) / 3);
     SetupIn in{n, h->cl, h->cl_leaves, h->leaf_lo, h->leaf_m, h->ldpre, h->nleaf,

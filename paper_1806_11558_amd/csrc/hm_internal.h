@@ -30,7 +30,7 @@ constexpr int kMortonBits = 21;
 constexpr int kNQ = 7;              // quadrature nodes of the triangle rule
 constexpr int kMaxLeaf = 64;        // leaf clusters fit one wavefront
 constexpr int kMaxRank = 256;
-constexpr int64_t kAcaPoolCap = int64_t(16) << 30;  // bytes of ACA working slots at once
+constexpr int64_t kAcaPoolCap = int64_t(40) << 30;  // bytes of ACA working slots at once
 
 // Radon's seven-point degree-5 rule: weights normalised to sum to one.
 // Node q = 0 is the centroid; nodes 1..3 use (a1, a1, b1), 4..6 (a2, a2, b2).

@@ -918,11 +918,24 @@ __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx
     const T* U = pool + (slot[b] - slot0);
     const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - tau.x;
     TL* d = arena + offI[p];
-    for (int e = lane; e < ld * r; e += 64) {
-      const int i = e % ld, l = e / ld;
-      T v = (i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
-      if (su) v = v / (T)su[tbase + toff[b] + l];
-      d[e] = (TL)v;
+    const int tot = ld * r;
+    // eight values per lane in flight
+    for (int e0 = lane; e0 < tot; e0 += 512) {
+      T v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + 64 * k, i = e % ld, l = e / ld;
+        v[k] = (e < tot && i < ml) ? U[(int64_t)l * m + off + i] : (T)0;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int e = e0 + 64 * k;
+        if (e < tot) {
+          T x = v[k];
+          if (su) x = x / (T)su[tbase + toff[b] + e / ld];
+          d[e] = (TL)x;
+        }
+      }
     }
   }
 }
@@ -979,9 +992,19 @@ __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, in
     for (int lf = ls.x; lf <= ls.y; ++lf) {
       const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - sig.x;
       TL* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
-      for (int e = lane; e < ld * r; e += 64) {
-        const int i = e % ld, l = e / ld;
-        d[e] = (TL)((i < ml) ? Vw[(int64_t)l * n + off + i] : (T)0);
+      const int tot = ld * r;
+      for (int e0 = lane; e0 < tot; e0 += 512) {
+        T v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int e = e0 + 64 * k, i = e % ld, l = e / ld;
+          v[k] = (e < tot && i < ml) ? Vw[(int64_t)l * n + off + i] : (T)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int e = e0 + 64 * k;
+          if (e < tot) d[e] = (TL)v[k];
+        }
       }
     }
   }
@@ -1102,11 +1125,19 @@ __global__ void k_gather_titems(const TItem* __restrict__ in, const int32_t* __r
 // predecessor's key and its own.
 __global__ void k_seg_begins(const uint64_t* __restrict__ keys, int64_t n, int64_t nleaf,
                              int64_t* __restrict__ beg) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p <= n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t prev = p > 0 ? (int64_t)keys[p - 1] : -1;
-    const int64_t cur = p < n ? (int64_t)keys[p] : nleaf;
-    for (int64_t c = prev + 1; c <= cur; ++c) beg[c] = p;
+  // beg[c] = first position whose key is >= c (keys sorted, all < nleaf), by
+  // a binary search per leaf: leaves without items cost no serial loop
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= nleaf;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if ((int64_t)keys[mid] < c)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    beg[c] = lo;
   }
 }
 
@@ -1309,7 +1340,7 @@ void panel_layout(const int2* blk, int64_t nb, const Cluster* cl, const int2* cl
   HM_LAUNCH_CHECK();
   P.cols = scan_total(P.wid, P.gcol, P.np, tmp, s);
   int64_t* ibeg = T.get<int64_t>(nleaf + 1);
-  k_seg_begins<<<grid_for(P.np + 1, 256), 256, 0, s>>>(key, P.np, nleaf, ibeg);
+  k_seg_begins<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(key, P.np, nleaf, ibeg);
   HM_LAUNCH_CHECK();
   P.col0 = T.get<int64_t>(nleaf);
   P.W = T.get<int64_t>(nleaf);
@@ -1604,7 +1635,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     k_gather_titems<<<grid_for(out.ntitems, 256), 256, 0, s>>>(raw, idx, out.ntitems, out.titems);
     HM_LAUNCH_CHECK();
     int64_t* lb = tt.get<int64_t>(nleaf + 1);
-    k_seg_begins<<<grid_for(out.ntitems + 1, 256), 256, 0, s>>>(key, out.ntitems, nleaf, lb);
+    k_seg_begins<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(key, out.ntitems, nleaf, lb);
     HM_LAUNCH_CHECK();
     out.tbeg = static_cast<int32_t*>(alloc((nleaf + 1) * sizeof(int32_t)));
     k_to_i32<<<grid_for(nleaf + 1, 256), 256, 0, s>>>(lb, nleaf + 1, out.tbeg);
