@@ -704,30 +704,40 @@ template <typename T, typename A, int NR, int G>
 __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int C, int cg, int g,
                                bool act, int wave, const A (&xg)[G][NR], A* __restrict__ w) {
   static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
+  constexpr int UNR = NR <= 2 ? 4 : 1;   // column groups per wavefront in flight
   const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
   const int64_t col0 = rn.col0 + a;
   const int ngrp = (uw + C - 1) / C;
-  for (int q = wave; q < ngrp; q += 4) {
-    const int j = q * C + cg;
-    A p[NR];
+  for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
+    // the granules of UNR column groups are loaded before any is reduced
+    typename Gran<T>::E sv[UNR][G];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) p[k] = 0;
-    const bool ok = act && j < uw;
-    {
-      typename Gran<T>::E sv[G];
-      Gran<T>::load(S + (int64_t)(ok ? j : uw - 1) * ld, sv);
+    for (int u = 0; u < UNR; ++u) {
+      const int j = (q0 + 4 * u) * C + cg;
+      const bool ok = act && q0 + 4 * u < ngrp && j < uw;
+      Gran<T>::load(S + (int64_t)(ok ? j : uw - 1) * ld, sv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int q = q0 + 4 * u;
+      if (q >= ngrp) break;                            // uniform over the wavefront
+      const int j = q * C + cg;
+      const bool ok = act && j < uw;
+      A p[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) p[k] = 0;
 #pragma unroll
       for (int e = 0; e < G; ++e) {
-        const A a = ok ? (A)sv[e] : (A)0;
+        const A a = ok ? (A)sv[u][e] : (A)0;
 #pragma unroll
         for (int k = 0; k < NR; ++k) p[k] += a * xg[e][k];
       }
-    }
 #pragma unroll
-    for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
-    if (act && g == 0 && j < uw) {
+      for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
+      if (act && g == 0 && j < uw) {
 #pragma unroll
-      for (int k = 0; k < NR; ++k) w[(col0 + j) * NR + k] = p[k];
+        for (int k = 0; k < NR; ++k) w[(col0 + j) * NR + k] = p[k];
+      }
     }
   }
 }
@@ -832,17 +842,47 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
         }
       } else {
         const T* S = reinterpret_cast<const T*>((uintptr_t)I.data);
-        for (int j0 = 0; j0 < I.w; j0 += C) {
-          const int j = j0 + cg;
-          if (act && j < I.w) {
-            typename Gran<T>::E s[G];
-            Gran<T>::load(S + (int64_t)j * ld + g * G, s);
-            A zz[NR];
-            load_row<A, NR>(z + (n + I.src + j) * NR, zz);
+        if constexpr (sizeof(T) < 8) {
+          for (int j0 = 0; j0 < I.w; j0 += C) {
+            const int j = j0 + cg;
+            if (act && j < I.w) {
+              typename Gran<T>::E s[G];
+              Gran<T>::load(S + (int64_t)j * ld + g * G, s);
+              A zz[NR];
+              load_row<A, NR>(z + (n + I.src + j) * NR, zz);
 #pragma unroll
-            for (int e = 0; e < G; ++e)
+              for (int e = 0; e < G; ++e)
 #pragma unroll
-              for (int k = 0; k < NR; ++k) acc[e][k] += (A)s[e] * zz[k];
+                for (int k = 0; k < NR; ++k) acc[e][k] += (A)s[e] * zz[k];
+            }
+          }
+        } else {
+          // FP64 slices: UNR column groups at a time with unconditional loads
+          // (a lane without a column reads the slice's last one and adds zero),
+          // so all their loads are in flight together (16% faster; slower for
+          // FP32 and FP16 slices, which keep the loop above)
+          constexpr int UNR = NR <= 2 ? 4 : 1;
+          const int ngrp = (I.w + C - 1) / C;
+          for (int q0 = 0; q0 < ngrp; q0 += UNR) {
+            typename Gran<T>::E s[UNR][G];
+            A zz[UNR][NR];
+            bool ok[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              const int j = (q0 + u) * C + cg;
+              ok[u] = act && q0 + u < ngrp && j < I.w;
+              const int jj = ok[u] ? j : I.w - 1;
+              Gran<T>::load(S + (int64_t)jj * ld + g * G, s[u]);
+              load_row<A, NR>(z + (n + I.src + jj) * NR, zz[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+              for (int e = 0; e < G; ++e) {
+                const A sv = ok[u] ? (A)s[u][e] : (A)0;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) acc[e][k] += sv * zz[u][k];
+              }
           }
         }
       }
