@@ -25,6 +25,9 @@ COMMON = [
 ]
 # files whose floating point must round exactly like the plain definition
 NO_CONTRACT = {"hm_geom.hip"}
+# files with matrix-core kernels: MFMA accumulators in ordinary vector
+# registers (no copies to and from the accumulation registers per product)
+MFMA_VGPR = {"hm_matvec.hip"}
 
 
 def hipcc() -> str:
@@ -37,6 +40,8 @@ def _compile(src: str) -> str:
     flags = list(COMMON)
     if os.path.basename(src) in NO_CONTRACT:
         flags.append("-ffp-contract=off")
+    if os.path.basename(src) in MFMA_VGPR:
+        flags += ["-mllvm", "-amdgpu-mfma-vgpr-form"]
     cmd = [hipcc(), *flags, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -545,7 +545,45 @@ template <typename T>
 __device__ inline double widen(T v) { return (double)v; }
 
 // Phase 1: one wavefront per admissible block, term tiles of 16 (up to four
-// per pass), rows in quads.
+// per pass), rows in quads.  NTL term tiles of one pass: two row quads at a
+// time, every load unconditional (clamped to the slice, the value zeroed
+// outside it) and every product issued, so no branch surrounds an MFMA; a
+// quad past the slice contributes exact zeros; rows go in in order.
+template <typename T, int NR, int NTL>
+__device__ inline void fwd1x_pass(const LrMeta& M, const MvLeaves& L,
+                                  const double* __restrict__ zx, int tg, int r, int lr, int lq,
+                                  f64x4 (&acc)[4]) {
+  constexpr int IU = 2;
+  const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
+  int lo = L.lo[M.sf];                    // the leaves of sigma are consecutive
+  for (int lf = M.sf; lf <= M.sl; ++lf) {
+    const int m = L.m[lf];
+    const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+    for (int i00 = 0; i00 < m; i00 += 4 * IU) {
+      double bv[IU], av[IU][NTL];
+#pragma unroll
+      for (int u = 0; u < IU; ++u) {
+        const int i = i00 + 4 * u + lq;
+        const bool ok = i < m;
+        const int ic = ok ? i : m - 1;
+        bv[u] = (ok && lr < NR) ? zx[(int64_t)(lo + ic) * NR + lr] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+          const int term = tg + t * 16 + lr;
+          const T v = S[(int64_t)min(term, r - 1) * ld + ic];
+          av[u][t] = (ok && term < r) ? widen(v) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < IU; ++u)
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av[u][t], bv[u], acc[t]);
+    }
+    S += (int64_t)ld * r;
+    lo += m;
+  }
+}
+
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, int64_t nl,
                                                MvLeaves L, const double* __restrict__ zx,
@@ -565,25 +603,11 @@ __global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, 
       f64x4 acc[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-      const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
-      int lo = L.lo[M.sf];                  // the leaves of sigma are consecutive
-      for (int lf = M.sf; lf <= M.sl; ++lf) {
-        const int m = L.m[lf];
-        const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
-        for (int i0 = 0; i0 < m; i0 += 4) {
-          const int i = i0 + lq;               // < ld: ld is m rounded up to 4
-          const double bv = (i < m && lr < NR) ? zx[(int64_t)(lo + i) * NR + lr] : 0.0;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (t < ntile) {                   // uniform over the wavefront
-              const int term = tg + t * 16 + lr;
-              const double av = term < r ? widen(S[(int64_t)term * ld + i]) : 0.0;
-              acc[t] = mfma16(av, bv, acc[t]);
-            }
-          }
-        }
-        S += (int64_t)ld * r;
-        lo += m;
+      switch (ntile) {                        // uniform over the wavefront
+        case 1: fwd1x_pass<T, NR, 1>(M, L, zx, tg, r, lr, lq, acc); break;
+        case 2: fwd1x_pass<T, NR, 2>(M, L, zx, tg, r, lr, lq, acc); break;
+        case 3: fwd1x_pass<T, NR, 3>(M, L, zx, tg, r, lr, lq, acc); break;
+        default: fwd1x_pass<T, NR, 4>(M, L, zx, tg, r, lr, lq, acc); break;
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -602,6 +626,50 @@ __global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, 
   }
 }
 
+// The column quads of one z tile for a leaf of NT 16-row tiles: KQ quads per
+// wavefront at a time, every load unconditional (clamped to the panel, the
+// value zeroed outside it) and every product issued, so the loop has no
+// branch around an MFMA and the accumulators stay in place.  A quad past the
+// tile contributes exact zeros; the products go in in column order.
+template <typename E, int NR, int NT, int KQ>
+__device__ inline void fwd2x_tile(const E* __restrict__ P, int64_t cbase, int ld, int tw,
+                                  const double* __restrict__ zs, int wave, int lr, int lq,
+                                  f64x4 (&acc)[4]) {
+  for (int q0 = wave; q0 * 4 < tw; q0 += 4 * KQ) {
+    double bv[KQ], av[KQ][NT];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) {
+      const int col = (q0 + 4 * u) * 4 + lq;
+      const bool okc = col < tw;
+      const int colc = okc ? col : tw - 1;
+      bv[u] = (okc && lr < NR) ? zs[colc * NR + lr] : 0.0;
+      const E* pc = P + (cbase + colc) * ld;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int row = t * 16 + lr;
+        const E v = pc[min(row, ld - 1)];
+        av[u][t] = (okc && row < ld) ? widen(v) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KQ; ++u)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t] = mfma16(av[u][t], bv[u], acc[t]);
+  }
+}
+
+template <typename E, int NR, int KQ>
+__device__ inline void fwd2x_tile_nt(int nrt, const E* __restrict__ P, int64_t cbase, int ld,
+                                     int tw, const double* __restrict__ zs, int wave, int lr,
+                                     int lq, f64x4 (&acc)[4]) {
+  switch (nrt) {                                        // uniform over the workgroup
+    case 1: fwd2x_tile<E, NR, 1, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    case 2: fwd2x_tile<E, NR, 2, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    case 3: fwd2x_tile<E, NR, 3, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    default: fwd2x_tile<E, NR, 4, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+  }
+}
+
 // Phase 2: one workgroup per work unit; the unit's z values are staged in
 // LDS per tile, each wavefront takes column quads round-robin and keeps one
 // accumulator per 16-row tile of the leaf; the four wavefronts are added in
@@ -613,7 +681,7 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
                                                const double* __restrict__ z,
                                                double* __restrict__ ypart, int ldmax) {
   static_assert(NR == 8 || NR == 16, "MFMA phase 2 takes 8 or 16 right-hand sides");
-  constexpr int kQuads = sizeof(TD) == 8 ? 2 : 1;
+  constexpr int kQuads = 2;
   // the z tile and the final combination of the wavefronts share one LDS
   // buffer (the tile is consumed before the combination starts)
   constexpr int kTile = (4 * kMaxLeaf * NR) / NR;     // columns: 256
@@ -646,36 +714,12 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
       }
       __syncthreads();
       const int64_t cbase = (int64_t)U.a + t0;          // first panel column of the tile
-      // kQuads column quads per wavefront at a time (two for FP64 panels:
-      // their loads are then in flight together, measured 32% faster; one
-      // for FP32, where two were not faster); the products go in in the
-      // same (column) order
-      for (int q0 = wave; q0 * 4 < tw; q0 += 4 * kQuads) {
-        double bv[kQuads], av[kQuads][4];
-#pragma unroll
-        for (int u = 0; u < kQuads; ++u) {
-          const int col = (q0 + 4 * u) * 4 + lq;
-          const bool okc = col < tw;
-          bv[u] = (okc && lr < NR) ? zs[(okc ? col : 0) * NR + lr] : 0.0;
-          const int64_t coff = (cbase + (okc ? col : 0)) * ld;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int row = t * 16 + lr;
-            av[u][t] = 0.0;
-            if (t < nrt && okc && row < ld)
-              av[u][t] = dense ? widen(reinterpret_cast<const TD*>((uintptr_t)rn.data)[coff + row])
-                               : widen(reinterpret_cast<const TL*>((uintptr_t)rn.data)[coff + row]);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kQuads; ++u) {
-          if ((q0 + 4 * u) * 4 < tw) {                  // uniform over the wavefront
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-              if (t < nrt) acc[t] = mfma16(av[u][t], bv[u], acc[t]);
-          }
-        }
-      }
+      if (dense)
+        fwd2x_tile_nt<TD, NR, kQuads>(nrt, reinterpret_cast<const TD*>((uintptr_t)rn.data), cbase,
+                                      ld, tw, zs, wave, lr, lq, acc);
+      else
+        fwd2x_tile_nt<TL, NR, kQuads>(nrt, reinterpret_cast<const TL*>((uintptr_t)rn.data), cbase,
+                                      ld, tw, zs, wave, lr, lq, acc);
     }
     __syncthreads();                                    // the last tile is consumed
 #pragma unroll
