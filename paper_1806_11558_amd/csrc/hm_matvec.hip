@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
                                                const double* __restrict__ z,
                                                double* __restrict__ ypart, int ldmax) {
   static_assert(NR == 8 || NR == 16, "MFMA phase 2 takes 8 or 16 right-hand sides");
-  constexpr int kQuads = 2;
+  constexpr int kQuads = 4;
   // the z tile and the final combination of the wavefronts share one LDS
   // buffer (the tile is consumed before the combination starts)
   constexpr int kTile = (4 * kMaxLeaf * NR) / NR;     // columns: 256
