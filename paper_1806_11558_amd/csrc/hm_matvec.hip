@@ -153,6 +153,57 @@ __device__ inline void fwd1_flush(A (&p)[NR], int g, int R, int j0, int C, int r
   }
 }
 
+// The slices of one block with every column-leaf slice of ld rows: P passes
+// of C columns, P known at compile time so that the granules of all passes
+// are loaded with no branch between them and the x loads; columns past r
+// read column r - 1 into accumulators that are never flushed.
+template <typename T, typename A, int NR, int P>
+__device__ inline void fwd1_uniform(const LrMeta& M, const MvLeaves& L, const A* __restrict__ z,
+                                    int r, int ld, int R, int C, int cg, int g, bool act, int lane,
+                                    A (&tl)[NR]) {
+  constexpr int G = Gran<T>::G;
+  A acc[P][NR];
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[q][k] = 0;
+  // 32-bit element offsets of the lane's granule in each pass
+  int off[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) off[q] = min(q * C + cg, r - 1) * ld + g * G;
+  const int sstride = ld * r;
+  const T* Sl = reinterpret_cast<const T*>((uintptr_t)M.vptr);
+  int lo = L.lo[M.sf];                       // the leaves of sigma are consecutive
+  for (int lf = M.sf; lf <= M.sl; ++lf, Sl += sstride) {
+    const int m = L.m[lf];
+    typename Gran<T>::E sv[P][G];
+#pragma unroll
+    for (int q = 0; q < P; ++q) Gran<T>::load(Sl + off[q], sv[q]);
+    A xg[G][NR];
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      // unconditional load of a clamped row, zeroed outside the slice
+      const int row = g * G + e;
+      const bool in = act && row < m;
+      const A* zr = z + (int64_t)(lo + (in ? row : 0)) * NR;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const A v = zr[k];
+        xg[e][k] = in ? v : (A)0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+#pragma unroll
+      for (int e = 0; e < G; ++e)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[q][k] += (A)sv[q][e] * xg[e][k];
+    lo += m;
+  }
+#pragma unroll
+  for (int q = 0; q < P; ++q) fwd1_flush<A, NR>(acc[q], g, R, q * C, C, r, lane, tl);
+}
+
 template <typename T, typename A, int NR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_fwd1(const LrMeta* __restrict__ meta, int64_t nl,
                                               MvLeaves L, A* __restrict__ z, int64_t n,
@@ -183,50 +234,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
       const int cg = (int)(((unsigned)lane * mul) >> 16), g = lane - cg * R;
       const bool act = cg < C;
       const int P = (r + C - 1) / C;
-      A acc[PMAX][NR];
-#pragma unroll
-      for (int q = 0; q < PMAX; ++q)
-#pragma unroll
-        for (int k = 0; k < NR; ++k) acc[q][k] = 0;
-      // 32-bit element offsets of the lane's granule in each pass; columns
-      // past r read column r - 1 into accumulators that are never flushed
-      int off[PMAX];
-#pragma unroll
-      for (int q = 0; q < PMAX; ++q) off[q] = min(q * C + cg, r - 1) * ld + g * G;
-      const int sstride = ld * r;
-      const T* Sl = S;
-      int lo = L.lo[M.sf];                   // the leaves of sigma are consecutive
-      for (int lf = M.sf; lf <= M.sl; ++lf, Sl += sstride) {
-        const int m = L.m[lf];
-        A xg[G][NR];
-#pragma unroll
-        for (int e = 0; e < G; ++e) {
-          // unconditional load of a clamped row, zeroed outside the slice
-          const int row = g * G + e;
-          const bool in = act && row < m;
-          const A* zr = z + (int64_t)(lo + (in ? row : 0)) * NR;
-#pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const A v = zr[k];
-            xg[e][k] = in ? v : (A)0;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < PMAX; ++q) {
-          if (q < P) {                                  // uniform over the wavefront
-            typename Gran<T>::E sv[G];
-            Gran<T>::load(Sl + off[q], sv);
-#pragma unroll
-            for (int e = 0; e < G; ++e)
-#pragma unroll
-              for (int k = 0; k < NR; ++k) acc[q][k] += (A)sv[e] * xg[e][k];
-          }
-        }
-        lo += m;
+      switch (P) {                                      // uniform over the wavefront
+        case 1: fwd1_uniform<T, A, NR, 1>(M, L, z, r, ld, R, C, cg, g, act, lane, tl); break;
+        case 2:
+          if constexpr (PMAX >= 2) fwd1_uniform<T, A, NR, 2>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
+        case 3:
+          if constexpr (PMAX >= 3) fwd1_uniform<T, A, NR, 3>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
+        default:
+          if constexpr (PMAX >= 4) fwd1_uniform<T, A, NR, 4>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
       }
-#pragma unroll
-      for (int q = 0; q < PMAX; ++q)
-        if (q < P) fwd1_flush<A, NR>(acc[q], g, R, q * C, C, r, lane, tl);
     } else {
       for (int lf = M.sf; lf <= M.sl; ++lf) {
         const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
