@@ -165,14 +165,23 @@ __global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restri
         xr[2][i] = g.c[2 * g.n + lo + i];
       }
       __syncthreads();
+      // entry e = i + ld j; (i, j) advance by a fixed step instead of a
+      // division per entry
+      const int di = (int)blockDim.x % ld, dj = (int)blockDim.x / ld;
+      int i = (int)threadIdx.x % ld, j = (int)threadIdx.x / ld;
       for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
-        const int i = e % ld, j = e / ld;
         T v = 0;
         if (i < m) {
           const Src<T> sj = src[j];
           v = eval_entry(xr[0][i], xr[1][i], xr[2][i], lo + i, sj, sig.x + j);
         }
         dst[e] = v;
+        i += di;
+        j += dj;
+        if (i >= ld) {
+          i -= ld;
+          ++j;
+        }
       }
       __syncthreads();                                  // before the next slice is staged
     } else {
