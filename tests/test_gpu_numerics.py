@@ -180,6 +180,37 @@ def test_edge_sizes(level, nsub, leaf):
     H.free()
 
 
+@pytest.mark.parametrize("nsub,leaf,ld", [(1000, 8, 8), (1000, 32, 32), (1280, 64, 40),
+                                           (1000, 64, 64)])
+@pytest.mark.parametrize("prec,eps,bound", [("f64", 1e-8, 1e-7), ("f32", 1e-6, 1e-5)])
+def test_products_every_row_tile_count(nsub, leaf, ld, prec, eps, bound):
+    """Leaves padded to ld = 8, 32, 40 and 64 rows: the 16-row tiles of the
+    MFMA products (1..4), the pass counts of phase 1 and the granule rows of
+    the one-column kernels all occur.  Forward and transposed products with
+    1, 8 and 16 right-hand sides, every column against the dense oracle."""
+    import paper_1806_11558_amd as hm
+    from oracle import bem
+    from synthetic import icosphere, normal_columns
+    V, T = icosphere(3)
+    T = T[:nsub]
+    say("tile counts", nsub, leaf, prec)
+    op = bem.Operator(V, T)
+    A = op.dense()
+    H = hm.HMatrix(V, T, leaf_size=leaf, eps=eps, precision=prec)
+    lv = H.leaves()                               # (lo, size, ld) per leaf
+    assert int(lv[:, 2].max()) == ld
+    for nrhs in (1, 8, 16):
+        x = normal_columns(op.n, nrhs, seed=nrhs)
+        xt = torch.tensor(x[:, 0] if nrhs == 1 else x, device=DEV)
+        y = H.matvec(xt).cpu().numpy().reshape(op.n, -1)
+        yT = H.matvec_T(xt).cpu().numpy().reshape(op.n, -1)
+        ref, refT = A @ x, A.T @ x
+        for k in range(nrhs):
+            assert rel2(y[:, k], ref[:, k]) <= bound, (nrhs, k)
+            assert rel2(yT[:, k], refT[:, k]) <= bound, (nrhs, k)
+    H.free()
+
+
 def test_zonal_harmonic_solves_n81920_fp32():
     """f = Y_l (l = 0..8, nine right-hand sides in one solve) at N = 81,920,
     FP32 form, eps 1e-5, GMRES to 1e-6.  The continuous solution is
