@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_minmax_partial(const double* __restrict
   }
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+    if ((int)threadIdx.x < s) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         lds[d][threadIdx.x] = fmin(lds[d][threadIdx.x], lds[d][threadIdx.x + s]);

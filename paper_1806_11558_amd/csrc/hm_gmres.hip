@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kGT) void k_dots(const double* __restrict__ Q, int6
   }
   lds[threadIdx.x] = (r0 < per) ? acc : 0.0;
   __syncthreads();
-  if (threadIdx.x < nr) {
+  if ((int)threadIdx.x < nr) {
     double s = 0.0;
     for (int t = 0; t < per; ++t) s += lds[t * nr + threadIdx.x];
     part[((int64_t)k * tiles + tile) * nr + threadIdx.x] = s;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kGT) void k_dots_dev(const double* __restrict__ Q, 
   }
   lds[threadIdx.x] = (r0 < per) ? acc : 0.0;
   __syncthreads();
-  if (threadIdx.x < nr) {
+  if ((int)threadIdx.x < nr) {
     double s = 0.0;
     for (int t = 0; t < per; ++t) s += lds[t * nr + threadIdx.x];
     part[((int64_t)k * tiles + tile) * nr + threadIdx.x] = s;
