@@ -110,6 +110,57 @@ constexpr int kMaxGeoms = 65536;
 // unit widths the product autotuner tries, the smallest first
 constexpr int kTuneCols[] = {512, 1024, 2048, 4096, 8192};
 
+// Block statistics of a build, summed on the device: out[0] dense entries,
+// [1] low-rank entries sum r (m + n), [2] U entries sum r m, [3] rank sum,
+// [4] rank max, [5] cap hits, [6] ACA entry evaluations (rows evaluated n +
+// r m).  out must be zero on entry; one atomic per wavefront and value.
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  return v;
+}
+__device__ inline unsigned long long wave_max_u64(unsigned long long v) {
+  for (int s = 32; s > 0; s >>= 1) {
+    const unsigned long long o = __shfl_xor(v, s, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__global__ void k_block_stats(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
+                              int64_t nl, const int4* __restrict__ cl,
+                              const int32_t* __restrict__ rank, const int32_t* __restrict__ info,
+                              unsigned long long* __restrict__ out) {
+  unsigned long long v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nd + nl;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    if (b < nd) {
+      const int4 t = cl[dns[b].x], sg = cl[dns[b].y];
+      v[0] += (unsigned long long)(t.y - t.x) * (unsigned long long)(sg.y - sg.x);
+    } else {
+      const int64_t k = b - nd;
+      const int4 t = cl[lr[k].x], sg = cl[lr[k].y];
+      const unsigned long long m = t.y - t.x, nn = sg.y - sg.x, r = rank[k];
+      const unsigned long long rows = (unsigned)info[k] >> 1;
+      v[1] += r * (m + nn);
+      v[2] += r * m;
+      v[3] += r;
+      v[4] = r > v[4] ? r : v[4];
+      v[5] += (unsigned)info[k] & 1u;
+      v[6] += rows * nn + r * m;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) v[k] = k == 4 ? wave_max_u64(v[k]) : wave_sum_u64(v[k]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      if (k == 4)
+        atomicMax(out + k, v[k]);
+      else
+        atomicAdd(out + k, v[k]);
+    }
+  }
+}
+
 }  // namespace hm
 
 using namespace hm;
@@ -460,17 +511,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   dfree(tmp, s);
   release_cached_memory(s);
 
-  // ---- statistics
-  std::vector<int32_t> rk(h->nl), inf(h->nl);
-  std::vector<int2> lrh(h->nl), dnh(h->nd);
-  std::vector<Cluster> clh(h->ncl);
-  if (h->nl) {
-    HM_HIP(hipMemcpy(rk.data(), h->sto.rank, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HM_HIP(hipMemcpy(inf.data(), h->sto.info, h->nl * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HM_HIP(hipMemcpy(lrh.data(), h->lr, h->nl * sizeof(int2), hipMemcpyDeviceToHost));
-  }
-  if (h->nd) HM_HIP(hipMemcpy(dnh.data(), h->dns, h->nd * sizeof(int2), hipMemcpyDeviceToHost));
-  HM_HIP(hipMemcpy(clh.data(), h->cl, h->ncl * sizeof(Cluster), hipMemcpyDeviceToHost));
+  // ---- statistics: block sums on the device, one small copy back
   hm_stats& st = h->st;
   std::memset(&st, 0, sizeof(st));
   st.n = n;
@@ -479,20 +520,25 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   st.n_dense = h->nd;
   st.n_lr = h->nl;
   st.depth = h->depth;
-  for (int64_t b = 0; b < h->nd; ++b) {
-    const Cluster t = clh[dnh[b].x], sg = clh[dnh[b].y];
-    st.dense_entries += (int64_t)(t.y - t.x) * (sg.y - sg.x);
-  }
-  for (int64_t b = 0; b < h->nl; ++b) {
-    const Cluster t = clh[lrh[b].x], sg = clh[lrh[b].y];
-    const int64_t m = t.y - t.x, nn = sg.y - sg.x;
-    st.lr_entries += (int64_t)rk[b] * (m + nn);
-    st.lr_u_entries += (int64_t)rk[b] * m;
-    st.rank_sum += rk[b];
-    st.rank_max = std::max<int64_t>(st.rank_max, rk[b]);
-    st.cap_hits += inf[b] & 1;
-    const int64_t rows = inf[b] >> 1;
-    st.aca_entry_evals += rows * nn + (int64_t)rk[b] * m;
+  {
+    unsigned long long* dsum = static_cast<unsigned long long*>(dalloc(7 * sizeof(unsigned long long), s));
+    HM_HIP(hipMemsetAsync(dsum, 0, 7 * sizeof(unsigned long long), s));
+    if (h->nd + h->nl > 0) {
+      k_block_stats<<<grid_for(h->nd + h->nl, 256, 4096), 256, 0, s>>>(
+          h->dns, h->nd, h->lr, h->nl, h->cl, h->sto.rank, h->sto.info, dsum);
+      HM_LAUNCH_CHECK();
+    }
+    unsigned long long hs[7];
+    HM_HIP(hipMemcpyAsync(hs, dsum, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    dfree(dsum, s);
+    st.dense_entries = (int64_t)hs[0];
+    st.lr_entries = (int64_t)hs[1];
+    st.lr_u_entries = (int64_t)hs[2];
+    st.rank_sum = (int64_t)hs[3];
+    st.rank_max = (int64_t)hs[4];
+    st.cap_hits = (int64_t)hs[5];
+    st.aca_entry_evals = (int64_t)hs[6];
   }
   st.stored_bytes = h->sto.D_elems * (int64_t)sizeof(T) + h->sto.lr_elems * (int64_t)sizeof(TL);
   st.n_panel_cols = h->sto.ncols;
