@@ -125,7 +125,7 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v) {
   }
   return v;
 }
-__global__ void k_block_stats(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
+__global__ __launch_bounds__(256) void k_block_stats(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
                               int64_t nl, const int4* __restrict__ cl,
                               const int32_t* __restrict__ rank, const int32_t* __restrict__ info,
                               unsigned long long* __restrict__ out) {
@@ -148,16 +148,24 @@ __global__ void k_block_stats(const int2* __restrict__ dns, int64_t nd, const in
       v[6] += rows * nn + r * m;
     }
   }
+  // wave reduction, then the 4 waves through LDS: one atomic per value and workgroup
+  __shared__ unsigned long long part[4][7];
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 7; ++k) v[k] = k == 4 ? wave_max_u64(v[k]) : wave_sum_u64(v[k]);
-  if ((threadIdx.x & 63) == 0) {
+  if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      if (k == 4)
-        atomicMax(out + k, v[k]);
-      else
-        atomicAdd(out + k, v[k]);
-    }
+    for (int k = 0; k < 7; ++k) part[wave][k] = v[k];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 7) {
+    const int k = (int)threadIdx.x;
+    unsigned long long a = part[0][k];
+    for (int w = 1; w < 4; ++w) a = k == 4 ? (part[w][k] > a ? part[w][k] : a) : a + part[w][k];
+    if (k == 4)
+      atomicMax(out + k, a);
+    else
+      atomicAdd(out + k, a);
   }
 }
 
@@ -524,7 +532,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     unsigned long long* dsum = static_cast<unsigned long long*>(dalloc(7 * sizeof(unsigned long long), s));
     HM_HIP(hipMemsetAsync(dsum, 0, 7 * sizeof(unsigned long long), s));
     if (h->nd + h->nl > 0) {
-      k_block_stats<<<grid_for(h->nd + h->nl, 256, 4096), 256, 0, s>>>(
+      k_block_stats<<<grid_for(h->nd + h->nl, 256, 256), 256, 0, s>>>(
           h->dns, h->nd, h->lr, h->nl, h->cl, h->sto.rank, h->sto.info, dsum);
       HM_LAUNCH_CHECK();
     }

@@ -162,8 +162,11 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int64_t* in, i
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+// out[i] = offs[tile] + the exclusive prefix of in within the tile; the
+// thread of element n - 1 also writes the grand total when total is given.
 __global__ __launch_bounds__(kScanThreads) void k_tile_apply(const int64_t* in, int64_t* out,
-                                                             int64_t n, const int64_t* offs) {
+                                                             int64_t n, const int64_t* offs,
+                                                             int64_t* total) {
   __shared__ int64_t lds_w[kScanThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   int64_t loc[kScanPer];
@@ -181,12 +184,9 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_apply(const int64_t* in, 
   for (int k = 0; k < kScanPer; ++k) {
     int64_t i = base + (int64_t)threadIdx.x * kScanPer + k;
     if (i < n) out[i] = run;
+    if (total && i == n - 1) *total = run + loc[k];
     run += loc[k];
   }
-}
-
-__global__ void k_total(const int64_t* in, const int64_t* out, int64_t n, int64_t* total) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *total = (n > 0) ? out[n - 1] + in[n - 1] : 0;
 }
 }  // namespace
 
@@ -197,7 +197,7 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* d_total,
   }
   const int64_t tiles = ceil_div(n, kScanTile);
   if (tiles == 1) {
-    k_tile_apply<<<1, kScanThreads, 0, s>>>(in, out, n, nullptr);
+    k_tile_apply<<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, d_total);
     HM_LAUNCH_CHECK();
   } else {
     int64_t* sums = dalloc_t<int64_t>(tiles, s);
@@ -205,14 +205,10 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* d_total,
     k_tile_sums<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, n, sums);
     HM_LAUNCH_CHECK();
     scan_excl_i64(sums, offs, tiles, nullptr, s);
-    k_tile_apply<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, out, n, offs);
+    k_tile_apply<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, out, n, offs, d_total);
     HM_LAUNCH_CHECK();
     dfree(sums, s);
     dfree(offs, s);
-  }
-  if (d_total) {
-    k_total<<<1, 64, 0, s>>>(in, out, n, d_total);
-    HM_LAUNCH_CHECK();
   }
 }
 
