@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
     for (int k = 0; k < NR; ++k) tl[k] = 0;
     const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
     const int R0 = M.vld / G, C0 = R0 > 0 ? 64 / R0 : 1;
-    if (M.vld > 0 && r <= PMAX * C0) {
+    if (M.vld > 0 && r <= PMAX * C0 && r <= 64) {
       const int ld = M.vld, R = R0, C = C0;
       // lane / R by a multiply and shift (exact for lane < 64, R <= 64)
       const unsigned mul = (unsigned)(65536.0f / (float)R) + 1u;
@@ -247,42 +247,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
           break;
       }
     } else {
-      for (int lf = M.sf; lf <= M.sl; ++lf) {
-        const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
-        const int R = ld / G, C = 64 / R;
-        const int cg = lane / R, g = lane % R;
-        const bool act = cg < C;
-        const int m = L.m[lf], lo = L.lo[lf];
-        A xg[G][NR];
+      // general path, 64 terms (one per lane) at a time
+      for (int t0 = 0; t0 < r; t0 += 64) {
+        const int rc = min(64, r - t0);
+        const T* Sl = S;
 #pragma unroll
-        for (int e = 0; e < G; ++e) {
-          const int row = g * G + e;
+        for (int k = 0; k < NR; ++k) tl[k] = 0;
+        for (int lf = M.sf; lf <= M.sl; ++lf) {
+          const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+          const int R = ld / G, C = 64 / R;
+          const int cg = lane / R, g = lane % R;
+          const bool act = cg < C;
+          const int m = L.m[lf], lo = L.lo[lf];
+          A xg[G][NR];
 #pragma unroll
-          for (int k = 0; k < NR; ++k)
-            xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
-        }
-        for (int j0 = 0; j0 < r; j0 += C) {
-          const int j = j0 + cg;
-          A p[NR];
+          for (int e = 0; e < G; ++e) {
+            const int row = g * G + e;
 #pragma unroll
-          for (int k = 0; k < NR; ++k) p[k] = 0;
-          if (act && j < r) {
-            typename Gran<T>::E sv[G];
-            Gran<T>::load(S + (int64_t)j * ld + g * G, sv);
-#pragma unroll
-            for (int e = 0; e < G; ++e)
-#pragma unroll
-              for (int k = 0; k < NR; ++k) p[k] += (A)sv[e] * xg[e][k];
+            for (int k = 0; k < NR; ++k)
+              xg[e][k] = (act && row < m) ? z[(int64_t)(lo + row) * NR + k] : (A)0;
           }
-          fwd1_flush<A, NR>(p, g, R, j0, C, r, lane, tl);
+          for (int j0 = 0; j0 < rc; j0 += C) {
+            const int j = j0 + cg;
+            A p[NR];
+#pragma unroll
+            for (int k = 0; k < NR; ++k) p[k] = 0;
+            if (act && j < rc) {
+              typename Gran<T>::E sv[G];
+              Gran<T>::load(Sl + (int64_t)(t0 + j) * ld + g * G, sv);
+#pragma unroll
+              for (int e = 0; e < G; ++e)
+#pragma unroll
+                for (int k = 0; k < NR; ++k) p[k] += (A)sv[e] * xg[e][k];
+            }
+            fwd1_flush<A, NR>(p, g, R, j0, C, rc, lane, tl);
+          }
+          Sl += (int64_t)ld * r;
         }
-        S += (int64_t)ld * r;
+        if (t0 + 64 < r && lane < rc) {       // every chunk but the last one
+          const A sc = su ? (A)su[M.toff + t0 + lane] : (A)1;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) z[(n + M.toff + t0 + lane) * NR + k] = tl[k] * sc;
+        }
       }
     }
-    if (lane < r) {
-      const A sc = su ? (A)su[M.toff + lane] : (A)1;
+    // terms 64 q + lane of the last chunk q (the only chunk when r <= 64)
+    const int tlast = r > 64 ? (r - 1) / 64 * 64 : 0;
+    if (tlast + lane < r) {
+      const A sc = su ? (A)su[M.toff + tlast + lane] : (A)1;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = tl[k] * sc;
+      for (int k = 0; k < NR; ++k) z[(n + M.toff + tlast + lane) * NR + k] = tl[k] * sc;
     }
   }
 }
@@ -851,38 +865,59 @@ __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta
   const int64_t nw = (int64_t)gridDim.x * 4;
   for (int64_t b = wid; b < nl; b += nw) {
     const LrMeta M = meta[b];
-    if (lane >= M.r) continue;
-    A acc[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0;
     const int nk = M.tl - M.tf + 1;
-    for (int q = 0; q < nk; ++q) {
-      const int64_t col = ucol[M.ub + q] + lane;
+    for (int l = lane; l < M.r; l += 64) {               // 64 terms at a time
+      A acc[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
+      for (int k = 0; k < NR; ++k) acc[k] = 0;
+      // four row leaves per step with their loads in flight together; the
+      // sum runs over the row leaves in order
+      int q = 0;
+      for (; q + 4 <= nk; q += 4) {
+        A v[4][NR];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) load_row<A, NR>(w + (ucol[M.ub + q + u] + l) * NR, v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc[k] += v[u][k];
+      }
+      for (; q < nk; ++q) {
+        const int64_t col = ucol[M.ub + q] + l;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
+      }
+      const A sc = su ? (A)su[M.toff + l] : (A)1;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) z[(n + M.toff + l) * NR + k] = acc[k] * sc;
     }
-    const A sc = su ? (A)su[M.toff + lane] : (A)1;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) z[(n + M.toff + lane) * NR + k] = acc[k] * sc;
   }
 }
 
 // ------------------------------------------------------------------ transposed, phase 2
 // Per column leaf: dense blocks contribute w entries (kind 0, lane = output
-// row), V slices contribute V s (kind 1, granule product).
+// row), V slices contribute V s (kind 1, granule product).  The items of a
+// leaf are dealt to S workgroups (item i to workgroup (i / 4) mod S, wavefront
+// i mod 4), so that a leaf's few hundred slices are not one long chain of
+// dependent loads per wavefront; with S > 1 each workgroup writes its partial
+// rows to ypart[c S + s] and k_tr2_sum adds them in order of s.
 template <typename T, typename A, typename VT, int NR>
 __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
                                              const TItem* __restrict__ items, MvLeaves L,
                                              const A* __restrict__ w, const A* __restrict__ z,
                                              int64_t n, const int32_t* __restrict__ perm,
-                                             VT* __restrict__ y, int nrhs, int k0) {
+                                             VT* __restrict__ y, int nrhs, int k0, int S,
+                                             A* __restrict__ ypart, int ldmax) {
   constexpr int G = Gran<T>::G;
   __shared__ A ybuf[4][kMaxLeaf][NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t per = (L.nleaf + kXcds - 1) / kXcds;
+  const int64_t nwork = L.nleaf * S;
+  const int64_t per = (nwork + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
-    const int64_t c = xcd_item(li, per);
-    if (c >= L.nleaf) continue;                         // uniform over the workgroup
+    const int64_t q = xcd_item(li, per);
+    if (q >= nwork) continue;                           // uniform over the workgroup
+    const int64_t c = q / S;
+    const int sp = (int)(q - c * S);
     const int ld = (int)(L.ldpre[c + 1] - L.ldpre[c]);
     const int R = ld / G, C = 64 / R;
     const int cg = lane / R, g = lane % R;
@@ -896,7 +931,7 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
       for (int e = 0; e < G; ++e) acc[e][k] = 0;
     }
     const int b0 = beg[c], b1 = beg[c + 1];
-    for (int it = b0 + wave; it < b1; it += 4) {
+    for (int it = b0 + 4 * sp + wave; it < b1; it += 4 * S) {
       const TItem I = items[it];
       if (I.kind == 0) {
         if (lane < I.w) {
@@ -976,12 +1011,34 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
       for (int k = 0; k < NR; ++k) ybuf[wave][lane][k] += yT[k];
     }
     __syncthreads();
+    A* yp = ypart + q * ldmax * NR;
     for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
       const int row = e / NR, k = e % NR;
       const A v = ((ybuf[0][row][k] + ybuf[1][row][k]) + ybuf[2][row][k]) + ybuf[3][row][k];
-      y[(int64_t)perm[lo + row] * nrhs + k0 + k] = (VT)v;
+      if (S == 1)
+        y[(int64_t)perm[lo + row] * nrhs + k0 + k] = (VT)v;
+      else
+        yp[e] = v;
     }
     __syncthreads();
+  }
+}
+
+// y rows of every column leaf = sum of its S partial rows (in order of s),
+// scattered to application order.
+template <typename A, typename VT, int NR>
+__global__ __launch_bounds__(256) void k_tr2_sum(MvLeaves L, int S, const A* __restrict__ ypart,
+                                                 int ldmax, const int32_t* __restrict__ perm,
+                                                 VT* __restrict__ y, int nrhs, int k0) {
+  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+    const int m = L.m[c], lo = L.lo[c];
+    const A* yp = ypart + c * S * ldmax * NR;
+    for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
+      const int row = e / NR, k = e % NR;
+      A v = 0;
+      for (int sp = 0; sp < S; ++sp) v += yp[(int64_t)sp * ldmax * NR + e];
+      y[(int64_t)perm[lo + row] * nrhs + k0 + k] = (VT)v;
+    }
   }
 }
 
@@ -996,9 +1053,6 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   k_gather<VT, A><<<grid_for(P.n * NR, 256, 4096), 256, 0, s>>>(x, nrhs, k0, NR, P.perm, P.n, z);
   HM_LAUNCH_CHECK();
   if (pr) HM_HIP(hipEventRecord(pr->ev[1], s));
-  // leaves carry similar work: the per-leaf grids cover the XCD-ordered
-  // index range (a multiple of kXcds)
-  const unsigned gl = (unsigned)std::min<int64_t>(ceil_div(P.L.nleaf, kXcds) * kXcds, P.grid);
   // blocks differ widely in size and come largest first, so they stay
   // round-robin over the XCDs
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
@@ -1042,8 +1096,21 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
       HM_LAUNCH_CHECK();
     }
     if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
-    k_tr2<TL, A, VT, NR><<<gl, 256, 0, s>>>(P.tbeg, P.titems, P.L, w, z, P.n, P.perm, y, nrhs, k0);
+    // workgroups per column leaf: up to 8, as many as the unit workspace
+    // (at least (units + 1) ldmax rows of 16 doubles) holds partial rows for
+    const int64_t cap = (P.nunits + 1) * (int64_t)16 * (int64_t)sizeof(double) /
+                        ((int64_t)NR * (int64_t)sizeof(A));
+    const int S = (int)std::max<int64_t>(1, std::min<int64_t>(8, cap / std::max<int64_t>(1, P.L.nleaf)));
+    // leaves carry similar work: the grid covers the XCD-ordered index range
+    const unsigned gt = (unsigned)std::min<int64_t>(ceil_div(P.L.nleaf * S, kXcds) * kXcds, P.grid);
+    k_tr2<TL, A, VT, NR><<<gt, 256, 0, s>>>(P.tbeg, P.titems, P.L, w, z, P.n, P.perm, y, nrhs, k0,
+                                            S, static_cast<A*>(P.ypart), P.ldmax);
     HM_LAUNCH_CHECK();
+    if (S > 1) {
+      k_tr2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(P.L.nleaf, P.grid), 256, 0, s>>>(
+          P.L, S, static_cast<const A*>(P.ypart), P.ldmax, P.perm, y, nrhs, k0);
+      HM_LAUNCH_CHECK();
+    }
   }
   if (pr) {
     HM_HIP(hipEventRecord(pr->ev[4], s));

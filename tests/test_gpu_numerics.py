@@ -211,6 +211,33 @@ def test_products_every_row_tile_count(nsub, leaf, ld, prec, eps, bound):
     H.free()
 
 
+def test_products_ranks_above_64():
+    """Leaf 8, eta 5, ACA eps 1e-14, max_rank 128 at N = 1,280: the largest
+    admissible blocks (80 x 80) reach ranks above 64, so phase 1 and the
+    transposed block sums take their terms 64 at a time.  Forward and
+    transposed products with 1, 2, 4, 8 and 16 right-hand sides against the
+    dense oracle."""
+    import paper_1806_11558_amd as hm
+    from oracle import bem
+    from synthetic import icosphere, normal_columns
+    V, T = icosphere(3)
+    say("ranks above 64")
+    op = bem.Operator(V, T)
+    A = op.dense()
+    H = hm.HMatrix(V, T, leaf_size=8, eta=5.0, eps=1e-14, max_rank=128, precision="f64")
+    assert H.stats()["rank_max"] > 64
+    for nrhs in (1, 2, 4, 8, 16):
+        x = normal_columns(op.n, nrhs, seed=20 + nrhs)
+        xt = torch.tensor(x[:, 0] if nrhs == 1 else x, device=DEV)
+        y = H.matvec(xt).cpu().numpy().reshape(op.n, -1)
+        yT = H.matvec_T(xt).cpu().numpy().reshape(op.n, -1)
+        ref, refT = A @ x, A.T @ x
+        for k in range(nrhs):
+            assert rel2(y[:, k], ref[:, k]) <= 1e-10, (nrhs, k)
+            assert rel2(yT[:, k], refT[:, k]) <= 1e-10, (nrhs, k)
+    H.free()
+
+
 def test_zonal_harmonic_solves_n81920_fp32():
     """f = Y_l (l = 0..8, nine right-hand sides in one solve) at N = 81,920,
     FP32 form, eps 1e-5, GMRES to 1e-6.  The continuous solution is
