@@ -853,7 +853,10 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, MvLea
 }
 
 // s_b[l] = sum over the row leaves of b of w[ucol + l]  ->  z[n + toff + l].
-// One wavefront per block, lane = term l.
+// One wavefront per block.  With r <= 16 (32) the wavefront splits into four
+// (two) groups of 16 (32) lanes, lane = (group, term); group g adds the row
+// leaves q = g, g + groups, ... and the groups are added by shifts at the end.
+// Ranks above 64 take their terms 64 at a time.
 template <typename A, int NR>
 __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta, int64_t nl,
                                                  const int64_t* __restrict__ ucol,
@@ -866,30 +869,45 @@ __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta
   for (int64_t b = wid; b < nl; b += nw) {
     const LrMeta M = meta[b];
     const int nk = M.tl - M.tf + 1;
-    for (int l = lane; l < M.r; l += 64) {               // 64 terms at a time
+    const int gw = M.r <= 16 ? 16 : (M.r <= 32 ? 32 : 64);   // uniform over the wavefront
+    const int ng = 64 / gw, grp = lane / gw;
+    for (int t0 = 0; t0 < M.r; t0 += 64) {
+      const int l = t0 + lane % gw;
+      const bool ok = l < M.r;
       A acc[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[k] = 0;
-      // four row leaves per step with their loads in flight together; the
-      // sum runs over the row leaves in order
-      int q = 0;
-      for (; q + 4 <= nk; q += 4) {
-        A v[4][NR];
+      if (ok) {
+        // four row leaves per step with their loads in flight together
+        int q = grp;
+        for (; q + 3 * ng < nk; q += 4 * ng) {
+          A v[4][NR];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) load_row<A, NR>(w + (ucol[M.ub + q + u] + l) * NR, v[u]);
+          for (int u = 0; u < 4; ++u)
+            load_row<A, NR>(w + (ucol[M.ub + q + u * ng] + l) * NR, v[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int k = 0; k < NR; ++k) acc[k] += v[u][k];
+            for (int k = 0; k < NR; ++k) acc[k] += v[u][k];
+        }
+        for (; q < nk; q += ng) {
+          const int64_t col = ucol[M.ub + q] + l;
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
+        }
       }
-      for (; q < nk; ++q) {
-        const int64_t col = ucol[M.ub + q] + l;
+      for (int sh = gw; sh < 64; sh <<= 1) {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
+        for (int k = 0; k < NR; ++k) {
+          const A o = __shfl_down(acc[k], sh, 64);
+          acc[k] += o;
+        }
       }
-      const A sc = su ? (A)su[M.toff + l] : (A)1;
+      if (grp == 0 && ok) {
+        const A sc = su ? (A)su[M.toff + l] : (A)1;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) z[(n + M.toff + l) * NR + k] = acc[k] * sc;
+        for (int k = 0; k < NR; ++k) z[(n + M.toff + l) * NR + k] = acc[k] * sc;
+      }
     }
   }
 }
