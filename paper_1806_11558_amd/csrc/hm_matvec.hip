@@ -376,49 +376,15 @@ __global__ __launch_bounds__(256) void k_fwd1m(const LrMeta* __restrict__ meta, 
 // Per row leaf: y_c = sum over its panels of P z[colmap], then scattered to
 // application order.  Panel 0 of a leaf holds dense slices (type TD), the
 // others U slices (type TL); both share the lane layout.
-template <typename T, typename A, int NR, int G>
-__device__ inline void fwd2_run(const Run& rn, int a, int uw, int ld, int C, int cg, int g, bool act,
-                                int wave, const int32_t* __restrict__ colmap,
-                                const A* __restrict__ z, A (&acc)[G][NR]) {
-  constexpr int UNR = 4;
-  static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
-  const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
-  const int32_t* map = colmap + rn.col0 + a;
-  const int ngrp = (uw + C - 1) / C;
-  // Loads are unconditional: a lane without a column of its own reads the
-  // panel's last column and contributes zero, so the compiler keeps all
-  // UNR loads in flight instead of waiting inside divergent branches.
-  for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
-    typename Gran<T>::E s[UNR][G];
-    int32_t zi[UNR];
-    bool ok[UNR];
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int q = q0 + 4 * u;
-      const int j = q * C + cg;
-      ok[u] = act && q < ngrp && j < uw;
-      const int jj = ok[u] ? j : uw - 1;
-      Gran<T>::load(S + (int64_t)jj * ld, s[u]);
-      zi[u] = map[jj];
-    }
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      A zz[NR];
-      load_row<A, NR>(z + (int64_t)zi[u] * NR, zz);
-#pragma unroll
-      for (int e = 0; e < G; ++e) {
-        const A sv = ok[u] ? (A)s[u][e] : (A)0;
-#pragma unroll
-        for (int k = 0; k < NR; ++k) acc[e][k] += sv * zz[k];
-      }
-    }
-  }
-}
-
+//
 // The workgroup first gathers the z values of a tile of panel columns into
 // LDS (one load per column instead of one per lane, and no map -> z
-// dependency inside the streaming loop), then streams the tile's columns.
-// Same column order per lane as fwd2_run.  A tile holds kZTileBytes of z.
+// dependency inside the streaming loop), then streams the tile's columns:
+// wavefront w takes column groups w, w + 4, ..., UNR of them at a time.
+// Loads are unconditional: a lane without a column of its own reads the
+// panel's last column and contributes zero, so the compiler keeps all UNR
+// loads in flight instead of waiting inside divergent branches.  A tile
+// holds kZTileBytes of z.
 constexpr int kZTileBytes = 8192;
 template <typename A, int NR>
 constexpr int z_tile() { return kZTileBytes / (int)(NR * sizeof(A)); }
@@ -477,9 +443,8 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, MvLe
                                               const A* __restrict__ z, A* __restrict__ ypart,
                                               int ldmax) {
   constexpr int G = Gran<TD>::G;
-  constexpr bool kLds = true;
   __shared__ A ybuf[4][kMaxLeaf][NR];
-  __shared__ A zt[kLds ? z_tile<A, NR>() * NR : 1];
+  __shared__ A zt[z_tile<A, NR>() * NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t per = (nunits + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
@@ -498,17 +463,10 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, MvLe
 #pragma unroll
       for (int k = 0; k < NR; ++k) acc[e][k] = 0;
     const Run rn = runs[(int64_t)U.run * L.nleaf + c];
-    if constexpr (kLds) {
-      if (std::is_same<TD, TL>::value || U.run == 0)
-        fwd2_run_lds<TD, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, zt, acc);
-      else
-        fwd2_run_lds<TL, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, zt, acc);
-    } else {
-      if (std::is_same<TD, TL>::value || U.run == 0)
-        fwd2_run<TD, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, acc);
-      else
-        fwd2_run<TL, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, acc);
-    }
+    if (std::is_same<TD, TL>::value || U.run == 0)
+      fwd2_run_lds<TD, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, zt, acc);
+    else
+      fwd2_run_lds<TL, A, NR, G>(rn, U.a, U.w, ld, C, cg, g, act, wave, colmap, z, zt, acc);
     // combine the column groups (tree over cg, stride R), then the waves
 #pragma unroll
     for (int e = 0; e < G; ++e)
