@@ -298,43 +298,46 @@ __device__ inline bool admissible(const double* bt, const double* bs, double eta
   return fmin(dt2, ds2) <= eta2 * dist2;
 }
 
-// Algorithm 1 for one level of candidate blocks: cls = 0 dense leaf,
-// 1 admissible leaf, 2 subdivide (not admissible, both clusters > leaf).
+// Algorithm 1 for one level of candidate blocks: admissible leaf, dense
+// leaf, or subdivide (not admissible, both clusters > leaf).  The class of
+// every candidate pair is packed for one scan: 1 = admissible (low 32
+// bits), 1 << 32 = dense leaf (high 32 bits), 0 = subdivide.  The exclusive
+// prefix then holds the admissible and dense offsets in its two halves, and
+// the split offset is k minus both.
 __global__ void k_classify(const int2* __restrict__ cand, int64_t ncand,
                            const Cluster* __restrict__ cl, const double* __restrict__ box,
-                           double eta2, int leaf, int64_t* __restrict__ fa,
-                           int64_t* __restrict__ fd, int64_t* __restrict__ fs) {
+                           double eta2, int leaf, int64_t* __restrict__ f) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncand;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = cand[k];
     const Cluster t = cl[ts.x], s = cl[ts.y];
     const bool adm = admissible(box + 6 * (int64_t)ts.x, box + 6 * (int64_t)ts.y, eta2);
     const bool split = !adm && (t.y - t.x > leaf) && (s.y - s.x > leaf);
-    fa[k] = adm ? 1 : 0;
-    fs[k] = split ? 1 : 0;
-    fd[k] = (!adm && !split) ? 1 : 0;
+    f[k] = adm ? 1 : (split ? 0 : (int64_t(1) << 32));
   }
 }
 
 // Children in the order (t1,s1), (t1,s2), (t2,s1), (t2,s2).
 __global__ void k_emit(const int2* __restrict__ cand, int64_t ncand, const Cluster* __restrict__ cl,
-                       const int64_t* __restrict__ fa, const int64_t* __restrict__ fd,
-                       const int64_t* __restrict__ fs, const int64_t* __restrict__ oa,
-                       const int64_t* __restrict__ od, const int64_t* __restrict__ os,
+                       const int64_t* __restrict__ f, const int64_t* __restrict__ off,
                        int2* __restrict__ adm_out, int2* __restrict__ dns_out,
                        int2* __restrict__ next) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncand;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = cand[k];
-    if (fa[k]) adm_out[oa[k]] = ts;
-    if (fd[k]) dns_out[od[k]] = ts;
-    if (fs[k]) {
+    const int64_t c = f[k], o = off[k];
+    const int64_t oa = o & 0xffffffffLL, od = o >> 32;
+    if (c == 1) {
+      adm_out[oa] = ts;
+    } else if (c != 0) {
+      dns_out[od] = ts;
+    } else {
       const int t1 = cl[ts.x].z, s1 = cl[ts.y].z;
-      int2* o = next + 4 * os[k];
-      o[0] = make_int2(t1, s1);
-      o[1] = make_int2(t1, s1 + 1);
-      o[2] = make_int2(t1 + 1, s1);
-      o[3] = make_int2(t1 + 1, s1 + 1);
+      int2* q = next + 4 * (k - oa - od);
+      q[0] = make_int2(t1, s1);
+      q[1] = make_int2(t1, s1 + 1);
+      q[2] = make_int2(t1 + 1, s1);
+      q[3] = make_int2(t1 + 1, s1 + 1);
     }
   }
 }
@@ -456,24 +459,25 @@ void build_block_tree(const Cluster* cl, int64_t nroots, const double* box, doub
   HM_HIP(hipStreamSynchronize(s));
   int64_t ncand = nroots;
   const double eta2 = eta * eta;
-  int64_t* tot = dalloc_t<int64_t>(3, s);
+  int64_t* tot = dalloc_t<int64_t>(1, s);
   int64_t lv = 0;
   while (ncand > 0) {
-    int64_t* f = dalloc_t<int64_t>(6 * ncand, s);
-    int64_t *fa = f, *fd = f + ncand, *fs = f + 2 * ncand;
-    int64_t *oa = f + 3 * ncand, *od = f + 4 * ncand, *os = f + 5 * ncand;
-    k_classify<<<grid_for(ncand, kT), kT, 0, s>>>(cand, ncand, cl, box, eta2, leaf, fa, fd, fs);
+    // the packed scan keeps each count in 32 bits
+    if (ncand >= (int64_t(1) << 32)) throw Error{HM_ERR_STATE, "block tree level too large"};
+    int64_t* f = dalloc_t<int64_t>(2 * ncand, s);
+    int64_t* off = f + ncand;
+    k_classify<<<grid_for(ncand, kT), kT, 0, s>>>(cand, ncand, cl, box, eta2, leaf, f);
     HM_LAUNCH_CHECK();
-    scan_excl_i64(fa, oa, ncand, tot, s);
-    scan_excl_i64(fd, od, ncand, tot + 1, s);
-    scan_excl_i64(fs, os, ncand, tot + 2, s);
+    scan_excl_i64(f, off, ncand, tot, s);
+    const int64_t packed = d2h_i64(tot, s);
     int64_t h[3];
-    HM_HIP(hipMemcpyAsync(h, tot, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
+    h[0] = packed & 0xffffffffLL;                       // admissible
+    h[1] = packed >> 32;                                // dense leaves
+    h[2] = ncand - h[0] - h[1];                         // split
     int2* a = dalloc_t<int2>(h[0], s);
     int2* d = dalloc_t<int2>(h[1], s);
     int2* nx = dalloc_t<int2>(4 * h[2], s);
-    k_emit<<<grid_for(ncand, kT), kT, 0, s>>>(cand, ncand, cl, fa, fd, fs, oa, od, os, a, d, nx);
+    k_emit<<<grid_for(ncand, kT), kT, 0, s>>>(cand, ncand, cl, f, off, a, d, nx);
     HM_LAUNCH_CHECK();
     adm_lv.push_back({a, h[0]});
     dns_lv.push_back({d, h[1]});
