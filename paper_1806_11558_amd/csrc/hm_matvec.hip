@@ -740,39 +740,47 @@ __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int 
                                bool act, int wave, const A (&xg)[G][NR], A* __restrict__ w) {
   static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
   constexpr int UNR = NR <= 2 ? 4 : 1;   // column groups per wavefront in flight
+  const int lane = threadIdx.x & 63;
   const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
   const int64_t col0 = rn.col0 + a;
   const int ngrp = (uw + C - 1) / C;
-  for (int q0 = wave; q0 < ngrp; q0 += 4 * UNR) {
-    // the granules of UNR column groups are loaded before any is reduced
+  // lane L = u C + c stores column group q0 + u, segment c: the UNR C
+  // columns of a step are contiguous and leave in one store
+  const int ul = lane / C, cl = lane - ul * C;
+  for (int q0 = wave * UNR; q0 < ngrp; q0 += 4 * UNR) {
+    // UNR consecutive column groups, all granules loaded before any is reduced
     typename Gran<T>::E sv[UNR][G];
+    bool ok[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int j = (q0 + 4 * u) * C + cg;
-      const bool ok = act && q0 + 4 * u < ngrp && j < uw;
-      Gran<T>::load(S + (int64_t)(ok ? j : uw - 1) * ld, sv[u]);
+      const int j = (q0 + u) * C + cg;
+      ok[u] = act && q0 + u < ngrp && j < uw;
+      Gran<T>::load(S + (int64_t)(ok[u] ? j : uw - 1) * ld, sv[u]);
     }
+    A v[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = 0;
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      const int q = q0 + 4 * u;
-      if (q >= ngrp) break;                            // uniform over the wavefront
-      const int j = q * C + cg;
-      const bool ok = act && j < uw;
       A p[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) p[k] = 0;
 #pragma unroll
       for (int e = 0; e < G; ++e) {
-        const A a = ok ? (A)sv[u][e] : (A)0;
+        const A x = ok[u] ? (A)sv[u][e] : (A)0;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] += a * xg[e][k];
+        for (int k = 0; k < NR; ++k) p[k] += x * xg[e][k];
       }
 #pragma unroll
-      for (int k = 0; k < NR; ++k) p[k] = seg_sum(p[k], g, R);
-      if (act && g == 0 && j < uw) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) w[(col0 + j) * NR + k] = p[k];
+      for (int k = 0; k < NR; ++k) {
+        const A t = __shfl(seg_sum(p[k], g, R), cl * R, 64);
+        if (ul == u) v[k] = t;
       }
+    }
+    const int jj = (q0 + ul) * C + cl;
+    if (ul < UNR && jj < uw) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) w[(col0 + jj) * NR + k] = v[k];
     }
   }
 }
