@@ -744,9 +744,11 @@ __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int 
   const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
   const int64_t col0 = rn.col0 + a;
   const int ngrp = (uw + C - 1) / C;
-  // lane L = u C + c stores column group q0 + u, segment c: the UNR C
-  // columns of a step are contiguous and leave in one store
-  const int ul = lane / C, cl = lane - ul * C;
+  // lane L = u C + c stores column group q0 + u0 + u, segment c: the UG C
+  // columns of a store round are contiguous and leave in one instruction
+  // (UG = 64 / C groups per round, so a round covers at most 64 lanes)
+  const int UG = 64 / C;
+  const int ul0 = lane / C, cl = lane - ul0 * C;
   for (int q0 = wave * UNR; q0 < ngrp; q0 += 4 * UNR) {
     // UNR consecutive column groups, all granules loaded before any is reduced
     typename Gran<T>::E sv[UNR][G];
@@ -757,9 +759,7 @@ __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int 
       ok[u] = act && q0 + u < ngrp && j < uw;
       Gran<T>::load(S + (int64_t)(ok[u] ? j : uw - 1) * ld, sv[u]);
     }
-    A v[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) v[k] = 0;
+    A ps[UNR][NR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       A p[NR];
@@ -772,15 +772,28 @@ __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int 
         for (int k = 0; k < NR; ++k) p[k] += x * xg[e][k];
       }
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        const A t = __shfl(seg_sum(p[k], g, R), cl * R, 64);
-        if (ul == u) v[k] = t;
-      }
+      for (int k = 0; k < NR; ++k) ps[u][k] = seg_sum(p[k], g, R);
     }
-    const int jj = (q0 + ul) * C + cl;
-    if (ul < UNR && jj < uw) {
+    for (int u0 = 0; u0 < UNR; u0 += UG) {              // uniform over the wavefront
+      const int ul = u0 + ul0;
+      A v[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) w[(col0 + jj) * NR + k] = v[k];
+      for (int k = 0; k < NR; ++k) v[k] = 0;
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (u >= u0 && u < u0 + UG) {                   // uniform over the wavefront
+#pragma unroll
+          for (int k = 0; k < NR; ++k) {
+            const A t = __shfl(ps[u][k], cl * R, 64);
+            if (ul == u) v[k] = t;
+          }
+        }
+      }
+      const int jj = (q0 + ul) * C + cl;
+      if (ul0 < UG && ul < UNR && jj < uw) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) w[(col0 + jj) * NR + k] = v[k];
+      }
     }
   }
 }
