@@ -205,6 +205,7 @@ struct hm_handle {
   Storage sto;
 
   void *z = nullptr, *w = nullptr, *ypart = nullptr;
+  int64_t ypart_bytes = 0;
   std::unique_ptr<SolveWs> sws;         // graph-replay solve workspace
   std::vector<std::array<double, 2>> tune;   // autotuner: (unit columns, ms)
   int max_nr_t = 1;
@@ -254,6 +255,7 @@ struct hm_handle {
     P.nunits = sto.nunits;
     P.ubeg = sto.ubeg;
     P.ypart = ypart;
+    P.ypart_bytes = ypart_bytes;
     P.ldmax = sto.ldmax;
     P.colmap = sto.colmap;
     P.meta = sto.meta;
@@ -500,7 +502,8 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     int64_t nu = h->sto.nunits;
     if (p.flags & HM_AUTOTUNE)
       nu = std::max(nu, count_units(h->sto, h->nleaf, kTuneCols[0], s));
-    h->ypart = h->alloc((size_t)(nu + 1) * h->sto.ldmax * kMaxNr * sizeof(double));
+    h->ypart_bytes = (nu + 1) * (int64_t)h->sto.ldmax * kMaxNr * (int64_t)sizeof(double);
+    h->ypart = h->alloc((size_t)h->ypart_bytes);
   }
   {
     const int64_t cols = h->sto.ncols + 1;

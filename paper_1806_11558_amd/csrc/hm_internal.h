@@ -122,6 +122,7 @@ struct MvPlan {
   int64_t nunits;
   const int32_t* ubeg;      // leaf -> first unit (nleaf + 1)
   void* ypart;              // workspace: per-unit partial rows, ldmax x 16 each
+  int64_t ypart_bytes;      // its size (the transposed product reuses it)
   int ldmax;
   const int32_t* colmap;
   const LrMeta* meta;

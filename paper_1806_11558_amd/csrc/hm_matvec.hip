@@ -1094,9 +1094,8 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
     }
     if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
     // workgroups per column leaf: up to 8, as many as the unit workspace
-    // (at least (units + 1) ldmax rows of 16 doubles) holds partial rows for
-    const int64_t cap = (P.nunits + 1) * (int64_t)16 * (int64_t)sizeof(double) /
-                        ((int64_t)NR * (int64_t)sizeof(A));
+    // holds partial rows (ldmax x NR) for
+    const int64_t cap = P.ypart_bytes / ((int64_t)P.ldmax * NR * (int64_t)sizeof(A));
     const int S = (int)std::max<int64_t>(1, std::min<int64_t>(8, cap / std::max<int64_t>(1, P.L.nleaf)));
     // leaves carry similar work: the grid covers the XCD-ordered index range
     const unsigned gt = (unsigned)std::min<int64_t>(ceil_div(P.L.nleaf * S, kXcds) * kXcds, P.grid);
