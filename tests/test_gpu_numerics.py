@@ -211,6 +211,31 @@ def test_products_every_row_tile_count(nsub, leaf, ld, prec, eps, bound):
     H.free()
 
 
+@pytest.mark.parametrize("prec,eps,bound", [("f64", 1e-8, 1e-7), ("f32", 1e-6, 1e-5)])
+def test_products_31_columns(prec, eps, bound):
+    """31 right-hand sides in one call run as passes of 16, 8, 4, 2 and 1
+    columns (every pass width of the forward and transposed kernels, in
+    FP64 with the MFMA passes); every column against the dense oracle at
+    N = 1,280."""
+    import paper_1806_11558_amd as hm
+    from oracle import bem
+    from synthetic import icosphere, normal_columns
+    V, T = icosphere(3)
+    say("31 columns", prec)
+    op = bem.Operator(V, T)
+    A = op.dense()
+    H = hm.HMatrix(V, T, leaf_size=32, eps=eps, precision=prec)
+    x = normal_columns(op.n, 31, seed=31)
+    xt = torch.tensor(x, device=DEV)
+    y = H.matvec(xt).cpu().numpy()
+    yT = H.matvec_T(xt).cpu().numpy()
+    ref, refT = A @ x, A.T @ x
+    for k in range(31):
+        assert rel2(y[:, k], ref[:, k]) <= bound, k
+        assert rel2(yT[:, k], refT[:, k]) <= bound, k
+    H.free()
+
+
 def test_products_ranks_above_64():
     """Leaf 8, eta 5, ACA eps 1e-14, max_rank 128 at N = 1,280: the largest
     admissible blocks (80 x 80) reach ranks above 64, so phase 1 and the
