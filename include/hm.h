@@ -145,64 +145,101 @@ hm_status hm_build_batch(const double* vertices, const int64_t* vtx_offsets,
                          const hm_params* p, void* stream, hm_handle** out);
 
 /*
- * hm_matvec -- y = H x, the approximate product of Sec. 2.3: dense leaves
- * apply their stored block, admissible leaves apply U (V^T x).
- *   x, y   device, [n, nrhs] row-major, dtype `dtype` (HM_F64 or HM_F32);
- *          y is overwritten; x and y must not overlap
+ * hm_matvec -- y = H x, the approximate product of Sec. 2.3 (last
+ * paragraph): dense leaves apply their stored block, admissible leaves apply
+ * U (V^T x), so a product costs O(k N log N).  It is the one operation the
+ * paper's solver needs per iteration (Sec. 3.4, Sec. 4.1).
+ *   x, y   device, [n, nrhs] row-major, dtype `dtype` (HM_F64 or HM_F32),
+ *          owned by the caller; y is overwritten; x and y must not overlap
+ *   n      rows of x and y; must equal the handle's number of unknowns
+ *          (else HM_ERR_ARG before any device access)
  *   nrhs   number of right-hand sides, >= 1
  * Accumulation is in double when either the storage or the vectors are
- * double, else in float.  Stream-ordered; no host synchronisation.
- * Deterministic: repeated calls give bitwise identical results.
+ * double, else in float.  Stream-ordered; no host synchronisation; allocates
+ * nothing (the product workspace belongs to the handle).  Deterministic:
+ * repeated calls give bitwise identical results.
+ * Errors: HM_ERR_ARG (NULL handle or vector, n mismatch, nrhs < 1, bad dtype,
+ * overlap), HM_ERR_HIP (launch failure).
  */
-hm_status hm_matvec(hm_handle* h, const void* x, void* y, int32_t nrhs,
+hm_status hm_matvec(hm_handle* h, const void* x, void* y, int64_t n, int32_t nrhs,
                     int32_t dtype, void* stream);
 
 /*
- * hm_matvec_T -- y = H^T x with the same storage (dense leaves transposed,
- * admissible leaves apply V (U^T x)).  Arguments as hm_matvec.
+ * hm_matvec_T -- y = H^T x with the same storage: the transpose of the
+ * product of Sec. 2.3 block by block, (U V^T)^T = V U^T for admissible
+ * leaves (U and V swap roles) and D^T for dense leaves.  The collocation
+ * matrix is not symmetric, so this is a separate operation; the adjoint
+ * solve uses it.  Arguments, ownership and errors as hm_matvec.
  */
-hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int32_t nrhs,
+hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int64_t n, int32_t nrhs,
                       int32_t dtype, void* stream);
 
 typedef struct {
   double tol;          /* relative residual |f - H s| / |f| to reach, > 0   */
   int32_t restart;     /* GMRES restart length m, 1..1000; 0 => 100         */
-  int32_t max_iter;    /* total Arnoldi steps allowed, >= 1                 */
+  int32_t max_iter;    /* total Arnoldi steps allowed (inner steps included
+                          with refine), >= 1                                */
   int32_t transpose;   /* 1: solve H^T s = f (adjoint), 0: H s = f          */
   int32_t use_x0;      /* 1: sigma holds the initial guess on entry         */
   int32_t flags;       /* HM_SOLVE_GRAPH or 0                               */
-  int32_t pad;
+  int32_t refine;      /* 0: GMRES with double products throughout;
+                          1: iterative refinement -- residual f - H s in
+                          double (vectors and accumulation), correction by
+                          GMRES whose products take float vectors (float
+                          accumulation for the HM_F32 / HM_F32_F16 forms) to
+                          the relative residual inner_tol, added in double  */
+  double inner_tol;    /* refine = 1: inner relative tolerance in (0, 1);
+                          0 => 1e-4.  Ignored when refine = 0               */
 } hm_solve_params;
 
 /* hm_solve_params.flags: replay one captured HIP graph per Arnoldi step
    (product, two Gram-Schmidt passes, norm) instead of launching its kernels
    one by one.  The graph and the solve workspace ((restart + 1) basis
    vectors) stay with the handle until the next solve with another nrhs,
-   restart or direction, or hm_free.  Results are bitwise those of flags = 0. */
+   restart, direction or refine mode, or hm_free.  Results are bitwise those
+   of flags = 0. */
 #define HM_SOLVE_GRAPH 1
 
 typedef struct {
-  int32_t iters;          /* Arnoldi steps taken (max over right-hand sides) */
+  int32_t iters;          /* Arnoldi steps taken (max over right-hand sides;
+                             summed over the inner solves with refine)      */
   int32_t restarts;       /* completed restart cycles                       */
   int32_t converged;      /* number of right-hand sides that converged      */
-  int32_t pad;
-  double rel_residual;    /* max over rhs of the explicit |f - H s| / |f|   */
+  int32_t ir_steps;       /* refinement corrections applied (0 without)     */
+  double rel_residual;    /* max over rhs of the explicit |f - H s| / |f|,
+                             with double products                            */
 } hm_solve_info;
 
 /*
- * hm_solve -- restarted GMRES on H s = f (or H^T s = f): x0 = 0 unless
- * use_x0, Arnoldi basis in double with classical Gram-Schmidt applied twice,
- * Givens rotations on the host, one matvec per step; the residual is
- * recomputed explicitly at every restart and at the end.  Each right-hand
- * side is an independent system; all are advanced together.
- *   f, sigma  device, [n, nrhs] row-major, dtype `dtype`
+ * hm_solve -- solve H s = f (or H^T s = f) for the density s.  The paper
+ * solves its symmetric Galerkin system by CG with one H-matrix product per
+ * step, stopped at a relative residual of 1e-8 (Sec. 4.1); the collocation
+ * matrix is not symmetric, so this is restarted GMRES with the same product:
+ * x0 = 0 unless use_x0, Arnoldi basis in double with classical Gram-Schmidt
+ * applied twice, Givens rotations on the host; the residual is recomputed
+ * explicitly at every restart and at the end.  With refine = 1 the solve is
+ * an iterative refinement around GMRES with float products (see
+ * hm_solve_params); it stops when the double residual reaches tol, when
+ * max_iter steps are spent, or when a correction no longer reduces the
+ * residual of any unconverged column by 10%.  Each right-hand side is an
+ * independent system; all are advanced together.
+ *   f, sigma  device, [n, nrhs] row-major, dtype `dtype`, owned by the
+ *             caller; must not overlap
+ *   n         rows of f and sigma; must equal the handle's unknowns
+ *   nrhs      1..256
  *   info      host, optional (may be NULL)
+ * The solve allocates its workspace ((restart + 1) n nrhs doubles plus a
+ * few vectors) from the library's pool for the call (kept with the handle
+ * with HM_SOLVE_GRAPH).
  * Returns HM_OK when every column reached tol, HM_NOT_CONVERGED otherwise
- * (sigma then holds the last iterate).  Synchronises `stream`.
+ * (sigma then holds the last iterate; info says how far it got).
+ * Errors: HM_ERR_ARG (NULL, n mismatch, bad nrhs / dtype / tol / restart /
+ * max_iter / refine / inner_tol / flags, overlap), HM_ERR_OOM, HM_ERR_HIP.
+ * Synchronises `stream`.
  */
-hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs,
-                   int32_t dtype, const hm_solve_params* sp,
-                   hm_solve_info* info, void* stream);
+hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int64_t n, int32_t nrhs,
+                   int32_t dtype, const hm_solve_params* sp, hm_solve_info* info,
+                   void* stream);
 
 /* Release every resource of h (NULL-safe); waits for work in flight.  The
    handle's device memory goes back to the library's memory pool on that

@@ -48,12 +48,12 @@ class Params(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("transpose", C.c_int32), ("use_x0", C.c_int32), ("flags", C.c_int32),
-                ("pad", C.c_int32)]
+                ("refine", C.c_int32), ("inner_tol", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("converged", C.c_int32),
-                ("pad", C.c_int32), ("rel_residual", C.c_double)]
+                ("ir_steps", C.c_int32), ("rel_residual", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -95,9 +95,10 @@ def lib():
     L.hm_params_default.argtypes = [C.POINTER(Params)]
     L.hm_build.argtypes = [vp, i64, vp, i64, C.POINTER(Params), vp, C.POINTER(vp)]
     L.hm_build_batch.argtypes = [vp, vp, vp, vp, i32, C.POINTER(Params), vp, C.POINTER(vp)]
-    L.hm_matvec.argtypes = [vp, vp, vp, i32, i32, vp]
-    L.hm_matvec_T.argtypes = [vp, vp, vp, i32, i32, vp]
-    L.hm_solve.argtypes = [vp, vp, vp, i32, i32, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]
+    L.hm_matvec.argtypes = [vp, vp, vp, i64, i32, i32, vp]
+    L.hm_matvec_T.argtypes = [vp, vp, vp, i64, i32, i32, vp]
+    L.hm_solve.argtypes = [vp, vp, vp, i64, i32, i32, C.POINTER(SolveParams),
+                           C.POINTER(SolveInfo), vp]
     L.hm_free.argtypes = [vp]
     L.hm_free.restype = None
     L.hm_query.argtypes = [vp, i32, vp, i64, C.POINTER(i64)]
@@ -174,7 +175,8 @@ def hm_build_batch(meshes, params: Params, stream=None) -> int:
     return h.value
 
 
-def _vec_args(x, n: int):
+def _vec_args(x):
+    """(rows, nrhs, dtype code) of a device vector [n] or [n, nrhs]."""
     import torch
     if not isinstance(x, torch.Tensor) or not x.is_cuda:
         raise HMError(HM_ERR_ARG, "vectors must be CUDA tensors")
@@ -182,20 +184,26 @@ def _vec_args(x, n: int):
         raise HMError(HM_ERR_ARG, "vectors must be float32 or float64")
     if not x.is_contiguous():
         raise HMError(HM_ERR_ARG, "vectors must be contiguous")
-    if x.shape[0] != n or x.dim() not in (1, 2):
-        raise HMError(HM_ERR_ARG, f"vector shape {tuple(x.shape)} does not match n={n}")
+    if x.dim() not in (1, 2):
+        raise HMError(HM_ERR_ARG, f"vector shape {tuple(x.shape)}: expected [n] or [n, nrhs]")
     nrhs = 1 if x.dim() == 1 else x.shape[1]
-    return nrhs, (HM_F32 if x.dtype == torch.float32 else HM_F64)
+    return x.shape[0], nrhs, (HM_F32 if x.dtype == torch.float32 else HM_F64)
+
+
+def _pair_args(a, b, what):
+    na, nrhs, dt = _vec_args(a)
+    if a.shape != b.shape or a.dtype != b.dtype:
+        raise HMError(HM_ERR_ARG, f"{what} must have the same shape and dtype")
+    _vec_args(b)
+    return na, nrhs, dt
 
 
 def hm_matvec(h: int, x, y, stream=None, transpose: bool = False) -> None:
-    n = x.shape[0]
-    nrhs, dt = _vec_args(x, n)
-    nrhs2, dt2 = _vec_args(y, n)
-    if (nrhs, dt) != (nrhs2, dt2) or x.shape != y.shape:
-        raise HMError(HM_ERR_ARG, "x and y must have the same shape and dtype")
+    """y = H x (or H^T x).  The library checks the row count against the
+    handle's number of unknowns."""
+    n, nrhs, dt = _pair_args(x, y, "x and y")
     f = lib().hm_matvec_T if transpose else lib().hm_matvec
-    _check(f(h, x.data_ptr(), y.data_ptr(), nrhs, dt, _stream_ptr(stream)))
+    _check(f(h, x.data_ptr(), y.data_ptr(), n, nrhs, dt, _stream_ptr(stream)))
 
 
 def hm_matvec_T(h: int, x, y, stream=None) -> None:
@@ -203,14 +211,10 @@ def hm_matvec_T(h: int, x, y, stream=None) -> None:
 
 
 def hm_solve(h: int, f, sigma, sp: SolveParams, stream=None) -> tuple[int, SolveInfo]:
-    n = f.shape[0]
-    nrhs, dt = _vec_args(f, n)
-    if sigma.shape != f.shape or sigma.dtype != f.dtype:
-        raise HMError(HM_ERR_ARG, "f and sigma must have the same shape and dtype")
-    _vec_args(sigma, n)
+    n, nrhs, dt = _pair_args(f, sigma, "f and sigma")
     info = SolveInfo()
-    st = lib().hm_solve(h, f.data_ptr(), sigma.data_ptr(), nrhs, dt, C.byref(sp), C.byref(info),
-                        _stream_ptr(stream))
+    st = lib().hm_solve(h, f.data_ptr(), sigma.data_ptr(), n, nrhs, dt, C.byref(sp),
+                        C.byref(info), _stream_ptr(stream))
     _check(st, ok=(HM_OK, HM_NOT_CONVERGED))
     return st, info
 
@@ -287,9 +291,15 @@ class HMatrix:
         return p
 
     # products -------------------------------------------------------------
+    def _rows(self, v):
+        if getattr(v, "shape", (None,))[0] != self.n:
+            raise HMError(HM_ERR_ARG, f"vector has {v.shape[0]} rows, the H-matrix {self.n}")
+
     def matvec(self, x, out=None, stream=None, transpose: bool = False):
         import torch
+        self._rows(x)
         y = torch.empty_like(x) if out is None else out
+        self._rows(y)
         hm_matvec(self._h, x, y, stream, transpose)
         return y
 
@@ -297,11 +307,18 @@ class HMatrix:
         return self.matvec(x, out, stream, transpose=True)
 
     def solve(self, f, *, tol: float = 1e-8, restart: int = 100, max_iter: int = 1000,
-              transpose: bool = False, x0=None, graph: bool = False, stream=None):
+              transpose: bool = False, x0=None, graph: bool = False, refine: bool = False,
+              inner_tol: float = 0.0, stream=None):
+        """GMRES on H s = f (hm_solve); with refine=True iterative refinement
+        around an inner GMRES with float products to inner_tol.  Returns
+        (sigma, info, status); status HM_NOT_CONVERGED is returned, not
+        raised."""
         import torch
+        self._rows(f)
         sp = SolveParams(tol=tol, restart=restart, max_iter=max_iter,
                          transpose=1 if transpose else 0, use_x0=0 if x0 is None else 1,
-                         flags=HM_SOLVE_GRAPH if graph else 0)
+                         flags=HM_SOLVE_GRAPH if graph else 0, refine=1 if refine else 0,
+                         inner_tol=inner_tol)
         sigma = torch.empty_like(f) if x0 is None else x0.clone()
         st, info = hm_solve(self._h, f, sigma, sp, stream)
         return sigma, info, st
@@ -368,13 +385,10 @@ class HMatrix:
         buf = np.zeros(max(r * (m + n), 1), dtype=self.storage_dtype)
         buf.view(np.int64)[0] = b if buf.itemsize == 8 else 0
         if buf.itemsize != 8:
-            tmp = np.zeros(max(r * (m + n) // 2 + 1, 1), dtype=np.int64)
-            tmp[0] = b
-            need = C.c_int64(0)
+            # the block index travels in the first 8 bytes of the buffer
             raw = np.zeros(max(r * (m + n), 2), dtype=np.float32)
             raw.view(np.int64)[0] = b
-            _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, raw.ctypes.data, raw.nbytes,
-                                  C.byref(need)))
+            _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, raw.ctypes.data, raw.nbytes, None))
             buf = raw[: r * (m + n)]
         else:
             _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, buf.ctypes.data, buf.nbytes, None))

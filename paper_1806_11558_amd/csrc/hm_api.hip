@@ -61,45 +61,66 @@ void gmres_copy_col(const double* Q, int64_t ldq, const int* jd, double* out, hi
 // together with the instantiated graph of one Arnoldi step (product of the
 // current basis vector, two Gram-Schmidt passes, norm), which is replayed
 // for every step; the step index is read from device memory (jd).
+//
+// Buffers: Q the basis (m + 1 vectors), fd the right-hand side of the GMRES
+// run, x its iterate, w the product / residual, xin the captured step's
+// input; with refinement also fo (the caller's right-hand side), xs (the
+// refined solution) and the float vectors xf, wf of the inner products.
 struct SolveWs {
   int nr = 0, m = 0;
-  bool tr = false;
+  bool tr = false, f32 = false;
   int64_t n = 0;
   double *Q = nullptr, *fd = nullptr, *x = nullptr, *w = nullptr, *hdev = nullptr,
-         *part = nullptr, *scl = nullptr, *ydev = nullptr, *xin = nullptr;
+         *part = nullptr, *scl = nullptr, *ydev = nullptr, *xin = nullptr, *fo = nullptr,
+         *xs = nullptr;
+  float *xf = nullptr, *wf = nullptr;
   int* jd = nullptr;
   std::vector<void*> mem;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t free_stream = nullptr;
-  void alloc(int64_t n_, int nr_, int m_, bool tr_, hipStream_t s) {
-    n = n_, nr = nr_, m = m_, tr = tr_;
+  // Lays the buffers out through get(count of doubles) -> double*.
+  template <typename Get>
+  void layout(int64_t n_, int nr_, int m_, bool tr_, bool f32_, Get&& get) {
+    n = n_, nr = nr_, m = m_, tr = tr_, f32 = f32_;
     const int64_t nv = n * nr;
-    auto A = [&](size_t cnt) {
+    Q = get((size_t)(m + 1) * nv);
+    fd = get(nv);
+    x = get(nv);
+    w = get(nv);
+    xin = get(nv);
+    hdev = get((size_t)(m + 2) * nr * 2 + nr);
+    part = get((size_t)(m + 2) * gmres_tiles(n) * nr);
+    scl = get(nr);
+    ydev = get((size_t)(m + 1) * nr);
+    jd = (int*)get(1);
+    if (f32) {
+      fo = get(nv);
+      xs = get(nv);
+      xf = (float*)get((nv + 1) / 2);
+      wf = (float*)get((nv + 1) / 2);
+    }
+  }
+  // From the library's pool (stream-ordered), freed with the workspace.
+  void alloc(int64_t n_, int nr_, int m_, bool tr_, bool f32_, hipStream_t s) {
+    layout(n_, nr_, m_, tr_, f32_, [&](size_t cnt) {
       double* q = (double*)dalloc(cnt * sizeof(double), s);
       mem.push_back(q);
       return q;
-    };
-    Q = A((size_t)(m + 1) * nv);
-    fd = A(nv);
-    x = A(nv);
-    w = A(nv);
-    xin = A(nv);
-    hdev = A((size_t)(m + 2) * nr * 2 + nr);
-    part = A((size_t)(m + 2) * gmres_tiles(n) * nr);
-    scl = A(nr);
-    ydev = A((size_t)(m + 1) * nr);
-    jd = (int*)A(1);
+    });
   }
   ~SolveWs() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (mem.empty()) return;
     for (void* q : mem) (void)hipFreeAsync(q, free_stream);
     (void)hipStreamSynchronize(free_stream);
   }
 };
 void convert_f32_to_f64(const float* a, int64_t tot, double* out, hipStream_t s);
 void convert_f64_to_f32(const double* a, int64_t tot, float* out, hipStream_t s);
+void gmres_add(const double* a, const double* b, int64_t tot, double* out, hipStream_t s);
+void gmres_copy_col_f32(const double* Q, int64_t ldq, const int* jd, float* out, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
@@ -568,6 +589,149 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace
 
+// ------------------------------------------------------------------ GMRES core
+namespace {
+// Restarted GMRES on op(H) x = b for every column of b at once (the columns
+// are independent systems).  `apply` computes w = op(H) v for double vectors
+// v, w of the solve workspace; the Arnoldi basis, the Gram-Schmidt passes and
+// the Givens rotations are in double.  b is ws->fd, the iterate ws->x (read
+// as the initial guess, written back).  Returns the number of Arnoldi steps;
+// rn receives the explicit residual norms |b - op(H) x| at the end.
+// With x_zero the initial guess is known to be zero and the first residual is
+// b itself (one product fewer).
+template <typename Apply, typename Step>
+int gmres_core(SolveWs* ws, int64_t n, int nr, int m, double tol, int max_iter, bool use_graph,
+               const Apply& apply, const Step& graph_step, const std::vector<double>& fn,
+               std::vector<double>& rn, std::vector<int>& conv, int& restarts, bool x_zero,
+               hipStream_t s) {
+  const int64_t nv = n * nr;
+  double *Q = ws->Q, *fd = ws->fd, *x = ws->x, *w = ws->w, *hdev = ws->hdev, *part = ws->part,
+         *scl = ws->scl, *ydev = ws->ydev;
+  double* hnorm = hdev + (size_t)(m + 2) * nr * 2;   // |w| of the current step
+  std::vector<double> hv((size_t)(m + 2) * nr * 2 + nr);
+  auto norms = [&](const double* v, std::vector<double>& out) {
+    gmres_dots(v, 0, 1, v, n, nr, part, hdev, s);
+    out.resize(nr);
+    HM_HIP(hipMemcpyAsync(out.data(), hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    for (auto& z : out) z = std::sqrt(std::max(z, 0.0));
+  };
+  // r = b - op(H) x  (into w)
+  auto residual = [&](std::vector<double>& r) {
+    apply(x, w);
+    gmres_sub(fd, w, nv, w, s);
+    norms(w, r);
+  };
+  auto rel = [&](int c, double r) { return fn[c] > 0 ? r / fn[c] : 0.0; };
+  if (x_zero) {
+    HM_HIP(hipMemcpyAsync(w, fd, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rn = fn;
+  } else {
+    residual(rn);
+  }
+  conv.assign(nr, 0);
+  for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= tol;
+  int total_it = 0;
+  // per-column Arnoldi state
+  std::vector<double> H((size_t)(m + 1) * m * nr), cs((size_t)m * nr), sn((size_t)m * nr),
+      gv((size_t)(m + 1) * nr);
+  std::vector<int> kc(nr);
+  std::vector<double> sc(nr);
+  while (total_it < max_iter) {
+    bool all = true;
+    for (int c = 0; c < nr; ++c) all = all && conv[c];
+    if (all) break;
+    // Q0 = r / |r| for active columns
+    for (int c = 0; c < nr; ++c) sc[c] = (!conv[c] && rn[c] > 0) ? 1.0 / rn[c] : 0.0;
+    HM_HIP(hipMemcpyAsync(scl, sc.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    gmres_scale_cols(w, scl, n, nr, Q, s);
+    std::vector<int> active(nr);
+    for (int c = 0; c < nr; ++c) {
+      active[c] = !conv[c];
+      kc[c] = 0;
+      std::fill(gv.begin() + (size_t)c * (m + 1), gv.begin() + (size_t)(c + 1) * (m + 1), 0.0);
+      gv[(size_t)c * (m + 1)] = rn[c];
+    }
+    for (int j = 0; j < m && total_it < max_iter; ++j) {
+      if (use_graph) {
+        graph_step(j);
+      } else {
+        double* qj = Q + (size_t)j * nv;
+        apply(qj, w);
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+          gmres_dots(Q, nv, j + 1, w, n, nr, part, hdev + (size_t)pass * (m + 2) * nr, s);
+          gmres_orth_update(Q, nv, hdev + (size_t)pass * (m + 2) * nr, j + 1, n, nr, w, s);
+        }
+        gmres_dots(w, 0, 1, w, n, nr, part, hnorm, s);
+      }
+      HM_HIP(hipMemcpyAsync(hv.data(), hdev, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      ++total_it;
+      bool any = false;
+      for (int c = 0; c < nr; ++c) {
+        const double hn = std::sqrt(std::max(hv[(size_t)(m + 2) * nr * 2 + c], 0.0));
+        sc[c] = 0.0;
+        if (!active[c]) continue;
+        double* Hc = H.data() + (size_t)c * (m + 1) * m;
+        for (int k = 0; k <= j; ++k)
+          Hc[(size_t)k * m + j] = hv[(size_t)k * nr + c] + hv[(size_t)(m + 2) * nr + (size_t)k * nr + c];
+        Hc[(size_t)(j + 1) * m + j] = hn;
+        // previous rotations
+        double* csc = cs.data() + (size_t)c * m;
+        double* snc = sn.data() + (size_t)c * m;
+        for (int k = 0; k < j; ++k) {
+          const double a = Hc[(size_t)k * m + j], b = Hc[(size_t)(k + 1) * m + j];
+          Hc[(size_t)k * m + j] = csc[k] * a + snc[k] * b;
+          Hc[(size_t)(k + 1) * m + j] = -snc[k] * a + csc[k] * b;
+        }
+        const double a = Hc[(size_t)j * m + j], b = Hc[(size_t)(j + 1) * m + j];
+        const double rr = std::hypot(a, b);
+        csc[j] = rr > 0 ? a / rr : 1.0;
+        snc[j] = rr > 0 ? b / rr : 0.0;
+        Hc[(size_t)j * m + j] = rr;
+        Hc[(size_t)(j + 1) * m + j] = 0.0;
+        double* gc = gv.data() + (size_t)c * (m + 1);
+        gc[j + 1] = -snc[j] * gc[j];
+        gc[j] = csc[j] * gc[j];
+        kc[c] = j + 1;
+        const double est = rel(c, std::fabs(gc[j + 1]));
+        if (est <= tol || hn == 0.0) {
+          active[c] = 0;
+        } else {
+          sc[c] = 1.0 / hn;
+          any = true;
+        }
+      }
+      if (!any) break;
+      HM_HIP(hipMemcpyAsync(scl, sc.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      gmres_scale_cols(w, scl, n, nr, Q + (size_t)(j + 1) * nv, s);
+    }
+    // x += Q y  (upper triangular solves on the host)
+    int kmaxc = 0;
+    for (int c = 0; c < nr; ++c) kmaxc = std::max(kmaxc, kc[c]);
+    if (kmaxc > 0) {
+      std::vector<double> y((size_t)kmaxc * nr, 0.0);
+      for (int c = 0; c < nr; ++c) {
+        const double* Hc = H.data() + (size_t)c * (m + 1) * m;
+        const double* gc = gv.data() + (size_t)c * (m + 1);
+        for (int k = kc[c] - 1; k >= 0; --k) {
+          double v = gc[k];
+          for (int l = k + 1; l < kc[c]; ++l) v -= Hc[(size_t)k * m + l] * y[(size_t)l * nr + c];
+          y[(size_t)k * nr + c] = Hc[(size_t)k * m + k] != 0.0 ? v / Hc[(size_t)k * m + k] : 0.0;
+        }
+      }
+      HM_HIP(hipMemcpyAsync(ydev, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      gmres_combine(Q, nv, ydev, kmaxc, n, nr, x, s);
+    }
+    ++restarts;
+    residual(rn);
+    for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= tol;
+  }
+  return total_it;
+}
+}  // namespace
+
 // ------------------------------------------------------------------ ABI
 extern "C" {
 
@@ -704,16 +868,20 @@ hm_status hm_build_batch(const double* vertices, const int64_t* vtx_offsets,
                       std::vector<int64_t>(tri_offsets, tri_offsets + n_geom + 1), p, stream, out);
 }
 
-static hm_status matvec_common(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,
-                               void* stream, bool transposed) {
-  if (!h) return arg_error("hm_matvec: NULL handle");
-  if (!x || !y) return arg_error("hm_matvec: NULL vector");
-  if (nrhs < 1) return arg_error("hm_matvec: nrhs must be >= 1");
-  if (dtype != HM_F64 && dtype != HM_F32) return arg_error("hm_matvec: bad dtype");
+static hm_status matvec_common(hm_handle* h, const void* x, void* y, int64_t n_rows, int32_t nrhs,
+                               int32_t dtype, void* stream, bool transposed) {
+  const char* who = transposed ? "hm_matvec_T" : "hm_matvec";
+  if (!h) return arg_error(std::string(who) + ": NULL handle");
+  if (!x || !y) return arg_error(std::string(who) + ": NULL vector");
+  if (n_rows != h->n)
+    return arg_error(std::string(who) + ": vectors have " + std::to_string(n_rows) +
+                     " rows, the handle " + std::to_string(h->n));
+  if (nrhs < 1) return arg_error(std::string(who) + ": nrhs must be >= 1");
+  if (dtype != HM_F64 && dtype != HM_F32) return arg_error(std::string(who) + ": bad dtype");
   const size_t vb = (size_t)h->n * nrhs * (dtype == HM_F32 ? 4 : 8);
   const char* xb = (const char*)x;
   const char* yb = (const char*)y;
-  if (xb < yb + vb && yb < xb + vb) return arg_error("hm_matvec: x and y overlap");
+  if (xb < yb + vb && yb < xb + vb) return arg_error(std::string(who) + ": x and y overlap");
   return guarded([&]() -> hm_status {
     matvec_dispatch(h->plan(), h->form, x, y, nrhs, dtype == HM_F32 ? 1 : 0, transposed,
                     as_stream(stream));
@@ -721,26 +889,41 @@ static hm_status matvec_common(hm_handle* h, const void* x, void* y, int32_t nrh
   });
 }
 
-hm_status hm_matvec(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,
+hm_status hm_matvec(hm_handle* h, const void* x, void* y, int64_t n, int32_t nrhs, int32_t dtype,
                     void* stream) {
-  return matvec_common(h, x, y, nrhs, dtype, stream, false);
+  return matvec_common(h, x, y, n, nrhs, dtype, stream, false);
 }
 
-hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int32_t nrhs, int32_t dtype,
+hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int64_t n, int32_t nrhs, int32_t dtype,
                       void* stream) {
-  return matvec_common(h, x, y, nrhs, dtype, stream, true);
+  return matvec_common(h, x, y, n, nrhs, dtype, stream, true);
 }
 
 // ------------------------------------------------------------------ GMRES
-hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32_t dtype,
-                   const hm_solve_params* sp, hm_solve_info* info, void* stream) {
-  if (!h) return arg_error("hm_solve: NULL handle");
-  if (!f || !sigma || !sp) return arg_error("hm_solve: NULL argument");
-  if (nrhs < 1 || nrhs > 256) return arg_error("hm_solve: nrhs must be in 1..256");
-  if (dtype != HM_F64 && dtype != HM_F32) return arg_error("hm_solve: bad dtype");
-  if (!(sp->tol > 0.0) || !std::isfinite(sp->tol)) return arg_error("hm_solve: tol must be > 0");
-  if (sp->restart < 0 || sp->restart > 1000) return arg_error("hm_solve: restart must be in 0..1000");
-  if (sp->max_iter < 1) return arg_error("hm_solve: max_iter must be >= 1");
+static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t n_rows,
+                              int32_t nrhs, int32_t dtype, const hm_solve_params* sp,
+                              hm_solve_info* info, void* stream) {
+  const std::string who = "hm_solve";
+  if (!h) return arg_error(who + ": NULL handle");
+  if (!f || !sigma || !sp) return arg_error(who + ": NULL argument");
+  if (n_rows != h->n)
+    return arg_error(who + ": vectors have " + std::to_string(n_rows) + " rows, the handle " +
+                     std::to_string(h->n));
+  if (nrhs < 1 || nrhs > 256) return arg_error(who + ": nrhs must be in 1..256");
+  if (dtype != HM_F64 && dtype != HM_F32) return arg_error(who + ": bad dtype");
+  if (!(sp->tol > 0.0) || !std::isfinite(sp->tol)) return arg_error(who + ": tol must be > 0");
+  if (sp->restart < 0 || sp->restart > 1000) return arg_error(who + ": restart must be in 0..1000");
+  if (sp->max_iter < 1) return arg_error(who + ": max_iter must be >= 1");
+  if (sp->refine != 0 && sp->refine != 1) return arg_error(who + ": refine must be 0 or 1");
+  if (sp->refine && (!(sp->inner_tol >= 0.0) || !(sp->inner_tol < 1.0)))
+    return arg_error(who + ": inner_tol must be in [0, 1)");
+  if (sp->flags & ~HM_SOLVE_GRAPH) return arg_error(who + ": unknown flag");
+  {
+    const size_t vb = (size_t)h->n * nrhs * (dtype == HM_F32 ? 4 : 8);
+    const char* fb = (const char*)f;
+    const char* sb = (const char*)sigma;
+    if (fb < sb + vb && sb < fb + vb) return arg_error(who + ": f and sigma overlap");
+  }
   return guarded([&]() -> hm_status {
     hipStream_t s = as_stream(stream);
     const int64_t n = h->n;
@@ -748,30 +931,41 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
     const int64_t nv = n * nr;
     const int m = sp->restart > 0 ? sp->restart : 100;
     const bool tr = sp->transpose != 0;
+    const bool refine = sp->refine != 0;
+    const double inner_tol = refine ? (sp->inner_tol > 0.0 ? sp->inner_tol : 1e-4) : 0.0;
     const MvPlan P = h->plan();
-    auto apply = [&](const double* in, double* out) {
-      matvec_dispatch(P, h->form, in, out, nr, 0, tr, s);
-    };
     // device workspace: per call, or kept with the handle for graph replays
     const bool use_graph = (sp->flags & HM_SOLVE_GRAPH) != 0;
     std::unique_ptr<SolveWs> local;
     SolveWs* ws = nullptr;
     if (use_graph) {
-      if (!h->sws || h->sws->nr != nr || h->sws->m != m || h->sws->tr != tr) {
+      if (!h->sws || h->sws->nr != nr || h->sws->m != m || h->sws->tr != tr ||
+          h->sws->f32 != refine) {
         if (h->sws) h->sws->free_stream = s;
         h->sws.reset(new SolveWs());
-        h->sws->alloc(n, nr, m, tr, s);
+        h->sws->alloc(n, nr, m, tr, refine, s);
       }
       ws = h->sws.get();
     } else {
       local.reset(new SolveWs());
       local->free_stream = s;
-      local->alloc(n, nr, m, tr, s);
+      local->alloc(n, nr, m, tr, refine, s);
       ws = local.get();
     }
-    double *Q = ws->Q, *fd = ws->fd, *x = ws->x, *w = ws->w, *hdev = ws->hdev, *part = ws->part,
-           *scl = ws->scl, *ydev = ws->ydev;
-    double* hnorm = hdev + (size_t)(m + 2) * nr * 2;   // |w| of the current step
+    // op(H) v with double vectors and double accumulation (the plain solve
+    // and the refinement residual) ...
+    auto apply64 = [&](const double* in, double* out) {
+      matvec_dispatch(P, h->form, in, out, nr, 0, tr, s);
+    };
+    // ... and with float vectors (the inner solve of the refinement): the
+    // basis vector is rounded to float, the product accumulates in float for
+    // the single-precision forms, the result is widened back to double
+    auto apply32 = [&](const double* in, double* out) {
+      convert_f64_to_f32(in, nv, ws->xf, s);
+      matvec_dispatch(P, h->form, ws->xf, ws->wf, nr, 1, tr, s);
+      convert_f32_to_f64(ws->wf, nv, out, s);
+    };
+    const int mhd = m + 2;
     if (use_graph && !ws->exec) {
       // capture one Arnoldi step on a private stream (the caller's may be the
       // null stream, which cannot capture); no profiling events inside
@@ -784,153 +978,98 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
         ~StreamGuard() { (void)hipStreamDestroy(st); }
       } sgd{cs};
       HM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-      gmres_copy_col(Q, nv, ws->jd, ws->xin, cs);
-      matvec_dispatch(Pg, h->form, ws->xin, w, nr, 0, tr, cs);
-      for (int pass = 0; pass < 2; ++pass) {
-        double* hp = hdev + (size_t)pass * (m + 2) * nr;
-        gmres_dots_dev(Q, nv, ws->jd, m + 1, w, n, nr, part, hp, cs);
-        gmres_orth_update_dev(Q, nv, hp, ws->jd, n, nr, w, cs);
+      if (refine) {
+        gmres_copy_col_f32(ws->Q, nv, ws->jd, ws->xf, cs);
+        matvec_dispatch(Pg, h->form, ws->xf, ws->wf, nr, 1, tr, cs);
+        convert_f32_to_f64(ws->wf, nv, ws->w, cs);
+      } else {
+        gmres_copy_col(ws->Q, nv, ws->jd, ws->xin, cs);
+        matvec_dispatch(Pg, h->form, ws->xin, ws->w, nr, 0, tr, cs);
       }
-      gmres_dots(w, 0, 1, w, n, nr, part, hnorm, cs);
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hp = ws->hdev + (size_t)pass * mhd * nr;
+        gmres_dots_dev(ws->Q, nv, ws->jd, m + 1, ws->w, n, nr, ws->part, hp, cs);
+        gmres_orth_update_dev(ws->Q, nv, hp, ws->jd, n, nr, ws->w, cs);
+      }
+      gmres_dots(ws->w, 0, 1, ws->w, n, nr, ws->part, ws->hdev + (size_t)mhd * nr * 2, cs);
       HM_HIP(hipStreamEndCapture(cs, &ws->graph));
       HM_HIP(hipGraphInstantiate(&ws->exec, ws->graph, nullptr, nullptr, 0));
     }
-
-    if (dtype == HM_F32) {
-      convert_f32_to_f64((const float*)f, nv, fd, s);
-      if (sp->use_x0) convert_f32_to_f64((const float*)sigma, nv, x, s);
-    } else {
-      HM_HIP(hipMemcpyAsync(fd, f, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-      if (sp->use_x0) HM_HIP(hipMemcpyAsync(x, sigma, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    if (!sp->use_x0) HM_HIP(hipMemsetAsync(x, 0, nv * sizeof(double), s));
-
-    std::vector<double> hv((size_t)(m + 2) * nr * 2 + nr);
+    auto graph_step = [&](int j) {
+      const int jh = j;
+      HM_HIP(hipMemcpyAsync(ws->jd, &jh, sizeof(int), hipMemcpyHostToDevice, s));
+      HM_HIP(hipGraphLaunch(ws->exec, s));
+    };
     auto norms = [&](const double* v, std::vector<double>& out) {
-      gmres_dots(v, 0, 1, v, n, nr, part, hdev, s);
+      gmres_dots(v, 0, 1, v, n, nr, ws->part, ws->hdev, s);
       out.resize(nr);
-      HM_HIP(hipMemcpyAsync(out.data(), hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HM_HIP(hipMemcpyAsync(out.data(), ws->hdev, nr * sizeof(double), hipMemcpyDeviceToHost, s));
       HM_HIP(hipStreamSynchronize(s));
       for (auto& z : out) z = std::sqrt(std::max(z, 0.0));
     };
-    std::vector<double> fn;
-    norms(fd, fn);
-    // r = f - H x  (into w)
-    auto residual = [&](std::vector<double>& rn) {
-      apply(x, w);
-      gmres_sub(fd, w, nv, w, s);
-      norms(w, rn);
-    };
-    std::vector<double> rn;
-    residual(rn);
+
+    // the right-hand side in double (fo when refining, else fd directly)
+    double* fsrc = refine ? ws->fo : ws->fd;
+    double* xsol = refine ? ws->xs : ws->x;
+    if (dtype == HM_F32) {
+      convert_f32_to_f64((const float*)f, nv, fsrc, s);
+      if (sp->use_x0) convert_f32_to_f64((const float*)sigma, nv, xsol, s);
+    } else {
+      HM_HIP(hipMemcpyAsync(fsrc, f, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (sp->use_x0)
+        HM_HIP(hipMemcpyAsync(xsol, sigma, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    if (!sp->use_x0) HM_HIP(hipMemsetAsync(xsol, 0, nv * sizeof(double), s));
+
+    std::vector<double> fn, rn;
     std::vector<int> conv(nr, 0);
+    norms(fsrc, fn);
     auto rel = [&](int c, double r) { return fn[c] > 0 ? r / fn[c] : 0.0; };
-    for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= sp->tol;
-    int total_it = 0, restarts = 0;
-    // per-column Arnoldi state
-    std::vector<double> H((size_t)(m + 1) * m * nr), cs((size_t)m * nr), sn((size_t)m * nr),
-        gv((size_t)(m + 1) * nr);
-    std::vector<int> kc(nr);
-    std::vector<double> sc(nr);
-    while (total_it < sp->max_iter) {
-      bool all = true;
-      for (int c = 0; c < nr; ++c) all = all && conv[c];
-      if (all) break;
-      // Q0 = r / |r| for active columns
-      for (int c = 0; c < nr; ++c) sc[c] = (!conv[c] && rn[c] > 0) ? 1.0 / rn[c] : 0.0;
-      HM_HIP(hipMemcpyAsync(scl, sc.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
-      gmres_scale_cols(w, scl, n, nr, Q, s);
-      std::vector<int> active(nr);
-      for (int c = 0; c < nr; ++c) {
-        active[c] = !conv[c];
-        kc[c] = 0;
-        std::fill(gv.begin() + (size_t)c * (m + 1), gv.begin() + (size_t)(c + 1) * (m + 1), 0.0);
-        gv[(size_t)c * (m + 1)] = rn[c];
-      }
-      int j = 0;
-      for (; j < m && total_it < sp->max_iter; ++j) {
-        if (use_graph) {
-          const int jh = j;
-          HM_HIP(hipMemcpyAsync(ws->jd, &jh, sizeof(int), hipMemcpyHostToDevice, s));
-          HM_HIP(hipGraphLaunch(ws->exec, s));
-        } else {
-          double* qj = Q + (size_t)j * nv;
-          apply(qj, w);
-          // classical Gram-Schmidt, twice
-          for (int pass = 0; pass < 2; ++pass) {
-            gmres_dots(Q, nv, j + 1, w, n, nr, part, hdev + (size_t)pass * (m + 2) * nr, s);
-            gmres_orth_update(Q, nv, hdev + (size_t)pass * (m + 2) * nr, j + 1, n, nr, w, s);
-          }
-          gmres_dots(w, 0, 1, w, n, nr, part, hnorm, s);
+    int total_it = 0, restarts = 0, ir_steps = 0;
+    if (!refine) {
+      total_it = gmres_core(ws, n, nr, m, sp->tol, sp->max_iter, use_graph, apply64, graph_step,
+                            fn, rn, conv, restarts, false, s);
+    } else {
+      // iterative refinement: the residual of the current solution in double
+      // (vectors and accumulation), the correction from GMRES with float
+      // products to the relative tolerance inner_tol, added in double
+      std::vector<double> rprev, rin, zero_fn;
+      std::vector<int> cin;
+      std::vector<double> keep(nr);
+      while (true) {
+        apply64(xsol, ws->w);
+        gmres_sub(ws->fo, ws->w, nv, ws->fd, s);    // r = f - H sigma  (the inner right-hand side)
+        norms(ws->fd, rn);
+        for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= sp->tol;
+        bool all = true;
+        for (int c = 0; c < nr; ++c) all = all && conv[c];
+        if (all || total_it >= sp->max_iter) break;
+        // stagnation: no column's residual fell below 90% of the previous one
+        if (!rprev.empty()) {
+          bool progress = false;
+          for (int c = 0; c < nr; ++c)
+            if (!conv[c] && rn[c] < 0.9 * rprev[c]) progress = true;
+          if (!progress) break;
         }
-        HM_HIP(hipMemcpyAsync(hv.data(), hdev, hv.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HM_HIP(hipStreamSynchronize(s));
-        ++total_it;
-        bool any = false;
-        for (int c = 0; c < nr; ++c) {
-          const double hn = std::sqrt(std::max(hv[(size_t)(m + 2) * nr * 2 + c], 0.0));
-          sc[c] = 0.0;
-          if (!active[c]) continue;
-          double* Hc = H.data() + (size_t)c * (m + 1) * m;
-          for (int k = 0; k <= j; ++k)
-            Hc[(size_t)k * m + j] = hv[(size_t)k * nr + c] + hv[(size_t)(m + 2) * nr + (size_t)k * nr + c];
-          Hc[(size_t)(j + 1) * m + j] = hn;
-          // previous rotations
-          double* csc = cs.data() + (size_t)c * m;
-          double* snc = sn.data() + (size_t)c * m;
-          for (int k = 0; k < j; ++k) {
-            const double a = Hc[(size_t)k * m + j], b = Hc[(size_t)(k + 1) * m + j];
-            Hc[(size_t)k * m + j] = csc[k] * a + snc[k] * b;
-            Hc[(size_t)(k + 1) * m + j] = -snc[k] * a + csc[k] * b;
-          }
-          const double a = Hc[(size_t)j * m + j], b = Hc[(size_t)(j + 1) * m + j];
-          const double rr = std::hypot(a, b);
-          csc[j] = rr > 0 ? a / rr : 1.0;
-          snc[j] = rr > 0 ? b / rr : 0.0;
-          Hc[(size_t)j * m + j] = rr;
-          Hc[(size_t)(j + 1) * m + j] = 0.0;
-          double* gc = gv.data() + (size_t)c * (m + 1);
-          gc[j + 1] = -snc[j] * gc[j];
-          gc[j] = csc[j] * gc[j];
-          kc[c] = j + 1;
-          const double est = rel(c, std::fabs(gc[j + 1]));
-          if (est <= sp->tol || hn == 0.0) {
-            active[c] = 0;
-          } else {
-            sc[c] = 1.0 / hn;
-            any = true;
-          }
-        }
-        if (!any) break;
-        HM_HIP(hipMemcpyAsync(scl, sc.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
-        gmres_scale_cols(w, scl, n, nr, Q + (size_t)(j + 1) * nv, s);
+        rprev = rn;
+        // converged columns take no part in the correction (zero right-hand side)
+        for (int c = 0; c < nr; ++c) keep[c] = conv[c] ? 0.0 : 1.0;
+        HM_HIP(hipMemcpyAsync(ws->scl, keep.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+        gmres_scale_cols(ws->fd, ws->scl, n, nr, ws->fd, s);
+        HM_HIP(hipMemsetAsync(ws->x, 0, nv * sizeof(double), s));
+        std::vector<double> fin(nr);
+        for (int c = 0; c < nr; ++c) fin[c] = conv[c] ? 0.0 : rn[c];
+        total_it += gmres_core(ws, n, nr, m, inner_tol, sp->max_iter - total_it, use_graph, apply32,
+                               graph_step, fin, rin, cin, restarts, true, s);
+        gmres_add(xsol, ws->x, nv, xsol, s);
+        ++ir_steps;
       }
-      // x += Q y  (upper triangular solves on the host)
-      int kmaxc = 0;
-      for (int c = 0; c < nr; ++c) kmaxc = std::max(kmaxc, kc[c]);
-      if (kmaxc > 0) {
-        std::vector<double> y((size_t)kmaxc * nr, 0.0);
-        for (int c = 0; c < nr; ++c) {
-          const double* Hc = H.data() + (size_t)c * (m + 1) * m;
-          const double* gc = gv.data() + (size_t)c * (m + 1);
-          for (int k = kc[c] - 1; k >= 0; --k) {
-            double v = gc[k];
-            for (int l = k + 1; l < kc[c]; ++l) v -= Hc[(size_t)k * m + l] * y[(size_t)l * nr + c];
-            y[(size_t)k * nr + c] = Hc[(size_t)k * m + k] != 0.0 ? v / Hc[(size_t)k * m + k] : 0.0;
-          }
-        }
-        HM_HIP(hipMemcpyAsync(ydev, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        gmres_combine(Q, nv, ydev, kmaxc, n, nr, x, s);
-      }
-      ++restarts;
-      residual(rn);
-      for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= sp->tol;
     }
     // result
     if (dtype == HM_F32)
-      convert_f64_to_f32(x, nv, (float*)sigma, s);
+      convert_f64_to_f32(xsol, nv, (float*)sigma, s);
     else
-      HM_HIP(hipMemcpyAsync(sigma, x, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HM_HIP(hipMemcpyAsync(sigma, xsol, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
     HM_HIP(hipStreamSynchronize(s));
     int nconv = 0;
     double worst = 0.0;
@@ -942,11 +1081,16 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int32_t nrhs, int32
       info->iters = total_it;
       info->restarts = restarts;
       info->converged = nconv;
-      info->pad = 0;
+      info->ir_steps = ir_steps;
       info->rel_residual = worst;
     }
     return nconv == nr ? HM_OK : HM_NOT_CONVERGED;
   });
+}
+
+hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int64_t n, int32_t nrhs,
+                   int32_t dtype, const hm_solve_params* sp, hm_solve_info* info, void* stream) {
+  return solve_common(h, f, sigma, n, nrhs, dtype, sp, info, stream);
 }
 
 void hm_free(hm_handle* h) {

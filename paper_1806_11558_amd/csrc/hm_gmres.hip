@@ -87,6 +87,14 @@ __global__ void k_scale_cols(const double* __restrict__ a, const double* __restr
     out[e] = a[e] * s[e % nr];
 }
 
+// out = a + b
+__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, int64_t tot,
+                      double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = a[e] + b[e];
+}
+
 // out = a - b
 __global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, int64_t tot,
                       double* __restrict__ out) {
@@ -163,6 +171,16 @@ __global__ void k_copy_col(const double* __restrict__ Q, int64_t ldq, const int*
     out[e] = q[e];
 }
 
+// out = (float) Q[jd[0]]: the Arnoldi vector of step j rounded to single
+// precision, the input of a product with float vectors
+__global__ void k_copy_col_f32(const double* __restrict__ Q, int64_t ldq, const int* __restrict__ jd,
+                               float* __restrict__ out) {
+  const double* q = Q + (int64_t)jd[0] * ldq;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ldq;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (float)q[e];
+}
+
 // ------------------------------------------------------------------ launchers
 void gmres_dots_dev(const double* Q, int64_t ldq, const int* jd, int nkmax, const double* w,
                     int64_t n, int nr, double* part, double* out, hipStream_t s) {
@@ -181,6 +199,10 @@ void gmres_orth_update_dev(const double* Q, int64_t ldq, const double* h, const 
 }
 void gmres_copy_col(const double* Q, int64_t ldq, const int* jd, double* out, hipStream_t s) {
   k_copy_col<<<grid_for(ldq, 256, 8192), 256, 0, s>>>(Q, ldq, jd, out);
+  HM_LAUNCH_CHECK();
+}
+void gmres_copy_col_f32(const double* Q, int64_t ldq, const int* jd, float* out, hipStream_t s) {
+  k_copy_col_f32<<<grid_for(ldq, 256, 8192), 256, 0, s>>>(Q, ldq, jd, out);
   HM_LAUNCH_CHECK();
 }
 void gmres_dots(const double* Q, int64_t ldq, int nk, const double* w, int64_t n, int nr,
@@ -209,6 +231,10 @@ void gmres_scale_cols(const double* a, const double* sc, int64_t n, int nr, doub
 }
 void gmres_sub(const double* a, const double* b, int64_t tot, double* out, hipStream_t s) {
   k_sub<<<grid_for(tot, 256, 8192), 256, 0, s>>>(a, b, tot, out);
+  HM_LAUNCH_CHECK();
+}
+void gmres_add(const double* a, const double* b, int64_t tot, double* out, hipStream_t s) {
+  k_add<<<grid_for(tot, 256, 8192), 256, 0, s>>>(a, b, tot, out);
   HM_LAUNCH_CHECK();
 }
 void convert_f32_to_f64(const float* a, int64_t tot, double* out, hipStream_t s) {

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(hm.Params) == 40
-    assert ctypes.sizeof(hm.SolveParams) == 32
+    assert ctypes.sizeof(hm.SolveParams) == 40
     assert ctypes.sizeof(hm.SolveInfo) == 24
     assert ctypes.sizeof(hm.Stats) == 21 * 8
 
@@ -70,9 +70,9 @@ def test_invalid_meshes_rejected(V, T, what):
 
 def test_null_handle_calls():
     L = hm.lib()
-    assert L.hm_matvec(None, None, None, 1, 0, None) == -1
-    assert L.hm_matvec_T(None, None, None, 1, 0, None) == -1
-    assert L.hm_solve(None, None, None, 1, 0, None, None, None) == -1
+    assert L.hm_matvec(None, None, None, 1, 1, 0, None) == -1
+    assert L.hm_matvec_T(None, None, None, 1, 1, 0, None) == -1
+    assert L.hm_solve(None, None, None, 1, 1, 0, None, None, None) == -1
     assert L.hm_query(None, 0, None, 0, None) == -1
     L.hm_free(None)           # NULL-safe
     assert "NULL" in hm.hm_last_error() or hm.hm_last_error() == ""
@@ -121,3 +121,51 @@ def test_invalid_batches_rejected(case, what):
 def test_null_build_batch_arguments():
     L = hm.lib()
     assert L.hm_build_batch(None, None, None, None, 1, None, None, None) == -1
+
+
+class _FakeCuda:
+    """Stands in for a device tensor in the binding's argument checks; its
+    data pointer is never dereferenced because the checks fail first."""
+    is_cuda = True
+
+    def __init__(self, shape, dtype):
+        import torch
+        self.shape = tuple(shape)
+        self.dtype = dtype
+        self._t = torch.empty(0)
+
+    def dim(self):
+        return len(self.shape)
+
+    def is_contiguous(self):
+        return True
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_wrong_length_rejected_before_any_device_access(monkeypatch):
+    """A vector whose row count differs from the handle's is refused by the
+    binding (HMatrix) and, for a raw handle, by the library itself."""
+    import torch
+    H = hm.HMatrix.__new__(hm.HMatrix)
+    H.n, H._h = 1280, None
+    x = _FakeCuda((1000,), torch.float64)
+    with pytest.raises(hm.HMError) as e:
+        H.matvec(x, out=_FakeCuda((1000,), torch.float64))
+    assert e.value.status == hm.HM_ERR_ARG and "rows" in str(e.value)
+    with pytest.raises(hm.HMError):
+        H.solve(x)
+    monkeypatch.setattr(torch, "Tensor", _FakeCuda)
+    with pytest.raises(hm.HMError) as e:
+        hm.hm_matvec(None, _FakeCuda((8, 2), torch.float64), _FakeCuda((8, 3), torch.float64))
+    assert "same shape" in str(e.value)
+
+
+def test_solve_refine_arguments_checked_in_header_order():
+    """refine / inner_tol are part of the solve parameters, and their checks
+    come after the handle check (a NULL handle is reported first)."""
+    sp = hm.SolveParams(tol=1e-8, restart=10, max_iter=10, refine=1, inner_tol=2.0)
+    L = hm.lib()
+    assert L.hm_solve(None, None, None, 1, 1, 0, ctypes.byref(sp), None, None) == -1
+    assert "NULL handle" in hm.hm_last_error()

@@ -1,6 +1,8 @@
 """FP16 factor storage (FP32 evaluation and ACA, FP32 dense blocks, U/V in
-FP16 with per-term FP32 scales for U): products against the dense oracle,
-and GMRES to a 1e-8 residual with respect to the stored operator."""
+FP16 with per-term FP32 scales for U): products against the dense oracle
+within exactly 10 eps at the tolerance the form is built for (eps 1e-4), a
+separate FP16-vs-FP32 consistency check of the factor rounding, and GMRES to
+a 1e-8 residual with respect to the stored operator."""
 import numpy as np
 import pytest
 import torch
@@ -10,9 +12,12 @@ from gpu_util import rel2, say
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 # FP16 keeps 11 significant bits: each stored factor entry is rounded with a
-# relative error <= 2^-11, and the product error is at most that fraction of
-# the low-rank part of H x.
+# relative error <= 2^-11 of its column's largest entry; the FP16 and FP32
+# forms built on one mesh share ranks and pivots up to float rounding, so
+# their products differ by a small multiple of that (consistency only; the
+# parity bound against the oracle is 10 eps).
 F16_BOUND = 2.0 ** -11
+EPS = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +34,7 @@ def test_f16_products(small, nrhs):
     from synthetic import normal_columns
     V, T, op, A = small
     say("f16 products", nrhs)
-    eps = 1e-5
+    eps = EPS
     H16 = hm.HMatrix(V, T, leaf_size=64, eps=eps, precision="f16")
     H32 = hm.HMatrix(V, T, leaf_size=64, eps=eps, precision="f32")
     assert H16.stats()["precision"] == 2
@@ -43,10 +48,9 @@ def test_f16_products(small, nrhs):
         y32 = H32.matvec(xt, transpose=tr).cpu().numpy().reshape(op.n, -1)
         ref = (A.T if tr else A) @ x
         assert rel2(y32, ref) <= 10 * eps
-        # the two forms share ranks and pivots up to float rounding, so their
-        # difference is the FP16 rounding of the factors
+        assert rel2(y16, ref) <= 10 * eps
+        # consistency of the two forms: the FP16 rounding of the factors
         assert rel2(y16, y32) <= 4 * F16_BOUND
-        assert rel2(y16, ref) <= 10 * eps + 4 * F16_BOUND
     H16.free()
     H32.free()
 
@@ -55,7 +59,7 @@ def test_f16_factors_roundtrip(small):
     import paper_1806_11558_amd as hm
     V, T, op, A = small
     say("f16 factors")
-    H = hm.HMatrix(V, T, leaf_size=64, eps=1e-5, precision="f16")
+    H = hm.HMatrix(V, T, leaf_size=64, eps=EPS, precision="f16")
     perm = H.perm()
     lb = H.lr_blocks()
     for b in np.random.default_rng(2).choice(len(lb), 20, replace=False):
@@ -63,7 +67,7 @@ def test_f16_factors_roundtrip(small):
         U, Vf = H.lr_factors(int(b))
         assert np.abs(Vf).max() <= 1.0 + 1e-3           # pivot normalisation
         Ab = A[np.ix_(perm[r0:r1], perm[c0:c1])]
-        assert np.linalg.norm(Ab - U @ Vf.T) / np.linalg.norm(Ab) <= 10 * 1e-5 + 4 * F16_BOUND
+        assert np.linalg.norm(Ab - U @ Vf.T) / np.linalg.norm(Ab) <= 10 * EPS
     H.free()
 
 
@@ -80,5 +84,5 @@ def test_f16_solve_to_1e8(small):
     assert float(torch.linalg.norm(r) / torch.linalg.norm(f)) <= 1.5e-8
     s = s.cpu().numpy()
     s_lu = np.linalg.solve(A, np.ones(op.n))
-    assert rel2(s, s_lu) <= np.linalg.cond(A) * (10 * 1e-4 + 4 * F16_BOUND)
+    assert rel2(s, s_lu) <= np.linalg.cond(A) * (10 * EPS + 1e-8)
     H.free()
