@@ -241,6 +241,27 @@ hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int64_t n, int32_t 
                    int32_t dtype, const hm_solve_params* sp, hm_solve_info* info,
                    void* stream);
 
+/*
+ * hm_solve_noalloc -- hm_solve for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as hm_solve
+ * (bitwise the same solution and info), but the solve workspace lives in a
+ * fixed device array of HM_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, and the call allocates
+ * nothing (the product workspace already belongs to the handle).
+ *   - The workspace needs 8 * (restart + 7) * n * nrhs bytes plus a little;
+ *     larger requests fail with HM_ERR_ARG before any device work.
+ *   - HM_SOLVE_GRAPH is rejected (HM_ERR_ARG).
+ *   - Every call on one GPU shares that GPU's array: calls that overlap in
+ *     time on one GPU (other threads, other streams) race and give wrong
+ *     results; serialise them.  Nothing in the array is assumed to be zero
+ *     or kept from the last call.
+ */
+#define HM_NOALLOC_SCRATCH_BYTES ((int64_t)128 << 20)
+hm_status hm_solve_noalloc(hm_handle* h, const void* f, void* sigma, int64_t n, int32_t nrhs,
+                           int32_t dtype, const hm_solve_params* sp, hm_solve_info* info,
+                           void* stream);
+
 /* Release every resource of h (NULL-safe); waits for work in flight.  The
    handle's device memory goes back to the library's memory pool on that
    device, which keeps it for later builds (allocating recently freed device

@@ -10,7 +10,7 @@ from ._binding import (  # noqa: F401
     HM_STRICT, HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE,
     HMError, HMLibraryMissing, HMatrix, Params, SolveInfo, SolveParams, Stats,
     hm_build, hm_build_batch, hm_entries, hm_free, hm_last_error, hm_matvec, hm_matvec_T,
-    hm_params_default, hm_query, hm_solve, lib, library_path, release_memory,
+    hm_params_default, hm_query, hm_solve, hm_solve_noalloc, lib, library_path, release_memory,
 )
 
 

@@ -99,6 +99,7 @@ def lib():
     L.hm_matvec_T.argtypes = [vp, vp, vp, i64, i32, i32, vp]
     L.hm_solve.argtypes = [vp, vp, vp, i64, i32, i32, C.POINTER(SolveParams),
                            C.POINTER(SolveInfo), vp]
+    L.hm_solve_noalloc.argtypes = L.hm_solve.argtypes
     L.hm_free.argtypes = [vp]
     L.hm_free.restype = None
     L.hm_query.argtypes = [vp, i32, vp, i64, C.POINTER(i64)]
@@ -107,7 +108,7 @@ def lib():
     L.hm_last_error.argtypes = []
     L.hm_release_memory.argtypes = []
     for f in ("hm_params_default", "hm_build", "hm_build_batch", "hm_release_memory", "hm_matvec", "hm_matvec_T", "hm_solve",
-              "hm_query", "hm_entries"):
+              "hm_solve_noalloc", "hm_query", "hm_entries"):
         getattr(L, f).restype = C.c_int
     _LIB = L
     return L
@@ -215,6 +216,17 @@ def hm_solve(h: int, f, sigma, sp: SolveParams, stream=None) -> tuple[int, Solve
     info = SolveInfo()
     st = lib().hm_solve(h, f.data_ptr(), sigma.data_ptr(), n, nrhs, dt, C.byref(sp),
                         C.byref(info), _stream_ptr(stream))
+    _check(st, ok=(HM_OK, HM_NOT_CONVERGED))
+    return st, info
+
+
+def hm_solve_noalloc(h: int, f, sigma, sp: SolveParams, stream=None) -> tuple[int, SolveInfo]:
+    """hm_solve with its workspace in the library's fixed device array (no
+    allocation; HM_NOALLOC_SCRATCH_BYTES at most)."""
+    n, nrhs, dt = _pair_args(f, sigma, "f and sigma")
+    info = SolveInfo()
+    st = lib().hm_solve_noalloc(h, f.data_ptr(), sigma.data_ptr(), n, nrhs, dt, C.byref(sp),
+                                C.byref(info), _stream_ptr(stream))
     _check(st, ok=(HM_OK, HM_NOT_CONVERGED))
     return st, info
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -900,10 +901,49 @@ hm_status hm_matvec_T(hm_handle* h, const void* x, void* y, int64_t n, int32_t n
 }
 
 // ------------------------------------------------------------------ GMRES
+// Workspace of hm_solve_noalloc: a file-scope device array, one copy per GPU
+// for the life of the process.  Host code uses only the address that
+// hipGetSymbolAddress returns for it on each device, never the array's name.
+constexpr size_t kScratchBytes = HM_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+// Device address of `scratch` on the current device, taken once per device.
+static double* scratch_address() {
+  static std::mutex mu;
+  static std::vector<double*> addr;
+  int dev = 0;
+  HM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      throw Error{HM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                  hipGetErrorString(e)};
+    addr[dev] = static_cast<double*>(ptr);
+  }
+  return addr[dev];
+}
+
+// Doubles the solve workspace takes, every buffer rounded up to 256 bytes.
+static size_t solve_ws_doubles(int64_t n, int nr, int m, bool refine) {
+  size_t tot = 0;
+  SolveWs probe;
+  probe.layout(n, nr, m, false, refine, [&](size_t cnt) {
+    tot += (cnt + 31) & ~(size_t)31;
+    return (double*)nullptr;
+  });
+  return tot;
+}
+
+// fixed_ws: null => the workspace comes from the library's pool; else the
+// solve runs in that device buffer of fixed_doubles doubles and allocates
+// nothing (no graph replay in that mode).
 static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t n_rows,
                               int32_t nrhs, int32_t dtype, const hm_solve_params* sp,
-                              hm_solve_info* info, void* stream) {
-  const std::string who = "hm_solve";
+                              hm_solve_info* info, void* stream, bool no_alloc) {
+  const std::string who = no_alloc ? "hm_solve_noalloc" : "hm_solve";
   if (!h) return arg_error(who + ": NULL handle");
   if (!f || !sigma || !sp) return arg_error(who + ": NULL argument");
   if (n_rows != h->n)
@@ -918,6 +958,16 @@ static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t 
   if (sp->refine && (!(sp->inner_tol >= 0.0) || !(sp->inner_tol < 1.0)))
     return arg_error(who + ": inner_tol must be in [0, 1)");
   if (sp->flags & ~HM_SOLVE_GRAPH) return arg_error(who + ": unknown flag");
+  if (no_alloc) {
+    if (sp->flags & HM_SOLVE_GRAPH)
+      return arg_error(who + ": HM_SOLVE_GRAPH is not available without allocation");
+    const int mm = sp->restart > 0 ? sp->restart : 100;
+    const size_t need = solve_ws_doubles(h->n, nrhs, mm, sp->refine != 0) * sizeof(double);
+    if (need > kScratchBytes)
+      return arg_error(who + ": the workspace needs " + std::to_string(need) +
+                       " bytes, more than the fixed " + std::to_string(kScratchBytes) +
+                       " (reduce n * nrhs * (restart + 7))");
+  }
   {
     const size_t vb = (size_t)h->n * nrhs * (dtype == HM_F32 ? 4 : 8);
     const char* fb = (const char*)f;
@@ -938,7 +988,19 @@ static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t 
     const bool use_graph = (sp->flags & HM_SOLVE_GRAPH) != 0;
     std::unique_ptr<SolveWs> local;
     SolveWs* ws = nullptr;
-    if (use_graph) {
+    if (no_alloc) {
+      // bump allocation in the device's fixed array (size checked above)
+      double* base = scratch_address();
+      size_t used = 0;
+      local.reset(new SolveWs());
+      local->free_stream = s;
+      local->layout(n, nr, m, tr, refine, [&](size_t cnt) {
+        double* q = base + used;
+        used += (cnt + 31) & ~(size_t)31;
+        return q;
+      });
+      ws = local.get();
+    } else if (use_graph) {
       if (!h->sws || h->sws->nr != nr || h->sws->m != m || h->sws->tr != tr ||
           h->sws->f32 != refine) {
         if (h->sws) h->sws->free_stream = s;
@@ -1090,7 +1152,13 @@ static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t 
 
 hm_status hm_solve(hm_handle* h, const void* f, void* sigma, int64_t n, int32_t nrhs,
                    int32_t dtype, const hm_solve_params* sp, hm_solve_info* info, void* stream) {
-  return solve_common(h, f, sigma, n, nrhs, dtype, sp, info, stream);
+  return solve_common(h, f, sigma, n, nrhs, dtype, sp, info, stream, false);
+}
+
+hm_status hm_solve_noalloc(hm_handle* h, const void* f, void* sigma, int64_t n, int32_t nrhs,
+                           int32_t dtype, const hm_solve_params* sp, hm_solve_info* info,
+                           void* stream) {
+  return solve_common(h, f, sigma, n, nrhs, dtype, sp, info, stream, true);
 }
 
 void hm_free(hm_handle* h) {
