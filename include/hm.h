@@ -299,9 +299,13 @@ typedef enum {
                              forward V^T x, (unused), forward panels, then
                              transposed gather, transposed panel dots,
                              transposed block sums, transposed column leaves */
-  HM_Q_TUNE = 11          /* double[k][2] (unit columns, ms per one-column
+  HM_Q_TUNE = 11,         /* double[k][2] (unit columns, ms per one-column
                              product) of every width the autotuner timed;
                              k = 0 without HM_AUTOTUNE                       */
+  HM_Q_DENSE_ENTRIES = 12 /* for dense block b = *(int64*)dst on entry (the
+                             order of HM_Q_DENSE_BLOCKS): its stored entries,
+                             double[m][n] row-major, rows and columns in
+                             Morton order of the block's clusters           */
 } hm_query_kind;
 
 #define HM_NPHASE 8        /* geometry, morton+sort, tree+boxes, partition,

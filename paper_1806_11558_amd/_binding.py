@@ -17,7 +17,7 @@ HM_STRICT = 1
 HM_PROFILE = 2
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
  HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES,
- HM_Q_TUNE) = range(12)
+ HM_Q_TUNE, HM_Q_DENSE_ENTRIES) = range(13)
 HM_NPHASE = 8
 HM_NKERNEL = 8
 KERNELS = ("fwd_gather", "fwd_vtx", "fwd_unused", "fwd_panels",
@@ -408,6 +408,17 @@ class HMatrix:
         U = buf[: m * r].reshape(r, m).T.astype(np.float64)
         V = buf[m * r:].reshape(r, n).T.astype(np.float64)
         return U, V
+
+    def dense_entries(self, b: int, blocks=None):
+        """The stored entries of dense block b (in the order of
+        dense_blocks(), which may be passed in), m x n, rows and columns in
+        Morton order."""
+        blk = (self.dense_blocks() if blocks is None else blocks)[b]
+        m, n = int(blk[1] - blk[0]), int(blk[3] - blk[2])
+        buf = np.zeros(max(m * n, 1), dtype=np.float64)
+        buf.view(np.int64)[0] = b
+        _check(lib().hm_query(self._h, HM_Q_DENSE_ENTRIES, buf.ctypes.data, buf.nbytes, None))
+        return buf[: m * n].reshape(m, n)
 
     def entries(self, rows, cols):
         return hm_entries(self._h, rows, cols)

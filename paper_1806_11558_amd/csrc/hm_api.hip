@@ -1300,6 +1300,48 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
         HM_HIP(hipFree(buf));
         return HM_OK;
       }
+      case HM_Q_DENSE_ENTRIES: {
+        if (!dst || dst_bytes < 8) return arg_error("hm_query: block index expected in dst");
+        const int64_t b = *(const int64_t*)dst;
+        if (b < 0 || b >= h->nd) return arg_error("hm_query: block index out of range");
+        int2 ts;
+        HM_HIP(hipMemcpy(&ts, h->dns + b, 8, hipMemcpyDeviceToHost));
+        Cluster t, sg;
+        HM_HIP(hipMemcpy(&t, h->cl + ts.x, 16, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(&sg, h->cl + ts.y, 16, hipMemcpyDeviceToHost));
+        int2 lt;
+        HM_HIP(hipMemcpy(&lt, h->cl_leaves + ts.x, 8, hipMemcpyDeviceToHost));
+        const int64_t m = t.y - t.x, nc = sg.y - sg.x;
+        if (!check(m * nc * 8)) return arg_error("hm_query: destination too small");
+        // the block's row slices, one per leaf of its row cluster: ld x nc,
+        // column-major, in the dense storage type
+        int64_t q0 = 0;
+        HM_HIP(hipMemcpy(&q0, h->sto.dub + b, 8, hipMemcpyDeviceToHost));
+        const int nlf = lt.y - lt.x + 1;
+        std::vector<uint64_t> addr(nlf);
+        std::vector<int32_t> llo(nlf), lm(nlf);
+        std::vector<int64_t> ld(nlf + 1);
+        HM_HIP(hipMemcpy(addr.data(), h->sto.dptr + q0, nlf * 8, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(llo.data(), h->leaf_lo + lt.x, nlf * 4, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(lm.data(), h->leaf_m + lt.x, nlf * 4, hipMemcpyDeviceToHost));
+        HM_HIP(hipMemcpy(ld.data(), h->ldpre + lt.x, (nlf + 1) * 8, hipMemcpyDeviceToHost));
+        const size_t es = h->f32 ? 4 : 8;
+        double* o = (double*)dst;
+        for (int k = 0; k < nlf; ++k) {
+          const int64_t ldk = ld[k + 1] - ld[k];
+          std::vector<char> buf((size_t)ldk * nc * es);
+          HM_HIP(hipMemcpy(buf.data(), (const void*)(uintptr_t)addr[k], buf.size(),
+                           hipMemcpyDeviceToHost));
+          for (int64_t j = 0; j < nc; ++j)
+            for (int i = 0; i < lm[k]; ++i) {
+              const int64_t e = j * ldk + i;
+              const double v = es == 4 ? (double)((const float*)buf.data())[e]
+                                       : ((const double*)buf.data())[e];
+              o[(int64_t)(llo[k] - t.x + i) * nc + j] = v;
+            }
+        }
+        return HM_OK;
+      }
       default:
         return arg_error("hm_query: unknown query kind");
     }

@@ -174,6 +174,8 @@ struct Storage {
   int32_t* ubeg = nullptr;
   int ldmax = 0;
   float* su = nullptr;       // per-term scales when the factors are FP16
+  int64_t* dub = nullptr;    // dense block -> its first (block, row leaf) item
+  uint64_t* dptr = nullptr;  // address of every dense item's slice (ld x n)
   int32_t* colmap = nullptr;
   int64_t ncols = 0;
   TItem* titems = nullptr;

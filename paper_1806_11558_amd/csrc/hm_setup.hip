@@ -1047,6 +1047,21 @@ __global__ void k_urec(const int32_t* __restrict__ sidx, const int32_t* __restri
   }
 }
 
+// Address of every dense item's slice, indexed by (block, row leaf) (for
+// reading the stored near field back).
+__global__ void k_drec(const int32_t* __restrict__ sidx, const int32_t* __restrict__ ib,
+                       const int32_t* __restrict__ ilf, int64_t np, const int2* __restrict__ blk,
+                       const int2* __restrict__ cl_leaves, const int64_t* __restrict__ ub,
+                       const int64_t* __restrict__ offI, uint64_t base, int esize,
+                       uint64_t* __restrict__ dptr) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = sidx[p];
+    const int b = ib[u], lf = ilf[u];
+    dptr[ub[b] + (lf - cl_leaves[blk[b].x].x)] = base + (uint64_t)(offI[p] * esize);
+  }
+}
+
 __global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* __restrict__ cl_leaves,
                           const int64_t* __restrict__ ldpre, const int32_t* __restrict__ rank,
                           const int64_t* __restrict__ toff, int64_t toff_base,
@@ -1447,6 +1462,17 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   if (PD.np > 0) {
     k_near<T><<<grid_for(PD.np, 1, 1 << 20), 256, 0, s>>>(g, PD.sidx, PD.ib, PD.ilf, PD.np,
                                                           in.dns, in.cl, L, PD.offI, D);
+    HM_LAUNCH_CHECK();
+  }
+  // slice addresses of the dense items, by (block, row leaf)
+  out.dub = static_cast<int64_t*>(alloc((size_t)(in.nd + 1) * sizeof(int64_t)));
+  out.dptr = static_cast<uint64_t*>(alloc((size_t)(PD.np + 1) * sizeof(uint64_t)));
+  if (in.nd > 0)
+    HM_HIP(hipMemcpyAsync(out.dub, oD, in.nd * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  if (PD.np > 0) {
+    k_drec<<<grid_for(PD.np, 256), 256, 0, s>>>(PD.sidx, PD.ib, PD.ilf, PD.np, in.dns,
+                                                in.cl_leaves, oD, PD.offI,
+                                                (uint64_t)(uintptr_t)D, esize, out.dptr);
     HM_LAUNCH_CHECK();
   }
   // keep what the transposed items need

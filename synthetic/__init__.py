@@ -6,8 +6,8 @@ H-matrix method's arithmetic (no quadrature, no kernel, no clustering), so
 that the CPU oracle and the HIP path can both consume the same inputs
 without sharing any computation.
 """
-from .meshes import icosphere, perturbed_sphere, mesh_sha256
+from .meshes import icosphere, mesh_sha256, perturbed_sphere, with_near_duplicates
 from .vectors import normal_columns, sample_rows
 
-__all__ = ["icosphere", "perturbed_sphere", "mesh_sha256",
+__all__ = ["icosphere", "perturbed_sphere", "with_near_duplicates", "mesh_sha256",
            "normal_columns", "sample_rows"]

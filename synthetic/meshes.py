@@ -101,6 +101,24 @@ def perturbed_sphere(level: int, seed: int, amplitude: float = 0.1, lmax: int = 
     return np.ascontiguousarray(v * r[:, None]), t
 
 
+def with_near_duplicates(v: np.ndarray, t: np.ndarray, count: int, shift: float, seed: int):
+    """The mesh (v, t) plus `count` extra triangles, each a copy of a randomly
+    chosen triangle (default_rng(seed)) moved by `shift` along one of its
+    edges: distinct triangles whose centres lie within `shift` of each
+    other, so that their Morton keys can tie.  The copies are appended after
+    the original triangles, with their own vertices."""
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(t.shape[0], count, replace=False)
+    tri = v[t[pick]]                                   # [count, 3, 3]
+    e = tri[:, 1] - tri[:, 0]
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    moved = tri + shift * e[:, None, :]
+    nv = v.shape[0]
+    v2 = np.concatenate([v, moved.reshape(-1, 3)])
+    t2 = np.concatenate([t, (nv + np.arange(3 * count)).reshape(count, 3)]).astype(np.int32)
+    return np.ascontiguousarray(v2), np.ascontiguousarray(t2)
+
+
 def mesh_sha256(v: np.ndarray, t: np.ndarray) -> str:
     h = hashlib.sha256()
     h.update(np.ascontiguousarray(v, dtype=np.float64).tobytes())

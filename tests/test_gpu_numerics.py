@@ -36,27 +36,6 @@ def test_entries(small, prec, tol):
     H.free()
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-6)])
-def test_dense_blocks_stored(small, prec, tol):
-    import paper_1806_11558_amd as hm
-    V, T, op, A = small
-    say("dense blocks", prec)
-    H = hm.HMatrix(V, T, leaf_size=32, eps=1e-6, precision=prec)
-    perm = H.perm()
-    db = H.dense_blocks()
-    assert len(db) > 0
-    # each dense block's product with a unit vector comes out of the matvec;
-    # here the stored entries are reconstructed via the factors-free path:
-    # H restricted to dense blocks is checked through hm_entries above and
-    # through the product below; count and shape checks here
-    m = db[:, 1] - db[:, 0]
-    n = db[:, 3] - db[:, 2]
-    assert (m <= 32).all() or (n <= 32).all()
-    st = H.stats()
-    assert st["dense_entries"] == int((m * n).sum())
-    H.free()
-
-
 @pytest.mark.parametrize("eps", [1e-4, 1e-6, 1e-8])
 def test_aca_blocks_vs_exact(small, eps):
     import paper_1806_11558_amd as hm
