@@ -31,6 +31,7 @@ constexpr int kNQ = 7;              // quadrature nodes of the triangle rule
 constexpr int kMaxLeaf = 64;        // leaf clusters fit one wavefront
 constexpr int kMaxRank = 256;
 constexpr int64_t kAcaPoolCap = int64_t(40) << 30;  // bytes of ACA working slots at once
+constexpr int kAcaFirstRank = 24;   // rank cap of the first ACA pass (slot size)
 
 // Radon's seven-point degree-5 rule: weights normalised to sum to one.
 // Node q = 0 is the centroid; nodes 1..3 use (a1, a1, b1), 4..6 (a2, a2, b2).
@@ -44,6 +45,7 @@ struct Radon7 {
   static constexpr double w1 = (155.0 - s15) / 1200.0;
   static constexpr double w2 = (155.0 + s15) / 1200.0;
 };
+
 
 // ---------------------------------------------------------------- device data
 // Geometry in Morton order, structure of arrays.
@@ -165,7 +167,7 @@ struct Storage {
   LrMeta* meta = nullptr;
   int64_t* ucol = nullptr;
   uint64_t* uptr = nullptr;
-  int64_t lr_elems = 0, toff_total = 0, nchunks = 0, u_items = 0;
+  int64_t lr_elems = 0, toff_total = 0, nchunks = 0, u_items = 0, aca_reruns = 0;
   Run* runs = nullptr;
   int nruns = 0;
   Unit* units = nullptr;

@@ -236,6 +236,19 @@ __device__ inline A wsum(A v) {
   return rdl_v(v, 63);
 }
 
+// Values that are equal in every lane, moved to scalar registers, so that
+// the compiler sees the branches on them as uniform.  The workgroup ACA and
+// the work queue branch only on such values: a barrier then never sits in
+// control flow that the compiler treats as divergent (it may otherwise let
+// some lanes run ahead to a barrier while others still hold pending work).
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni(float v) { return __int_as_float(uni(__float_as_int(v))); }
+__device__ inline double uni(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)uni((int)(unsigned)b), hi = (unsigned)uni((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Pivot search: key = bit pattern of |value| (monotone for non-negative
 // floats), larger key wins, ties go to the smaller index (stored as ~index,
 // larger wins).  {0, 0} is the "no candidate" sentinel and loses to every
@@ -279,22 +292,35 @@ __device__ inline int piv_index(const Piv& p) {
   return (p.k == 0 && p.ni == 0) ? -1 : (int)(~p.ni);
 }
 
+// Size classes of the batched ACA, by max(m, n) of the block: 0 one
+// 1,024-thread workgroup per block (> kAcaBig), 1 one 256-thread workgroup
+// (> 256), 2..4 one wavefront per block with Q = 4, 2, 1 rows and columns
+// per lane (up to 256, 128, 64).  Each class is its own kernel (its own
+// register allocation) and its own work queue.
 constexpr int kAcaClasses = 5;
-constexpr int kAcaBig = 4096;   // max(m, n) above which a block gets 1024 threads
+constexpr int kAcaBig = 4096;
+constexpr int kAcaThreads = 256;
+constexpr int kAcaWaves = kAcaThreads / 64;
+
+// Working slot of a block: U column-major m x kc, then V n x kc, then m
+// bytes of used-row flags (workgroup variant); kc = the block's rank cap in
+// the pass that owns the slot.
+struct AcaSlot {
+  uint64_t ptr;
+  int32_t kc;
+  int32_t pad;
+};
 
 template <typename T>
 struct AcaArgs {
   Geom<T> g;
   const int2* blk;       // (tau, sigma) of the chunk's blocks
   const Cluster* cl;
-  const int64_t* slot;   // element offset of every block's working slot in pool
-  int64_t slot0;         // slot offset of the chunk's first block (pool[0])
-  T* pool;
-  const int32_t* list[kAcaClasses];  // blocks of class 0 (1024-thread workgroup),
-                                     // 1 (256-thread workgroup), 2..4 (wavefront,
-                                     // Q = 4, 2, 1)
+  const AcaSlot* slot;   // working slot of every block of the chunk
+  const int32_t* list[kAcaClasses];  // block indices of each class, largest first
   int64_t cnt[kAcaClasses];
-  int kmax;
+  int* head;             // queue position of each class (zero before the launches)
+  int kmax;              // rank cap of this pass
   double eps;
   int32_t* rank;         // out: rank per block
   int32_t* info;         // out: bit 0 cap hit, bits 1.. number of row evaluations
@@ -319,8 +345,6 @@ __device__ inline X pick(const X (&a)[Q], int q) {
 // L + 64 q, q < Q.  The working factors live in the block's slot: U
 // column-major m x kcap, then V n x kcap; a lane only reads and writes its
 // own rows / columns of them, other lanes' values arrive by readlane.
-constexpr int kAcaThreads = 256;
-constexpr int kAcaWaves = kAcaThreads / 64;
 
 template <typename T, int Q>
 __device__ void aca_wave(const AcaArgs<T>& A, int b) {
@@ -330,7 +354,7 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   const Cluster tau = A.cl[ts.x], sig = A.cl[ts.y];
   const int r0 = tau.x, m = tau.y - tau.x, c0 = sig.x, n = sig.y - sig.x;
   const int kcap = min(A.kmax, min(m, n));
-  T* U = A.pool + (A.slot[b] - A.slot0);
+  T* U = reinterpret_cast<T*>((uintptr_t)A.slot[b].ptr);
   T* V = U + (int64_t)kcap * m;
   const Geom<T>& g = A.g;
   bool hr[Q], hc[Q], used[Q];
@@ -534,7 +558,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
   const Cluster tau = A.cl[ts.x], sig = A.cl[ts.y];
   const int r0 = tau.x, m = tau.y - tau.x, c0 = sig.x, n = sig.y - sig.x;
   const int kcap = min(A.kmax, min(m, n));
-  T* U = A.pool + (A.slot[b] - A.slot0);
+  T* U = reinterpret_cast<T*>((uintptr_t)A.slot[b].ptr);
   T* V = U + (int64_t)kcap * m;
   uint8_t* used = reinterpret_cast<uint8_t*>(V + (int64_t)kcap * n);
   const Geom<T>& g = A.g;
@@ -586,9 +610,9 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
     if (tid == 0) used[istar] = 1;
     ++rows_eval;
     ++nused;
-    const int jstar = piv_index(wg_piv<NT>(pv, sh.pv, &sh.pv_out));
+    const int jstar = uni(piv_index(wg_piv<NT>(pv, sh.pv, &sh.pv_out)));
     // every thread may read V[r][j*] now (barriers in wg_piv)
-    const T delta = (jstar >= 0 && jstar < n) ? V[(int64_t)r * n + jstar] : (T)0;
+    const T delta = uni((jstar >= 0 && jstar < n) ? V[(int64_t)r * n + jstar] : (T)0);
     // every thread holds delta before the owner of j* overwrites that entry
     __syncthreads();
     if (delta == (T)0) {
@@ -599,7 +623,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
         const T k = (r > 0) ? (T)fabs(U[(int64_t)(r - 1) * m + i]) : (T)0;
         piv_merge(nx, key_bits(k), ~(unsigned)i);
       }
-      istar = piv_index(wg_piv<NT>(nx, sh.pv, &sh.pv_out));
+      istar = uni(piv_index(wg_piv<NT>(nx, sh.pv, &sh.pv_out)));
       if (istar < 0 || istar >= m) break;
       continue;
     }
@@ -714,10 +738,10 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
       sh.pv_out = best;
     }
     __syncthreads();
-    uu = sh.out[0];
-    vv = sh.out[1];
-    const double cross = sh.out[2];
-    const int inext = piv_index(sh.pv_out);
+    uu = uni(sh.out[0]);
+    vv = uni(sh.out[1]);
+    const double cross = uni(sh.out[2]);
+    const int inext = uni(piv_index(sh.pv_out));
     __syncthreads();
     s2 += 2.0 * cross + uu * vv;
     ++r;
@@ -736,40 +760,61 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
   }
 }
 
-// Classes 0 (NT = 1024) and 1 (NT = 256): one block per workgroup.
+// The batched ACA (Sec. 3.1, "Batching"): every class is one persistent
+// launch over a work queue of its blocks, largest first, so that blocks of
+// uneven size and rank are taken up by whichever workgroup or wavefront is
+// free (the load imbalance of fixed assignments).  A workgroup or wavefront
+// leaves when the queue position passes the last block.
+//
+// Classes 0 (NT = 1,024) and 1 (NT = 256): one block per workgroup.  One
+// latch, no early continue: every block ends at the barrier below, so the
+// thread that fetches the next position has finished the current block (its
+// result stores included) before any thread reads the next position.
 template <typename T, int NT, int CLS>
 __global__ __launch_bounds__(NT, NT == 256 ? 4 : 1) void k_aca_wg(AcaArgs<T> A) {
   __shared__ AcaShared<T, NT> sh;
-  for (int64_t t = blockIdx.x; t < A.cnt[CLS]; t += gridDim.x) {
-    aca_wg<T, NT>(A, A.list[CLS][t], sh);
+  __shared__ int item_sh;
+  while (true) {
+    if (threadIdx.x == 0) item_sh = atomicAdd(A.head + CLS, 1);
+    __syncthreads();
+    const int64_t it = uni(item_sh);
+    if (it >= A.cnt[CLS]) break;
+    aca_wg<T, NT>(A, A.list[CLS][it], sh);
     __syncthreads();
   }
 }
 
-// Classes 2..4: one block per wavefront, four per workgroup.
+// Classes 2..4: one block per wavefront; every wavefront takes its own
+// blocks from the queue, NB consecutive (similar) blocks per fetch for the
+// small classes, which have millions of blocks (no barriers).
 template <typename T, int Q>
 __global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_aca_wave(AcaArgs<T> A) {
   constexpr int c = Q == 4 ? 2 : (Q == 2 ? 3 : 4);
-  // wave-uniform: the block's descriptors come in by scalar loads
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t ng = (A.cnt[c] + kAcaWaves - 1) / kAcaWaves;
-  for (int64_t t = blockIdx.x; t < ng; t += gridDim.x) {
-    const int64_t k = t * kAcaWaves + wave;
-    if (k < A.cnt[c]) aca_wave<T, Q>(A, A.list[c][k]);
+  constexpr int NB = Q == 4 ? 1 : (Q == 2 ? 2 : 4);
+  const int lane = threadIdx.x & 63;
+  const int64_t cnt = A.cnt[c];
+  while (true) {
+    int it = 0;
+    if (lane == 0) it = atomicAdd(A.head + c, NB);
+    it = uni(it);
+    if (it >= cnt) break;
+    const int64_t end = std::min<int64_t>(it + NB, cnt);
+    for (int64_t k = it; k < end; ++k) aca_wave<T, Q>(A, A.list[c][k]);
   }
 }
 
-// Class of every block: 0 1024-thread workgroup (max(m, n) > kAcaBig),
-// 1 256-thread workgroup (> 256), 2 wavefront with Q = 4, 3 with Q = 2,
-// 4 with Q = 1; flags[c * nb + b] = (class == c).
+// Class of every block (see kAcaClasses).  With mask, only blocks whose
+// mask entry is set get a class.  flags[c * nb + b] = (class == c).
 __global__ void k_aca_classes(const int2* __restrict__ blk, int64_t nb,
-                              const Cluster* __restrict__ cl, int64_t* __restrict__ flags) {
+                              const Cluster* __restrict__ cl, const int64_t* __restrict__ mask,
+                              int64_t* __restrict__ flags) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
     const Cluster t = cl[ts.x], s = cl[ts.y];
     const int64_t mx = max(t.y - t.x, s.y - s.x);
-    const int c = mx > kAcaBig ? 0 : (mx > 256 ? 1 : (mx > 128 ? 2 : (mx > 64 ? 3 : 4)));
+    int c = mx > kAcaBig ? 0 : (mx > 256 ? 1 : (mx > 128 ? 2 : (mx > 64 ? 3 : 4)));
+    if (mask && !mask[b]) c = -1;
 #pragma unroll
     for (int k = 0; k < kAcaClasses; ++k) flags[k * nb + b] = (k == c) ? 1 : 0;
   }
@@ -908,8 +953,7 @@ __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx
                                                 const int2* __restrict__ blk,
                                                 const Cluster* __restrict__ cl, LeafTab L,
                                                 const int32_t* __restrict__ rank,
-                                                const int64_t* __restrict__ slot, int64_t slot0,
-                                                const T* __restrict__ pool,
+                                                const AcaSlot* __restrict__ slot,
                                                 const int64_t* __restrict__ offI,
                                                 const float* __restrict__ su,
                                                 const int64_t* __restrict__ toff, int64_t tbase,
@@ -924,7 +968,7 @@ __global__ __launch_bounds__(256) void k_pack_u(const int32_t* __restrict__ sidx
     const int2 ts = blk[b];
     const Cluster tau = cl[ts.x];
     const int m = tau.y - tau.x, r = rank[b];
-    const T* U = pool + (slot[b] - slot0);
+    const T* U = reinterpret_cast<const T*>((uintptr_t)slot[b].ptr);
     const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - tau.x;
     TL* d = arena + offI[p];
     const int tot = ld * r;
@@ -955,8 +999,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_u_scales(const int2* __restrict__ blk, int64_t nb,
                                                   const Cluster* __restrict__ cl,
                                                   const int32_t* __restrict__ rank,
-                                                  const int64_t* __restrict__ slot, int64_t slot0,
-                                                  const T* __restrict__ pool,
+                                                  const AcaSlot* __restrict__ slot,
                                                   const int64_t* __restrict__ toff, int64_t tbase,
                                                   float* __restrict__ su) {
   const int lane = threadIdx.x & 63;
@@ -964,7 +1007,7 @@ __global__ __launch_bounds__(256) void k_u_scales(const int2* __restrict__ blk, 
   for (int64_t b = blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += nw) {
     const Cluster tau = cl[blk[b].x];
     const int m = tau.y - tau.x, r = rank[b];
-    const T* U = pool + (slot[b] - slot0);
+    const T* U = reinterpret_cast<const T*>((uintptr_t)slot[b].ptr);
     for (int l = 0; l < r; ++l) {
       float mx = 0.f;
       for (int i = lane; i < m; i += 64) mx = fmaxf(mx, fabsf((float)U[(int64_t)l * m + i]));
@@ -981,8 +1024,7 @@ template <typename T, typename TL>
 __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, int64_t nb,
                                                 const Cluster* __restrict__ cl, LeafTab L,
                                                 const int32_t* __restrict__ rank,
-                                                const int64_t* __restrict__ slot, int64_t slot0,
-                                                const T* __restrict__ pool, int kmax,
+                                                const AcaSlot* __restrict__ slot,
                                                 const int64_t* __restrict__ voff,
                                                 TL* __restrict__ varena,
                                                 uint64_t* __restrict__ vptr) {
@@ -993,8 +1035,7 @@ __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, in
     const int2 ts = blk[b];
     const Cluster tau = cl[ts.x], sig = cl[ts.y];
     const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
-    const int kcap = min(kmax, min(m, n));
-    const T* Vw = pool + (slot[b] - slot0) + (int64_t)kcap * m;
+    const T* Vw = reinterpret_cast<const T*>((uintptr_t)slot[b].ptr) + (int64_t)slot[b].kc * m;
     TL* dst = varena + voff[b];
     if (lane == 0) vptr[b] = (uint64_t)(uintptr_t)dst;
     const int2 ls = L.cl_leaves[ts.y];
@@ -1204,13 +1245,18 @@ __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* 
 }
 
 // ------------------------------------------------------------------ ACA launchers
-// Runs the batched ACA on the blocks blk[0..nb): classes, task lists, one
-// launch.  flags, offs: 4 * nb int64 scratch; lists: 4 * nb int32 scratch.
+// The batched ACA over the blocks of a chunk (with mask: only the marked
+// ones) at rank cap kmax: class lists, then one queue launch per class,
+// largest class first.  flags, offs: kAcaClasses * nb int64 scratch; lists:
+// kAcaClasses * nb int32; head: kAcaClasses int.
 template <typename T>
-void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl, const int64_t* slot,
-             int64_t slot0, T* pool, int kmax, double eps, int64_t* flags, int64_t* offs,
-             int32_t* lists, int32_t* rank, int32_t* info, int64_t* tmp, hipStream_t s) {
-  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, flags);
+void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
+             const AcaSlot* slot, int kmax, double eps, const int64_t* mask, int64_t* flags,
+             int64_t* offs, int32_t* lists, int* head, int32_t* rank, int32_t* info,
+             int64_t* tmp, hipStream_t s) {
+  if (nb == 0) return;
+  if (nb >= INT32_MAX) throw Error{HM_ERR_STATE, "ACA chunk of more than 2^31 blocks"};
+  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, mask, flags);
   HM_LAUNCH_CHECK();
   for (int k = 0; k < kAcaClasses; ++k)
     scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
@@ -1219,34 +1265,53 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl, c
   HM_HIP(hipStreamSynchronize(s));
   k_split_lists<<<grid_for(nb, 256), 256, 0, s>>>(flags, offs, nb, lists);
   HM_LAUNCH_CHECK();
-  AcaArgs<T> A{g, blk, cl, slot, slot0, pool, {}, {}, kmax, eps, rank, info};
+  AcaArgs<T> A{};
+  A.g = g;
+  A.blk = blk;
+  A.cl = cl;
+  A.slot = slot;
   for (int k = 0; k < kAcaClasses; ++k) {
     A.list[k] = lists + k * nb;
     A.cnt[k] = cnt[k];
   }
+  A.head = head;
+  A.kmax = kmax;
+  A.eps = eps;
+  A.rank = rank;
+  A.info = info;
+  HM_HIP(hipMemsetAsync(head, 0, kAcaClasses * sizeof(int), s));
   int dev = 0, ncu = 0;
   HM_HIP(hipGetDevice(&dev));
   HM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t cap = (int64_t)std::max(ncu, 1) * 32;
-  // largest blocks first: one workgroup each, then the wavefront classes
+  ncu = std::max(ncu, 1);
+  // grid: as many workgroups as can be resident at once (the queue does the
+  // rest), never more than the class has work for
+  auto grid = [&](const void* k, int threads, int64_t work) {
+    int per_cu = 0;
+    HM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)ncu * std::max(per_cu, 1)));
+  };
   if (cnt[0] > 0) {
-    k_aca_wg<T, 1024, 0><<<(unsigned)std::min<int64_t>(cnt[0], cap), 1024, 0, s>>>(A);
+    k_aca_wg<T, 1024, 0><<<grid((const void*)k_aca_wg<T, 1024, 0>, 1024, cnt[0]), 1024, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[1] > 0) {
-    k_aca_wg<T, 256, 1><<<(unsigned)std::min<int64_t>(cnt[1], cap), 256, 0, s>>>(A);
+    k_aca_wg<T, 256, 1><<<grid((const void*)k_aca_wg<T, 256, 1>, 256, cnt[1]), 256, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[2] > 0) {
-    k_aca_wave<T, 4><<<(unsigned)std::min<int64_t>(ceil_div(cnt[2], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wave<T, 4><<<grid((const void*)k_aca_wave<T, 4>, kAcaThreads, ceil_div(cnt[2], kAcaWaves)),
+                       kAcaThreads, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[3] > 0) {
-    k_aca_wave<T, 2><<<(unsigned)std::min<int64_t>(ceil_div(cnt[3], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wave<T, 2><<<grid((const void*)k_aca_wave<T, 2>, kAcaThreads, ceil_div(cnt[3], 2 * kAcaWaves)),
+                       kAcaThreads, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
   if (cnt[4] > 0) {
-    k_aca_wave<T, 1><<<(unsigned)std::min<int64_t>(ceil_div(cnt[4], kAcaWaves), cap), kAcaThreads, 0, s>>>(A);
+    k_aca_wave<T, 1><<<grid((const void*)k_aca_wave<T, 1>, kAcaThreads, ceil_div(cnt[4], 4 * kAcaWaves)),
+                       kAcaThreads, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
 }
@@ -1262,7 +1327,15 @@ __global__ void k_term_caps(const int2* __restrict__ blk, int64_t nb, const Clus
   }
 }
 
-// Working-slot sizes of all blocks (the class flags are recomputed per chunk).
+// Elements of a working slot at rank cap kcap: U (m x kcap) and V
+// (n x kcap), then m bytes of used-row flags, rounded up to 4 elements.
+template <typename T>
+__device__ inline int64_t slot_elems(int64_t m, int64_t n, int kcap) {
+  const int64_t flag_elems = (m + (int64_t)sizeof(T) - 1) / (int64_t)sizeof(T);
+  return (((int64_t)kcap * (m + n) + flag_elems) + 3) & ~(int64_t)3;
+}
+
+// Working-slot sizes (elements) of all blocks at rank cap kmax.
 template <typename T>
 __global__ void k_slot_sizes(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
                              int kmax, int64_t* __restrict__ slot) {
@@ -1271,9 +1344,45 @@ __global__ void k_slot_sizes(const int2* __restrict__ blk, int64_t nb, const Clu
     const int2 ts = blk[b];
     const Cluster t = cl[ts.x], s = cl[ts.y];
     const int64_t m = t.y - t.x, n = s.y - s.x;
-    const int64_t kcap = min((int64_t)kmax, min(m, n));
-    const int64_t flag_elems = (m + (int64_t)sizeof(T) - 1) / (int64_t)sizeof(T);
-    slot[b] = ((kcap * (m + n) + flag_elems) + 3) & ~(int64_t)3;
+    slot[b] = slot_elems<T>(m, n, (int)min((int64_t)kmax, min(m, n)));
+  }
+}
+
+// Slot descriptors of a chunk's blocks: pool + (off[b] - off0) and the rank
+// cap kmax of the pass.  With mask, only the marked blocks are written.
+template <typename T>
+__global__ void k_slot_desc(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
+                            int kmax, const int64_t* __restrict__ off, int64_t off0, T* pool,
+                            const int64_t* __restrict__ mask, AcaSlot* __restrict__ desc) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    if (mask && !mask[b]) continue;
+    const int2 ts = blk[b];
+    const Cluster t = cl[ts.x], s = cl[ts.y];
+    const int kcap = min(kmax, min(t.y - t.x, s.y - s.x));
+    AcaSlot d;
+    d.ptr = (uint64_t)(uintptr_t)(pool + (off[b] - off0));
+    d.kc = kcap;
+    d.pad = 0;
+    desc[b] = d;
+  }
+}
+
+// Blocks of the first pass that stopped at its rank cap k1 although the full
+// cap allows more terms: mark[b] = 1 and their slot size at the full cap.
+template <typename T>
+__global__ void k_rerun_marks(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
+                              const int32_t* __restrict__ info, int k1, int kmax,
+                              int64_t* __restrict__ mark, int64_t* __restrict__ size) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = blk[b];
+    const Cluster t = cl[ts.x], s = cl[ts.y];
+    const int64_t m = t.y - t.x, n = s.y - s.x;
+    const int full = (int)min((int64_t)kmax, min(m, n));
+    const bool again = (info[b] & 1) && k1 < full;
+    mark[b] = again ? 1 : 0;
+    size[b] = again ? slot_elems<T>(m, n, full) : 0;
   }
 }
 
@@ -1509,9 +1618,12 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   double ms_pack = 0;
   if (nl > 0) {
     Temps ta{s, {}};
+    // first pass at the rank cap k1 (slots sized for it); blocks that stop
+    // at k1 although kmax allows more are run again with full-size slots
+    const int k1 = std::min(kmax, kAcaFirstRank);
     int64_t* slot = ta.get<int64_t>(nl);
     int64_t* slot_off = ta.get<int64_t>(nl + 1);
-    k_slot_sizes<T><<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl, kmax, slot);
+    k_slot_sizes<T><<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl, k1, slot);
     HM_LAUNCH_CHECK();
     scan_excl_i64(slot, slot_off, nl, slot_off + nl, s);
     // all slots at once when they fit the budget; otherwise chunks of
@@ -1554,14 +1666,38 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     int64_t* voff = ta.get<int64_t>(nl + 1);
     uint64_t* vptr = ta.get<uint64_t>(nl);
     int64_t* oU = ta.get<int64_t>(nl + 1);
+    AcaSlot* desc = ta.get<AcaSlot>(nl);
+    int64_t* rmark = ta.get<int64_t>(nl);
+    int64_t* rsize = ta.get<int64_t>(nl);
+    int64_t* roff = ta.get<int64_t>(nl + 1);
+    int* head = ta.get<int>(kAcaClasses);
     int64_t b0 = 0;
     while (b0 < nl) {
       int64_t b1 = hoff.empty() ? nl : b0 + 1;
       while (b1 < nl && hoff[b1 + 1] - hoff[b0] <= pool_elems) ++b1;
       const int64_t slot0 = slot_at(b0);
       const int64_t nb = b1 - b0;
-      run_aca<T>(g, in.lr + b0, nb, in.cl, slot_off + b0, slot0, pool, kmax, in.eps, cflags,
-                 coffs, clists, out.rank + b0, out.info + b0, tmp, s);
+      k_slot_desc<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, k1, slot_off + b0,
+                                                       slot0, pool, nullptr, desc + b0);
+      HM_LAUNCH_CHECK();
+      run_aca<T>(g, in.lr + b0, nb, in.cl, desc + b0, k1, in.eps, nullptr, cflags, coffs, clists,
+                 head, out.rank + b0, out.info + b0, tmp, s);
+      T* pool2 = nullptr;
+      if (k1 < kmax) {
+        k_rerun_marks<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, out.info + b0,
+                                                           k1, kmax, rmark, rsize);
+        HM_LAUNCH_CHECK();
+        const int64_t elems2 = scan_total(rsize, roff, nb, tmp, s);
+        if (elems2 > 0) {
+          pool2 = static_cast<T*>(dalloc((size_t)elems2 * esize, s));
+          k_slot_desc<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, kmax, roff, 0,
+                                                           pool2, rmark, desc + b0);
+          HM_LAUNCH_CHECK();
+          run_aca<T>(g, in.lr + b0, nb, in.cl, desc + b0, kmax, in.eps, rmark, cflags, coffs,
+                     clists, head, out.rank + b0, out.info + b0, tmp, s);
+          ++out.aca_reruns;
+        }
+      }
       HM_HIP(hipStreamSynchronize(s));
       const auto tp = clk::now();
       // term offsets in t
@@ -1573,9 +1709,9 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       HM_LAUNCH_CHECK();
       const int64_t velems = scan_total(vsz, voff, nb, tmp, s);
       TL* varena = static_cast<TL*>(alloc((size_t)velems * lsize));
-      k_pack_v<T, TL><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L, out.rank + b0,
-                                                          slot_off + b0, slot0, pool, kmax, voff,
-                                                          varena, vptr);
+      k_pack_v<T, TL><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L,
+                                                               out.rank + b0, desc + b0, voff,
+                                                               varena, vptr);
       HM_LAUNCH_CHECK();
       k_lr_meta<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, in.ldpre,
                                                   out.rank + b0, toffc, toff_base, vptr, ub + b0,
@@ -1589,14 +1725,13 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       TL* uarena = static_cast<TL*>(alloc((size_t)PU.elems * lsize));
       if (scaled && nb > 0) {
         k_u_scales<T><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(
-            in.lr + b0, nb, in.cl, out.rank + b0, slot_off + b0, slot0, pool, toffc,
-            toff_base, out.su);
+            in.lr + b0, nb, in.cl, out.rank + b0, desc + b0, toffc, toff_base, out.su);
         HM_LAUNCH_CHECK();
       }
       if (PU.np > 0) {
         k_pack_u<T, TL><<<grid_for(PU.np, 4, 1 << 20), 256, 0, s>>>(
-            PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0, in.cl, L, out.rank + b0, slot_off + b0,
-            slot0, pool, PU.offI, scaled ? out.su : nullptr, toffc, toff_base, uarena);
+            PU.sidx, PU.ib, PU.ilf, PU.np, in.lr + b0, in.cl, L, out.rank + b0, desc + b0,
+            PU.offI, scaled ? out.su : nullptr, toffc, toff_base, uarena);
         HM_LAUNCH_CHECK();
       }
       const int64_t colbase = out.dense_cols + ucols;
@@ -1617,6 +1752,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       HM_LAUNCH_CHECK();
       HM_HIP(hipStreamSynchronize(s));
       tu.release();
+      if (pool2) dfree(pool2, s);
       ms_pack += ms_since(tp);
       toff_base += terms;
       ucols += PU.cols;
