@@ -19,6 +19,12 @@ Modules
               boxes and admissibility (Sec. 2.3, eq. admissibilityCondition),
               block cluster tree (Sec. 2.3, Algorithm 1).
   aca         Adaptive cross approximation with partial pivoting (Sec. 2.3).
+  galerkin    The paper's own Galerkin discretisation (Sec. 2.2, eq.
+              linearSystem) with piecewise constants: 7 x 7 rule for pairs
+              that share no vertex, outer Gauss rule with the inner integral
+              in closed form (the Duffy / polar split, Sec. 4.1) for
+              touching pairs; right-hand sides; the potential for the
+              interior error eps(h) of Sec. 4.3.
   sphere      Closed forms on the unit sphere used as pins.
 
 Parity unpinned: the exact discretisation-error values at each refinement

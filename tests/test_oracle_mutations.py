@@ -7,8 +7,9 @@ import pytest
 
 import test_oracle_aca as pins_aca
 import test_oracle_cluster as pins_cluster
+import test_oracle_galerkin as pins_galerkin
 import test_oracle_quadrature as pins_quad
-from oracle import aca, bem, cluster, quadrature
+from oracle import aca, bem, cluster, galerkin, quadrature
 
 
 def _fails(fn, *args):
@@ -89,3 +90,23 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_galerkin_dropped_height_terms_are_caught(monkeypatch):
+    """The off-plane part of the closed-form inner integral left out."""
+    monkeypatch.setattr(galerkin, "_height_terms", lambda ad, h, la, lb, ra, rb: 0.0 * ad)
+    _fails(pins_galerkin.test_inner_integral_off_plane_matches_brute_force)
+
+
+def test_galerkin_unsigned_sub_triangles_are_caught(monkeypatch):
+    """Every sub-triangle counted positive (a point beyond an edge then
+    over-counts): an in-plane point outside T and the touching pairs."""
+    monkeypatch.setattr(galerkin, "_signed", lambda cr, val: val)
+    _fails(pins_galerkin.test_inner_integral_off_plane_matches_brute_force)
+
+
+def test_galerkin_dropped_four_pi_is_caught(monkeypatch, ico):
+    monkeypatch.setattr(galerkin, "FOUR_PI", 1.0)
+    # both rules scale alike (their comparison cannot see it); the harmonic
+    # test on the sphere does
+    _fails(pins_galerkin.test_interior_error_third_order_on_the_unit_sphere, ico)
