@@ -83,13 +83,29 @@ typedef enum {
                              each column-unit width of its schedule
                              (512 .. 8192) on its own storage and keeps the
                              fastest; measurements via HM_Q_TUNE             */
+#define HM_GALERKIN 8     /* the Galerkin matrix of Sec. 2.2 (eq.
+                             linearSystem) with piecewise constants instead
+                             of collocation at the centroids:
+                             a_ij = int_Ti int_Tj 1/(4 pi |x - y|), Radon's
+                             seven-point rule on both triangles for pairs
+                             that share no vertex; for identical triangles
+                             and triangles that share an edge or a vertex
+                             (Sec. 4.1: higher-order quadrature and the
+                             Duffy trick) a 12 x 12 Gauss rule on T_i in
+                             collapsed coordinates with the inner integral
+                             over T_j in closed form, in double.  The right
+                             side is f_i = int_Ti f; the matrix is symmetric
+                             up to quadrature error, so HM_SOLVE_CG applies.
+                             Needs the vertex indices to be shared between
+                             neighbouring triangles (a conforming mesh)   */
 
 typedef struct {
   int32_t leaf_size;        /* C_leaf of (C3); 1..64.  Paper: 32             */
   int32_t max_rank;         /* ACA rank cap k_max; 1..256; 0 => 64.  The cap
                                is also limited by min(m, n) of each block     */
   int32_t precision;        /* hm_precision                                   */
-  int32_t flags;            /* HM_STRICT | HM_PROFILE | HM_AUTOTUNE           */
+  int32_t flags;            /* HM_STRICT | HM_PROFILE | HM_AUTOTUNE |
+                               HM_GALERKIN                                    */
   double eta;               /* admissibility parameter eta >= 0.  Paper: 1.0 */
   double aca_eps;           /* relative Frobenius stopping tolerance of ACA;
                                0 => fixed-rank mode (every block gets
@@ -102,8 +118,9 @@ typedef struct {
 hm_status hm_params_default(hm_params* p);
 
 /*
- * hm_build -- set up the H-matrix of the collocation operator of one mesh
- * (Sec. 2.3 and Sec. 3; Algorithm 1).
+ * hm_build -- set up the H-matrix of the collocation operator (or, with
+ * HM_GALERKIN, of the Galerkin matrix) of one mesh (Sec. 2.3 and Sec. 3;
+ * Algorithm 1).
  *   vertices   host, double[n_vertices][3]
  *   triangles  host, int32[n_triangles][3], vertex indices in [0, n_vertices);
  *              every triangle must have positive area
@@ -181,7 +198,7 @@ typedef struct {
                           with refine), >= 1                                */
   int32_t transpose;   /* 1: solve H^T s = f (adjoint), 0: H s = f          */
   int32_t use_x0;      /* 1: sigma holds the initial guess on entry         */
-  int32_t flags;       /* HM_SOLVE_GRAPH or 0                               */
+  int32_t flags;       /* HM_SOLVE_GRAPH, HM_SOLVE_CG or 0                  */
   int32_t refine;      /* 0: GMRES with double products throughout;
                           1: iterative refinement -- residual f - H s in
                           double (vectors and accumulation), correction by
@@ -199,6 +216,16 @@ typedef struct {
    restart, direction or refine mode, or hm_free.  Results are bitwise those
    of flags = 0. */
 #define HM_SOLVE_GRAPH 1
+/* hm_solve_params.flags: conjugate gradients instead of GMRES, the solver of
+   Sec. 4.1 for the symmetric positive definite Galerkin system (HM_GALERKIN
+   handles; on a collocation handle CG is not guaranteed to converge).  One
+   product per step, every right-hand side with its own step lengths, vectors
+   and recurrences in double; stops when the recursively updated residual
+   reaches tol relative to |f|, then checks the explicit residual (a column
+   whose explicit residual misses tol is reported not converged).  restart is
+   ignored; max_iter bounds the steps.  Not combined with HM_SOLVE_GRAPH,
+   refine = 1 or transpose = 1 (HM_ERR_ARG). */
+#define HM_SOLVE_CG 2
 
 typedef struct {
   int32_t iters;          /* Arnoldi steps taken (max over right-hand sides;
@@ -213,8 +240,10 @@ typedef struct {
 /*
  * hm_solve -- solve H s = f (or H^T s = f) for the density s.  The paper
  * solves its symmetric Galerkin system by CG with one H-matrix product per
- * step, stopped at a relative residual of 1e-8 (Sec. 4.1); the collocation
- * matrix is not symmetric, so this is restarted GMRES with the same product:
+ * step, stopped at a relative residual of 1e-8 (Sec. 4.1): HM_SOLVE_CG
+ * (info->restarts then counts the explicit-residual cycles).  The
+ * collocation matrix is not symmetric, so the default is restarted GMRES
+ * with the same product:
  * x0 = 0 unless use_x0, Arnoldi basis in double with classical Gram-Schmidt
  * applied twice, Givens rotations on the host; the residual is recomputed
  * explicitly at every restart and at the end.  With refine = 1 the solve is
@@ -342,9 +371,11 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes,
 
 /*
  * hm_entries -- evaluate matrix entries a(rows[k], cols[k]) (application
- * indices) on the device with the build's entry kernel and precision; the
- * result is written to out[k] as double.  rows, cols, out: host arrays of
- * length count.  Used to check the quadrature against the oracle.
+ * indices) on the device with the build's entry kernel and precision (the
+ * collocation entries, or with HM_GALERKIN the Galerkin entries, singular
+ * pairs included); the result is written to out[k] as double.  rows, cols,
+ * out: host arrays of length count.  Used to check the quadrature against
+ * the oracle.
  */
 hm_status hm_entries(hm_handle* h, const int32_t* rows, const int32_t* cols,
                      int64_t count, double* out);

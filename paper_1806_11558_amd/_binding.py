@@ -12,9 +12,11 @@ HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_OOM, HM_ERR_HIP, HM_ERR_ACA, HM_ERR_STATE = -1, -2, -3, -4, -5
 HM_F64, HM_F32, HM_F32_F16 = 0, 1, 2
 HM_SOLVE_GRAPH = 1
+HM_SOLVE_CG = 2
 HM_AUTOTUNE = 4
 HM_STRICT = 1
 HM_PROFILE = 2
+HM_GALERKIN = 8
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
  HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES,
  HM_Q_TUNE, HM_Q_DENSE_ENTRIES) = range(13)
@@ -263,9 +265,11 @@ class HMatrix:
     def __init__(self, vertices, triangles, *, leaf_size: int = 32, eta: float = 1.0,
                  eps: float = 1e-6, max_rank: int = 64, precision: str = "f64",
                  strict: bool = False, profile: bool = False, mem_limit_bytes: int = 0,
-                 autotune: bool = False, stream=None):
+                 autotune: bool = False, operator: str = "collocation", stream=None):
+        """operator: "collocation" (centroid collocation) or "galerkin"
+        (HM_GALERKIN: the Galerkin matrix with piecewise constants)."""
         p = self._params(leaf_size, eta, eps, max_rank, precision, strict, profile,
-                         mem_limit_bytes, autotune)
+                         mem_limit_bytes, autotune, operator)
         self.n = int(np.asarray(triangles).shape[0])
         self.offsets = np.array([0, self.n], dtype=np.int64)
         self._h = hm_build(vertices, triangles, p, stream)
@@ -274,12 +278,12 @@ class HMatrix:
     def batch(cls, meshes, *, leaf_size: int = 32, eta: float = 1.0, eps: float = 1e-6,
               max_rank: int = 64, precision: str = "f64", strict: bool = False,
               profile: bool = False, mem_limit_bytes: int = 0, autotune: bool = False,
-              stream=None):
+              operator: str = "collocation", stream=None):
         """One handle for several meshes [(vertices, triangles), ...]
         (hm_build_batch); unknowns are the triangles in concatenated order."""
         self = cls.__new__(cls)
         p = self._params(leaf_size, eta, eps, max_rank, precision, strict, profile,
-                         mem_limit_bytes, autotune)
+                         mem_limit_bytes, autotune, operator)
         sizes = [int(np.asarray(t).shape[0]) for _, t in meshes]
         self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         self.n = int(self.offsets[-1])
@@ -287,7 +291,9 @@ class HMatrix:
         return self
 
     def _params(self, leaf_size, eta, eps, max_rank, precision, strict, profile, mem_limit_bytes,
-                autotune=False):
+                autotune=False, operator="collocation"):
+        if operator not in ("collocation", "galerkin"):
+            raise HMError(HM_ERR_ARG, f"unknown operator {operator!r}")
         p = hm_params_default()
         p.leaf_size = leaf_size
         p.eta = eta
@@ -295,7 +301,9 @@ class HMatrix:
         p.max_rank = max_rank
         p.precision = {"f64": HM_F64, "f32": HM_F32, "f16": HM_F32_F16}[precision]
         p.flags = ((HM_STRICT if strict else 0) | (HM_PROFILE if profile else 0)
-                   | (HM_AUTOTUNE if autotune else 0))
+                   | (HM_AUTOTUNE if autotune else 0)
+                   | (HM_GALERKIN if operator == "galerkin" else 0))
+        self.operator = operator
         p.mem_limit_bytes = mem_limit_bytes
         self.params = p
         self.storage_dtype = np.float64 if precision == "f64" else np.float32
@@ -320,16 +328,21 @@ class HMatrix:
 
     def solve(self, f, *, tol: float = 1e-8, restart: int = 100, max_iter: int = 1000,
               transpose: bool = False, x0=None, graph: bool = False, refine: bool = False,
-              inner_tol: float = 0.0, stream=None):
+              inner_tol: float = 0.0, method: str = "gmres", stream=None):
         """GMRES on H s = f (hm_solve); with refine=True iterative refinement
-        around an inner GMRES with float products to inner_tol.  Returns
+        around an inner GMRES with float products to inner_tol; method="cg"
+        for conjugate gradients (HM_SOLVE_CG, the Galerkin system).  Returns
         (sigma, info, status); status HM_NOT_CONVERGED is returned, not
         raised."""
+        if method not in ("gmres", "cg"):
+            raise HMError(HM_ERR_ARG, f"unknown method {method!r}")
         import torch
         self._rows(f)
         sp = SolveParams(tol=tol, restart=restart, max_iter=max_iter,
                          transpose=1 if transpose else 0, use_x0=0 if x0 is None else 1,
-                         flags=HM_SOLVE_GRAPH if graph else 0, refine=1 if refine else 0,
+                         flags=(HM_SOLVE_GRAPH if graph else 0)
+                         | (HM_SOLVE_CG if method == "cg" else 0),
+                         refine=1 if refine else 0,
                          inner_tol=inner_tol)
         sigma = torch.empty_like(f) if x0 is None else x0.clone()
         st, info = hm_solve(self._h, f, sigma, sp, stream)

@@ -35,11 +35,13 @@ void launch_leaf_table(const Cluster* cl, int64_t ncl, const int32_t* pos_leaf, 
 void launch_boxes(const Cluster* cl, const std::vector<int64_t>& level_beg, const int32_t* leaf_cl,
                   int64_t nleaf, const double* c, int64_t n, double* box, hipStream_t s);
 void build_block_tree(const Cluster* cl, int64_t nroots, const double* box, double eta, int leaf,
-                      int2** adm_out, int64_t* nadm, int2** dns_out, int64_t* ndns,
-                      int64_t* depth, hipStream_t s);
+                      const GalTouch& gt, int2** adm_out, int64_t* nadm, int2** dns_out,
+                      int64_t* ndns, int64_t* depth, hipStream_t s);
 template <typename T>
-void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
-                    int64_t cnt, double* out, hipStream_t s);
+void launch_entries(const Geom<T>& g, int op, const int32_t* inv, const int32_t* rows,
+                    const int32_t* cols, int64_t cnt, double* out, hipStream_t s);
+void launch_tri_sorted(const double* V, const int32_t* Tri, const int32_t* perm, int64_t n,
+                       double* v, int32_t* vid, hipStream_t s);
 void launch_inverse_perm(const int32_t* perm, int64_t n, int32_t* inv, hipStream_t s);
 
 int gmres_tiles(int64_t n);
@@ -121,6 +123,10 @@ struct SolveWs {
 void convert_f32_to_f64(const float* a, int64_t tot, double* out, hipStream_t s);
 void convert_f64_to_f32(const double* a, int64_t tot, float* out, hipStream_t s);
 void gmres_add(const double* a, const double* b, int64_t tot, double* out, hipStream_t s);
+void cg_update(double* x, double* r, const double* p, const double* q, const double* rr,
+               const double* pq, const double* active, int64_t n, int nr, hipStream_t s);
+void cg_dir(double* p, const double* r, const double* rr_new, const double* rr_old,
+            const double* active, int64_t n, int nr, hipStream_t s);
 void gmres_copy_col_f32(const double* Q, int64_t ldq, const int* jd, float* out, hipStream_t s);
 
 // ------------------------------------------------------------------ errors
@@ -210,6 +216,9 @@ struct hm_handle {
   void* o = nullptr;
   void* aw = nullptr;
   void* sf = nullptr;
+  int op = kOpColloc;            // kOpGalerkin with HM_GALERKIN
+  double* tv = nullptr;          // Galerkin: vertices, Morton order [9][n]
+  int32_t* vid = nullptr;        // Galerkin: vertex indices [3][n]
   uint64_t* keys = nullptr;      // Morton keys, application order
   int32_t* perm = nullptr;       // Morton position -> triangle
   int32_t* inv = nullptr;
@@ -444,11 +453,16 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   h->aw = h->alloc(n * sizeof(T));
   h->sf = h->alloc(n * sizeof(T));
   launch_geom_sorted<T>(V, Tri, h->perm, n, h->c, (T*)h->o, (T*)h->aw, (T*)h->sf, s);
+  if (h->op == kOpGalerkin) {
+    h->tv = h->alloc_t<double>(9 * n);
+    h->vid = h->alloc_t<int32_t>(3 * n);
+    launch_tri_sorted(V, Tri, h->perm, n, h->tv, h->vid, s);
+  }
   dfree(V, s);
   dfree(Tri, s);
   HM_HIP(hipStreamSynchronize(s));
   h->ms[1] = ms_since(t0);
-  const Geom<T> g{h->c, (const T*)h->o, (const T*)h->aw, (const T*)h->sf, n};
+  const Geom<T> g{h->c, (const T*)h->o, (const T*)h->aw, (const T*)h->sf, n, h->tv, h->vid};
 
   // ---- cluster tree, leaves, boxes
   t0 = clk::now();
@@ -487,7 +501,11 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
   // ---- block cluster tree (Algorithm 1, level-wise)
   t0 = clk::now();
   int2 *adm = nullptr, *dns = nullptr;
-  build_block_tree(h->cl, G, h->box, p.eta, p.leaf_size, &adm, &h->nl, &dns, &h->nd, &h->depth, s);
+  GalTouch gt;
+  if (h->op == kOpGalerkin) gt = make_gal_touch(h->c, h->tv, h->vid, n, nv, s);
+  build_block_tree(h->cl, G, h->box, p.eta, p.leaf_size, gt, &adm, &h->nl, &dns, &h->nd, &h->depth,
+                   s);
+  free_gal_touch(gt, s);
   h->lr = h->alloc_t<int2>(h->nl);
   h->dns = h->alloc_t<int2>(h->nd);
   if (h->nl) HM_HIP(hipMemcpyAsync(h->lr, adm, h->nl * sizeof(int2), hipMemcpyDeviceToDevice, s));
@@ -509,7 +527,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     if (p.mem_limit_bytes > 0) budget = std::min(budget, (p.mem_limit_bytes - h->bytes) / 3);
     SetupIn in{n, h->cl, h->cl_leaves, h->leaf_lo, h->leaf_m, h->ldpre, h->nleaf,
                h->dns, h->nd, h->lr, h->nl, p.max_rank > 0 ? p.max_rank : 64, p.aca_eps,
-               std::max<int64_t>(budget, 1 << 20)};
+               std::max<int64_t>(budget, 1 << 20), h->op};
     build_storage<T, TL>(g, in, h->sto, [h](size_t b) { return h->alloc(b); }, s);
     h->ms[4] = h->sto.ms_near;
     h->ms[5] = h->sto.ms_aca;
@@ -731,6 +749,84 @@ int gmres_core(SolveWs* ws, int64_t n, int nr, int m, double tol, int max_iter, 
   }
   return total_it;
 }
+
+// Conjugate gradients (Sec. 4.1: the solver of the symmetric Galerkin
+// system, one product per step) for every column of b = ws->fd at once, each
+// with its own step lengths; the iterate ws->x is read as the initial guess
+// and written back.  In cycles: the residual b - H x is computed
+// explicitly, CG runs on the unconverged columns (r in Q, p in Q + nv, H p
+// in w) until their recursively updated residuals reach tol, and the
+// explicit residual decides again; a cycle that improves no unconverged
+// column by 10% ends the solve.  Returns the steps taken; rn receives the
+// explicit residual norms at the end.
+template <typename Apply>
+int cg_core(SolveWs* ws, int64_t n, int nr, double tol, int max_iter, const Apply& apply,
+            const std::vector<double>& fn, std::vector<double>& rn, std::vector<int>& conv,
+            int& cycles, hipStream_t s) {
+  const int64_t nv = n * nr;
+  double *r = ws->Q, *p = ws->Q + nv, *x = ws->x, *q = ws->w, *part = ws->part;
+  double* pq = ws->hdev;
+  double* rra = ws->hdev + nr;
+  double* rrb = ws->hdev + 2 * nr;
+  double* active = ws->scl;
+  auto rel = [&](int c, double v) { return fn[c] > 0 ? v / fn[c] : 0.0; };
+  std::vector<double> rr(nr), act(nr), rprev;
+  // r = b - H x, rra = |r|^2 per column, rn = |r|
+  auto residual = [&]() {
+    apply(x, q);
+    gmres_sub(ws->fd, q, nv, r, s);
+    gmres_dots(r, 0, 1, r, n, nr, part, rra, s);
+    HM_HIP(hipMemcpyAsync(rr.data(), rra, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    rn.resize(nr);
+    for (int c = 0; c < nr; ++c) rn[c] = std::sqrt(std::max(rr[c], 0.0));
+    for (int c = 0; c < nr; ++c) conv[c] = rel(c, rn[c]) <= tol;
+  };
+  residual();
+  int it = 0;
+  while (true) {
+    bool all = true;
+    for (int c = 0; c < nr; ++c) all = all && conv[c];
+    if (all || it >= max_iter) break;
+    if (!rprev.empty()) {
+      bool progress = false;
+      for (int c = 0; c < nr; ++c)
+        if (!conv[c] && rn[c] < 0.9 * rprev[c]) progress = true;
+      if (!progress) break;
+    }
+    rprev = rn;
+    for (int c = 0; c < nr; ++c) act[c] = conv[c] ? 0.0 : 1.0;
+    HM_HIP(hipMemcpyAsync(active, act.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(p, r, nv * sizeof(double), hipMemcpyDeviceToDevice, s));
+    while (it < max_iter) {
+      apply(p, q);
+      gmres_dots(p, 0, 1, q, n, nr, part, pq, s);
+      cg_update(x, r, p, q, rra, pq, active, n, nr, s);
+      gmres_dots(r, 0, 1, r, n, nr, part, rrb, s);
+      HM_HIP(hipMemcpyAsync(rr.data(), rrb, nr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HM_HIP(hipStreamSynchronize(s));
+      ++it;
+      bool any = false, changed = false;
+      for (int c = 0; c < nr; ++c) {
+        if (act[c] == 0.0) continue;
+        if (rel(c, std::sqrt(std::max(rr[c], 0.0))) <= tol || !(rr[c] > 0.0)) {
+          act[c] = 0.0;
+          changed = true;
+        } else {
+          any = true;
+        }
+      }
+      if (!any) break;
+      if (changed)
+        HM_HIP(hipMemcpyAsync(active, act.data(), nr * sizeof(double), hipMemcpyHostToDevice, s));
+      cg_dir(p, r, rrb, rra, active, n, nr, s);
+      std::swap(rra, rrb);
+    }
+    ++cycles;
+    residual();
+  }
+  return it;
+}
 }  // namespace
 
 // ------------------------------------------------------------------ ABI
@@ -762,7 +858,8 @@ hm_status check_params(const hm_params* p, const char* who) {
   if (!(p->aca_eps >= 0.0) || !std::isfinite(p->aca_eps))
     return arg_error(w + ": aca_eps must be finite and >= 0");
   if (p->mem_limit_bytes < 0) return arg_error(w + ": mem_limit_bytes < 0");
-  if (p->flags & ~(HM_STRICT | HM_PROFILE | HM_AUTOTUNE)) return arg_error(w + ": unknown flag");
+  if (p->flags & ~(HM_STRICT | HM_PROFILE | HM_AUTOTUNE | HM_GALERKIN))
+    return arg_error(w + ": unknown flag");
   return HM_OK;
 }
 
@@ -802,6 +899,7 @@ hm_status build_handle(const double* vertices, int64_t n_vertices, const int32_t
     h->form = p->precision;
     h->f32 = (p->precision != HM_F64) ? 1 : 0;
     h->ts = h->f32 ? 4 : 8;
+    h->op = (p->flags & HM_GALERKIN) ? kOpGalerkin : kOpColloc;
     HM_HIP(hipGetDevice(&h->device));
     if (p->flags & HM_PROFILE) {
       for (auto& e : h->prof.ev) HM_HIP(hipEventCreate(&e));
@@ -957,11 +1055,16 @@ static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t 
   if (sp->refine != 0 && sp->refine != 1) return arg_error(who + ": refine must be 0 or 1");
   if (sp->refine && (!(sp->inner_tol >= 0.0) || !(sp->inner_tol < 1.0)))
     return arg_error(who + ": inner_tol must be in [0, 1)");
-  if (sp->flags & ~HM_SOLVE_GRAPH) return arg_error(who + ": unknown flag");
+  if (sp->flags & ~(HM_SOLVE_GRAPH | HM_SOLVE_CG)) return arg_error(who + ": unknown flag");
+  const bool cg = (sp->flags & HM_SOLVE_CG) != 0;
+  if (cg && (sp->flags & HM_SOLVE_GRAPH))
+    return arg_error(who + ": HM_SOLVE_CG does not combine with HM_SOLVE_GRAPH");
+  if (cg && sp->refine) return arg_error(who + ": HM_SOLVE_CG does not combine with refine");
+  if (cg && sp->transpose) return arg_error(who + ": HM_SOLVE_CG does not combine with transpose");
   if (no_alloc) {
     if (sp->flags & HM_SOLVE_GRAPH)
       return arg_error(who + ": HM_SOLVE_GRAPH is not available without allocation");
-    const int mm = sp->restart > 0 ? sp->restart : 100;
+    const int mm = cg ? 1 : (sp->restart > 0 ? sp->restart : 100);
     const size_t need = solve_ws_doubles(h->n, nrhs, mm, sp->refine != 0) * sizeof(double);
     if (need > kScratchBytes)
       return arg_error(who + ": the workspace needs " + std::to_string(need) +
@@ -979,7 +1082,8 @@ static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t 
     const int64_t n = h->n;
     const int nr = nrhs;
     const int64_t nv = n * nr;
-    const int m = sp->restart > 0 ? sp->restart : 100;
+    // CG keeps r and p where GMRES keeps its basis (two vectors)
+    const int m = cg ? 1 : (sp->restart > 0 ? sp->restart : 100);
     const bool tr = sp->transpose != 0;
     const bool refine = sp->refine != 0;
     const double inner_tol = refine ? (sp->inner_tol > 0.0 ? sp->inner_tol : 1e-4) : 0.0;
@@ -1088,7 +1192,9 @@ static hm_status solve_common(hm_handle* h, const void* f, void* sigma, int64_t 
     norms(fsrc, fn);
     auto rel = [&](int c, double r) { return fn[c] > 0 ? r / fn[c] : 0.0; };
     int total_it = 0, restarts = 0, ir_steps = 0;
-    if (!refine) {
+    if (cg) {
+      total_it = cg_core(ws, n, nr, sp->tol, sp->max_iter, apply64, fn, rn, conv, restarts, s);
+    } else if (!refine) {
       total_it = gmres_core(ws, n, nr, m, sp->tol, sp->max_iter, use_graph, apply64, graph_step,
                             fn, rn, conv, restarts, false, s);
     } else {
@@ -1365,11 +1471,13 @@ hm_status hm_entries(hm_handle* h, const int32_t* rows, const int32_t* cols, int
     HM_HIP(hipMemcpyAsync(dr, rows, count * 4, hipMemcpyHostToDevice, s));
     HM_HIP(hipMemcpyAsync(dc, cols, count * 4, hipMemcpyHostToDevice, s));
     if (h->f32) {
-      Geom<float> g{h->c, (const float*)h->o, (const float*)h->aw, (const float*)h->sf, h->n};
-      launch_entries<float>(g, h->inv, dr, dc, count, dout, s);
+      Geom<float> g{h->c, (const float*)h->o, (const float*)h->aw, (const float*)h->sf, h->n,
+                    h->tv, h->vid};
+      launch_entries<float>(g, h->op, h->inv, dr, dc, count, dout, s);
     } else {
-      Geom<double> g{h->c, (const double*)h->o, (const double*)h->aw, (const double*)h->sf, h->n};
-      launch_entries<double>(g, h->inv, dr, dc, count, dout, s);
+      Geom<double> g{h->c, (const double*)h->o, (const double*)h->aw, (const double*)h->sf, h->n,
+                     h->tv, h->vid};
+      launch_entries<double>(g, h->op, h->inv, dr, dc, count, dout, s);
     }
     HM_HIP(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, s));
     HM_HIP(hipStreamSynchronize(s));

@@ -5,7 +5,9 @@
 // admissibility test of Sec. 2.3 (eq. admissibilityCondition) must round
 // exactly like the plain FP64 definition, so that the block partition is
 // bit-identical to it.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "hm_internal.h"
 
@@ -298,20 +300,50 @@ __device__ inline bool admissible(const double* bt, const double* bs, double eta
   return fmin(dt2, ds2) <= eta2 * dist2;
 }
 
+// Squared distance of two boxes.
+__device__ inline double box_dist2(const double* bt, const double* bs) {
+  double g[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) g[d] = fmax(fmax(bs[d] - bt[3 + d], bt[d] - bs[3 + d]), 0.0);
+  return (g[0] * g[0] + g[1] * g[1]) + g[2] * g[2];
+}
+
+// Does a triangle of cluster t share a vertex with one of cluster s?  Walks
+// the triangles around the vertices of the smaller cluster.
+__device__ inline bool share_vertex(const GalTouch& gt, Cluster t, Cluster s) {
+  const Cluster a = (t.y - t.x <= s.y - s.x) ? t : s;
+  const Cluster b = (t.y - t.x <= s.y - s.x) ? s : t;
+  for (int i = a.x; i < a.y; ++i)
+    for (int k = 0; k < 3; ++k) {
+      const int32_t v = gt.vid[k * gt.n + i];
+      for (int32_t q = gt.vbeg[v]; q < gt.vbeg[v + 1]; ++q) {
+        const int32_t p = gt.vpos[q];
+        if (b.x <= p && p < b.y) return true;
+      }
+    }
+  return false;
+}
+
 // Algorithm 1 for one level of candidate blocks: admissible leaf, dense
 // leaf, or subdivide (not admissible, both clusters > leaf).  The class of
 // every candidate pair is packed for one scan: 1 = admissible (low 32
 // bits), 1 << 32 = dense leaf (high 32 bits), 0 = subdivide.  The exclusive
 // prefix then holds the admissible and dense offsets in its two halves, and
-// the split offset is k minus both.
+// the split offset is k minus both.  With gt.vid (Galerkin) an admissible
+// pair whose triangles share a vertex is not admissible: its entries include
+// singular integrals, which the ACA does not evaluate.  Only pairs whose
+// boxes are within the reach of touching triangles are searched.
 __global__ void k_classify(const int2* __restrict__ cand, int64_t ncand,
                            const Cluster* __restrict__ cl, const double* __restrict__ box,
-                           double eta2, int leaf, int64_t* __restrict__ f) {
+                           double eta2, int leaf, GalTouch gt, int64_t* __restrict__ f) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < ncand;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = cand[k];
     const Cluster t = cl[ts.x], s = cl[ts.y];
-    const bool adm = admissible(box + 6 * (int64_t)ts.x, box + 6 * (int64_t)ts.y, eta2);
+    const double* bt = box + 6 * (int64_t)ts.x;
+    const double* bs = box + 6 * (int64_t)ts.y;
+    bool adm = admissible(bt, bs, eta2);
+    if (adm && gt.vid && box_dist2(bt, bs) <= gt.reach2) adm = !share_vertex(gt, t, s);
     const bool split = !adm && (t.y - t.x > leaf) && (s.y - s.x > leaf);
     f[k] = adm ? 1 : (split ? 0 : (int64_t(1) << 32));
   }
@@ -380,6 +412,107 @@ template void launch_geom_sorted<float>(const double*, const int32_t*, const int
 template void launch_geom_sorted<double>(const double*, const int32_t*, const int32_t*, int64_t,
                                          double*, double*, double*, double*, hipStream_t);
 
+// Vertices and vertex indices of every triangle in Morton order (the
+// Galerkin operator's singular entries and its touching test):
+// v[(3 k + d) n + p] = coordinate d of vertex k of triangle perm[p],
+// vid[k n + p] = its vertex index.
+__global__ void k_tri_sorted(const double* __restrict__ V, const int32_t* __restrict__ Tri,
+                             const int32_t* __restrict__ perm, int64_t n, double* __restrict__ v,
+                             int32_t* __restrict__ vid) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = perm[p];
+    for (int k = 0; k < 3; ++k) {
+      const int32_t a = Tri[3 * t + k];
+      vid[k * n + p] = a;
+      for (int d = 0; d < 3; ++d) v[(3 * k + d) * n + p] = V[3 * (int64_t)a + d];
+    }
+  }
+}
+void launch_tri_sorted(const double* V, const int32_t* Tri, const int32_t* perm, int64_t n,
+                       double* v, int32_t* vid, hipStream_t s) {
+  k_tri_sorted<<<grid_for(n, kT), kT, 0, s>>>(V, Tri, perm, n, v, vid);
+  HM_LAUNCH_CHECK();
+}
+
+// Largest centroid-to-vertex distance (squared, as the bits of a
+// non-negative double, which order like the values).
+__global__ void k_tri_reach(const double* __restrict__ c, const double* __restrict__ tv, int64_t n,
+                            unsigned long long* __restrict__ out) {
+  double r2 = 0.0;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x)
+    for (int k = 0; k < 3; ++k) {
+      double d2 = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        const double e = tv[(3 * k + d) * n + p] - c[d * n + p];
+        d2 += e * e;
+      }
+      r2 = fmax(r2, d2);
+    }
+  atomicMax(out, (unsigned long long)__double_as_longlong(r2));
+}
+
+// (vertex, position) pairs of every triangle corner.
+__global__ void k_corner_pairs(const int32_t* __restrict__ vid, int64_t n,
+                               uint64_t* __restrict__ key, int32_t* __restrict__ pos) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 3 * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    key[e] = (uint64_t)(uint32_t)vid[e];
+    pos[e] = (int32_t)(e % n);
+  }
+}
+
+// vbeg[v] = first sorted entry with key >= v, for v = 0..nv.
+__global__ void k_vertex_begins(const uint64_t* __restrict__ key, int64_t ne, int64_t nv,
+                                int32_t* __restrict__ vbeg) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e <= ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = e == 0 ? 0 : (int64_t)key[e - 1] + 1;
+    const int64_t hi = e == ne ? nv : (int64_t)key[e];
+    for (int64_t v = lo; v <= hi; ++v) vbeg[v] = (int32_t)e;
+  }
+}
+
+GalTouch make_gal_touch(const double* c, const double* tv, const int32_t* vid, int64_t n,
+                        int64_t nv, hipStream_t s) {
+  if (3 * n >= INT32_MAX) throw Error{HM_ERR_STATE, "too many triangle corners"};
+  GalTouch t;
+  t.vid = vid;
+  t.n = n;
+  unsigned long long* r = dalloc_t<unsigned long long>(1, s);
+  HM_HIP(hipMemsetAsync(r, 0, sizeof(unsigned long long), s));
+  k_tri_reach<<<std::min<unsigned>(grid_for(n, kT), 1024), kT, 0, s>>>(c, tv, n, r);
+  HM_LAUNCH_CHECK();
+  uint64_t* key = dalloc_t<uint64_t>(3 * n, s);
+  t.vpos = dalloc_t<int32_t>(3 * n, s);
+  t.vbeg = dalloc_t<int32_t>(nv + 1, s);
+  k_corner_pairs<<<grid_for(3 * n, kT), kT, 0, s>>>(vid, n, key, t.vpos);
+  HM_LAUNCH_CHECK();
+  int bits = 1;
+  while ((int64_t(1) << bits) < nv) ++bits;
+  radix_sort_u64_i32(key, t.vpos, 3 * n, bits, s);
+  k_vertex_begins<<<grid_for(3 * n + 1, kT), kT, 0, s>>>(key, 3 * n, nv, t.vbeg);
+  HM_LAUNCH_CHECK();
+  unsigned long long rb = 0;
+  HM_HIP(hipMemcpyAsync(&rb, r, sizeof(rb), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  dfree(key, s);
+  dfree(r, s);
+  double r2 = 0.0;
+  std::memcpy(&r2, &rb, sizeof(r2));
+  // the centroids of two touching triangles are at most 2 r_max apart; the
+  // margin covers the rounding of the boxes
+  t.reach2 = 4.0 * r2 * (1.0 + 1e-9);
+  return t;
+}
+
+void free_gal_touch(GalTouch& t, hipStream_t s) {
+  if (t.vbeg) dfree(t.vbeg, s);
+  if (t.vpos) dfree(t.vpos, s);
+  t = GalTouch{};
+}
+
 // Builds the CBC tree level by level on the device.  Returns the number of
 // clusters; level_beg receives the first cluster of every level (plus end).
 int64_t build_cluster_tree(const std::vector<int64_t>& goff, int leaf, Cluster* cl, int64_t cap,
@@ -447,8 +580,8 @@ void launch_boxes(const Cluster* cl, const std::vector<int64_t>& level_beg, cons
 // Returns the admissible and dense leaf lists (device, owned by the caller)
 // in level order.
 void build_block_tree(const Cluster* cl, int64_t nroots, const double* box, double eta, int leaf,
-                      int2** adm_out, int64_t* nadm, int2** dns_out, int64_t* ndns,
-                      int64_t* depth, hipStream_t s) {
+                      const GalTouch& gt, int2** adm_out, int64_t* nadm, int2** dns_out,
+                      int64_t* ndns, int64_t* depth, hipStream_t s) {
   std::vector<std::pair<int2*, int64_t>> adm_lv, dns_lv;
   // traversal from (root_g, root_g) of every geometry: geometries never
   // interact, so the operator is block diagonal over them
@@ -466,7 +599,7 @@ void build_block_tree(const Cluster* cl, int64_t nroots, const double* box, doub
     if (ncand >= (int64_t(1) << 32)) throw Error{HM_ERR_STATE, "block tree level too large"};
     int64_t* f = dalloc_t<int64_t>(2 * ncand, s);
     int64_t* off = f + ncand;
-    k_classify<<<grid_for(ncand, kT), kT, 0, s>>>(cand, ncand, cl, box, eta2, leaf, f);
+    k_classify<<<grid_for(ncand, kT), kT, 0, s>>>(cand, ncand, cl, box, eta2, leaf, gt, f);
     HM_LAUNCH_CHECK();
     scan_excl_i64(f, off, ncand, tot, s);
     const int64_t packed = d2h_i64(tot, s);

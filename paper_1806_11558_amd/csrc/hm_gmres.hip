@@ -1,8 +1,8 @@
 // Vector kernels of the restarted GMRES solver (double precision Arnoldi).
 //
 // The paper solves its symmetric Galerkin system by CG with one H-matrix
-// product per step (Sec. 4.1); the collocation matrix used here is not
-// symmetric, so the solve is GMRES with the same product.  All reductions
+// product per step (Sec. 4.1); the collocation matrix is not symmetric, so
+// its solve is GMRES with the same product.  Both are here.  All reductions
 // write per-tile partial sums that a second kernel adds in a fixed order, so
 // the solve is bitwise reproducible.
 #include "hm_internal.h"
@@ -181,7 +181,46 @@ __global__ void k_copy_col_f32(const double* __restrict__ Q, int64_t ldq, const 
     out[e] = (float)q[e];
 }
 
+// ---- conjugate gradients (Sec. 4.1), every column its own recurrence.
+// alpha_c = rr[c] / pq[c] for active columns (0 for inactive ones and for
+// pq = 0); x += alpha p, r -= alpha q.
+__global__ void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            const double* __restrict__ rr, const double* __restrict__ pq,
+                            const double* __restrict__ active, int64_t n, int nr) {
+  const int64_t tot = n * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nr);
+    const double a = (active[c] != 0.0 && pq[c] != 0.0) ? rr[c] / pq[c] : 0.0;
+    x[e] += a * p[e];
+    r[e] -= a * q[e];
+  }
+}
+
+// p = r + beta p with beta_c = rr_new[c] / rr_old[c], active columns only.
+__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ r,
+                         const double* __restrict__ rr_new, const double* __restrict__ rr_old,
+                         const double* __restrict__ active, int64_t n, int nr) {
+  const int64_t tot = n * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % nr);
+    if (active[c] != 0.0 && rr_old[c] != 0.0) p[e] = r[e] + (rr_new[c] / rr_old[c]) * p[e];
+  }
+}
+
 // ------------------------------------------------------------------ launchers
+void cg_update(double* x, double* r, const double* p, const double* q, const double* rr,
+               const double* pq, const double* active, int64_t n, int nr, hipStream_t s) {
+  k_cg_update<<<grid_for(n * nr, 256, 8192), 256, 0, s>>>(x, r, p, q, rr, pq, active, n, nr);
+  HM_LAUNCH_CHECK();
+}
+void cg_dir(double* p, const double* r, const double* rr_new, const double* rr_old,
+            const double* active, int64_t n, int nr, hipStream_t s) {
+  k_cg_dir<<<grid_for(n * nr, 256, 8192), 256, 0, s>>>(p, r, rr_new, rr_old, active, n, nr);
+  HM_LAUNCH_CHECK();
+}
 void gmres_dots_dev(const double* Q, int64_t ldq, const int* jd, int nkmax, const double* w,
                     int64_t n, int nr, double* part, double* out, hipStream_t s) {
   const int tiles = gmres_tiles(n);

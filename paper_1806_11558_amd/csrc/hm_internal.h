@@ -54,6 +54,8 @@ struct Radon7 {
 //                          then y, then z
 //   aw  : T[n]             |T_j| / (4 pi)
 //   sf  : T[n]             analytic self-term a_jj
+//   v   : double[9][n]     vertices (v0 xyz, v1 xyz, v2 xyz), Galerkin only
+//   vid : int32[3][n]      global vertex indices, Galerkin only
 template <typename T>
 struct Geom {
   const double* c;
@@ -61,10 +63,43 @@ struct Geom {
   const T* aw;
   const T* sf;
   int64_t n;
+  const double* v = nullptr;
+  const int32_t* vid = nullptr;
 };
+
+// Operator of a handle: collocation at centroids (the default) or the
+// paper's Galerkin discretisation (Sec. 2.2, eq. linearSystem).
+enum { kOpColloc = 0, kOpGalerkin = 1 };
+
+// Gauss-Legendre rule on [0, 1] for the singular Galerkin entries (outer
+// integral in collapsed coordinates, kGalQ x kGalQ points).
+constexpr int kGalQ = 12;
+struct GaussRule {
+  double x[kGalQ];
+  double w[kGalQ];
+};
+GaussRule gauss_rule01();
 
 // Cluster record: lo, hi (Morton positions), first child (-1 for a leaf), level.
 using Cluster = int4;
+
+// Galerkin admissibility: the test for triangles of two clusters that share
+// a vertex (the supports of their basis functions touch).
+//   vid   : int32[3][n]   vertex indices, Morton order
+//   vbeg  : int32[nv + 1] vertex -> first entry of vpos
+//   vpos  : int32[3 n]    Morton positions of the triangles around each vertex
+//   reach2: (2 r_max)^2 with r_max the largest centroid-to-vertex distance;
+//           the centroids of two touching triangles are at most 2 r_max apart
+struct GalTouch {
+  const int32_t* vid = nullptr;
+  int32_t* vbeg = nullptr;
+  int32_t* vpos = nullptr;
+  int64_t n = 0;
+  double reach2 = 0.0;
+};
+GalTouch make_gal_touch(const double* c, const double* tv, const int32_t* vid, int64_t n,
+                        int64_t nv, hipStream_t s);
+void free_gal_touch(GalTouch& t, hipStream_t s);
 
 
 
@@ -159,6 +194,7 @@ struct SetupIn {
   int kmax;
   double eps;
   int64_t pool_budget_bytes;   // upper bound for the ACA working pool
+  int op;                      // kOpColloc or kOpGalerkin
 };
 struct Storage {
   int64_t D_elems = 0, dense_cols = 0;

@@ -100,102 +100,6 @@ __device__ inline T eval_entry(double xi, double yi, double zi, int i, const Src
   return w * s.aw;
 }
 
-template <typename T>
-__device__ inline T entry_at(const Geom<T>& g, int i, int j) {
-  Src<T> s;
-  load_src(g, j, s);
-  return eval_entry(g.c[i], g.c[g.n + i], g.c[2 * g.n + i], i, s, j);
-}
-
-// Entries at arbitrary (application) index pairs, for checking.
-template <typename T>
-__global__ void k_entries(Geom<T> g, const int32_t* __restrict__ inv_perm,
-                          const int32_t* __restrict__ rows, const int32_t* __restrict__ cols,
-                          int64_t cnt, double* __restrict__ out) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt;
-       k += (int64_t)gridDim.x * blockDim.x)
-    out[k] = (double)entry_at(g, inv_perm[rows[k]], inv_perm[cols[k]]);
-}
-
-__global__ void k_inverse_perm(const int32_t* __restrict__ perm, int64_t n,
-                               int32_t* __restrict__ inv) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * blockDim.x)
-    inv[perm[p]] = (int32_t)p;
-}
-
-// ------------------------------------------------------------------ near field
-// Dense leaves of Algorithm 1, assembled in one batch (Sec. 3.3): one
-// workgroup per (dense block, row leaf) slice, written straight into the row
-// leaf's panel (ld x n, column-major, zero padding rows).
-struct LeafTab {
-  const int32_t* lo;     // first position of leaf
-  const int32_t* m;      // size
-  const int64_t* ldpre;  // prefix of ld over leaves (nleaf + 1 entries)
-  const int2* cl_leaves; // per cluster: first and last leaf
-};
-
-__device__ inline int leaf_ld(const LeafTab& L, int lf) {
-  return (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restrict__ sidx,
-                                              const int32_t* __restrict__ ib,
-                                              const int32_t* __restrict__ ilf, int64_t np,
-                                              const int2* __restrict__ dns,
-                                              const Cluster* __restrict__ cl, LeafTab L,
-                                              const int64_t* __restrict__ offI, T* __restrict__ D) {
-  // the slice's source triangles (columns, at most a leaf) and collocation
-  // points (rows) are staged in LDS once; entries read them from there
-  __shared__ Src<T> src[kMaxLeaf];
-  __shared__ double xr[3][kMaxLeaf];
-  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
-    const int32_t u = sidx[p];
-    const int b = ib[u], lf = ilf[u];
-    const Cluster sig = cl[dns[b].y];
-    const int n = sig.y - sig.x;
-    const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
-    T* dst = D + offI[p];
-    if (n <= kMaxLeaf) {                                // dense blocks are leaf pairs
-      for (int j = threadIdx.x; j < n; j += blockDim.x) load_src_u(g, sig.x + j, src[j]);
-      for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        xr[0][i] = g.c[lo + i];
-        xr[1][i] = g.c[g.n + lo + i];
-        xr[2][i] = g.c[2 * g.n + lo + i];
-      }
-      __syncthreads();
-      // entry e = i + ld j; (i, j) advance by a fixed step instead of a
-      // division per entry
-      const int di = (int)blockDim.x % ld, dj = (int)blockDim.x / ld;
-      int i = (int)threadIdx.x % ld, j = (int)threadIdx.x / ld;
-      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
-        T v = 0;
-        if (i < m) {
-          const Src<T> sj = src[j];
-          v = eval_entry(xr[0][i], xr[1][i], xr[2][i], lo + i, sj, sig.x + j);
-        }
-        dst[e] = v;
-        i += di;
-        j += dj;
-        if (i >= ld) {
-          i -= ld;
-          ++j;
-        }
-      }
-      __syncthreads();                                  // before the next slice is staged
-    } else {
-      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
-        const int i = e % ld, j = e / ld;
-        T v = 0;
-        if (i < m) v = entry_at(g, lo + i, sig.x + j);
-        dst[e] = v;
-      }
-    }
-  }
-}
-
-// ------------------------------------------------------------------ ACA
 // ---- wavefront primitives (gfx9 DPP).  The row-of-16 butterfly (quad
 // permutes, half mirror, mirror) followed by the two row broadcasts leaves
 // the full result in lane 63; readlane makes it uniform.  Masked rows of a
@@ -236,6 +140,398 @@ __device__ inline A wsum(A v) {
   return rdl_v(v, 63);
 }
 
+// ---- row side of an entry.  Collocation: the collocation point x_i.
+// Galerkin: the whole triangle T_i (centroid, node offsets, |T_i| / 4 pi).
+template <typename T, int OP>
+struct Tgt;
+template <typename T>
+struct Tgt<T, kOpColloc> {
+  double x, y, z;
+};
+template <typename T>
+struct Tgt<T, kOpGalerkin> {
+  double x, y, z;
+  T ox[kNQ], oy[kNQ], oz[kNQ];
+  T aw;
+};
+
+// Row i = base + k, base wavefront-uniform (one 32-bit offset per load).
+template <typename T>
+__device__ inline void load_tgt(const Geom<T>& g, int base, int k, Tgt<T, kOpColloc>& t) {
+  const uint32_t b8 = (uint32_t)k * 8u;
+  t.x = ld_at(g.c + base, b8);
+  t.y = ld_at(g.c + g.n + base, b8);
+  t.z = ld_at(g.c + 2 * g.n + base, b8);
+}
+template <typename T>
+__device__ inline void load_tgt(const Geom<T>& g, int base, int k, Tgt<T, kOpGalerkin>& t) {
+  const uint32_t b8 = (uint32_t)k * 8u, bt = (uint32_t)k * (uint32_t)sizeof(T);
+  t.x = ld_at(g.c + base, b8);
+  t.y = ld_at(g.c + g.n + base, b8);
+  t.z = ld_at(g.c + 2 * g.n + base, b8);
+#pragma unroll
+  for (int q = 0; q < kNQ; ++q) {
+    t.ox[q] = ld_at(g.o + (int64_t)q * g.n + base, bt);
+    t.oy[q] = ld_at(g.o + (int64_t)(kNQ + q) * g.n + base, bt);
+    t.oz[q] = ld_at(g.o + (int64_t)(2 * kNQ + q) * g.n + base, bt);
+  }
+  t.aw = ld_at(g.aw + base, bt);
+}
+
+// The value of lane l of every member (l wavefront-uniform).
+template <typename T>
+__device__ inline Tgt<T, kOpColloc> rdl_tgt(const Tgt<T, kOpColloc>& a, int l) {
+  return Tgt<T, kOpColloc>{rdl_v(a.x, l), rdl_v(a.y, l), rdl_v(a.z, l)};
+}
+template <typename T>
+__device__ inline Tgt<T, kOpGalerkin> rdl_tgt(const Tgt<T, kOpGalerkin>& a, int l) {
+  Tgt<T, kOpGalerkin> r;
+  r.x = rdl_v(a.x, l);
+  r.y = rdl_v(a.y, l);
+  r.z = rdl_v(a.z, l);
+#pragma unroll
+  for (int q = 0; q < kNQ; ++q) {
+    r.ox[q] = rdl_v(a.ox[q], l);
+    r.oy[q] = rdl_v(a.oy[q], l);
+    r.oz[q] = rdl_v(a.oz[q], l);
+  }
+  r.aw = rdl_v(a.aw, l);
+  return r;
+}
+
+// Galerkin entry of two triangles that share no vertex:
+// |T_i| |T_j| / (4 pi) sum_p w_p sum_q w_q / |x_ip - y_jq| (Radon's rule on
+// both triangles, Sec. 2.2), the centroid difference in double.
+template <typename T>
+__device__ inline T eval_far_g(const Tgt<T, kOpGalerkin>& t, const Src<T>& s) {
+  const T dx = (T)(t.x - s.cx), dy = (T)(t.y - s.cy), dz = (T)(t.z - s.cz);
+  T outer[3] = {0, 0, 0};
+#pragma unroll
+  for (int p = 0; p < kNQ; ++p) {
+    const T px = dx + t.ox[p], py = dy + t.oy[p], pz = dz + t.oz[p];
+    T acc[3] = {0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kNQ; ++q) {
+      const T ex = px - s.ox[q], ey = py - s.oy[q], ez = pz - s.oz[q];
+      acc[q == 0 ? 0 : (q <= 3 ? 1 : 2)] += rsq(ex * ex + ey * ey + ez * ez);
+    }
+    outer[p == 0 ? 0 : (p <= 3 ? 1 : 2)] +=
+        (T)Radon7::w0 * acc[0] + (T)Radon7::w1 * acc[1] + (T)Radon7::w2 * acc[2];
+  }
+  const T sum = (T)Radon7::w0 * outer[0] + (T)Radon7::w1 * outer[1] + (T)Radon7::w2 * outer[2];
+  return sum * (t.aw * s.aw) * (T)12.566370614359172954;   // |T_i||T_j|/(4 pi) = 4 pi aw_i aw_j
+}
+
+// Entry of row t (position i) and source s (position j).  Galerkin pairs
+// that touch are not evaluated here (see galerkin_singular); they never lie
+// in an admissible block, so the ACA meets only this form.
+template <typename T>
+__device__ inline T op_entry(const Tgt<T, kOpColloc>& t, int i, const Src<T>& s, int j) {
+  return eval_entry(t.x, t.y, t.z, i, s, j);
+}
+template <typename T>
+__device__ inline T op_entry(const Tgt<T, kOpGalerkin>& t, int i, const Src<T>& s, int j) {
+  (void)i;
+  (void)j;
+  return eval_far_g(t, s);
+}
+
+// ---- singular Galerkin entries (Sec. 4.1: higher-order quadrature and the
+// Duffy trick), in double.
+// int_T dsigma_y / |x - y| for the flat triangle T with vertices v[0..2]
+// and any point x: T is the signed sum of the triangles (x', a, b) over its
+// edges, x' the projection of x onto the plane of T at signed height d; in
+// polar coordinates about x' every edge gives, between its end points,
+// h asinh(l / c) + |d| atan(|d| l / (h R)) - |d| atan(l / h)
+// (h distance of x' to the edge line, l coordinate along it, c^2 = h^2 + d^2,
+// R distance from x to the end point).
+__device__ inline double tri_inner_integral(const double x[3], const double v[3][3]) {
+  double e1[3], e2[3], n[3];
+  for (int k = 0; k < 3; ++k) {
+    e1[k] = v[1][k] - v[0][k];
+    e2[k] = v[2][k] - v[0][k];
+  }
+  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int k = 0; k < 3; ++k) n[k] /= nn;
+  const double d = (x[0] - v[0][0]) * n[0] + (x[1] - v[0][1]) * n[1] + (x[2] - v[0][2]) * n[2];
+  const double ad = fabs(d);
+  double xp[3];
+  for (int k = 0; k < 3; ++k) xp[k] = x[k] - d * n[k];
+  double total = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double* a = v[k];
+    const double* b = v[(k + 1) % 3];
+    double e[3], am[3], bm[3];
+    for (int c = 0; c < 3; ++c) {
+      e[c] = b[c] - a[c];
+      am[c] = a[c] - xp[c];
+      bm[c] = b[c] - xp[c];
+    }
+    const double le = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    // twice the signed area of (x', a, b) relative to n
+    const double cr = (am[1] * e[2] - am[2] * e[1]) * n[0] + (am[2] * e[0] - am[0] * e[2]) * n[1] +
+                      (am[0] * e[1] - am[1] * e[0]) * n[2];
+    const double h = fabs(cr) / le;
+    if (!(h > 0.0)) continue;                            // x' on the edge line
+    const double la = (am[0] * e[0] + am[1] * e[1] + am[2] * e[2]) / le;
+    const double lb = (bm[0] * e[0] + bm[1] * e[1] + bm[2] * e[2]) / le;
+    const double ra = sqrt((x[0] - a[0]) * (x[0] - a[0]) + (x[1] - a[1]) * (x[1] - a[1]) +
+                           (x[2] - a[2]) * (x[2] - a[2]));
+    const double rb = sqrt((x[0] - b[0]) * (x[0] - b[0]) + (x[1] - b[1]) * (x[1] - b[1]) +
+                           (x[2] - b[2]) * (x[2] - b[2]));
+    const double c = sqrt(h * h + d * d);
+    double val = h * (asinh(lb / c) - asinh(la / c));
+    if (ad > 0.0)
+      val += ad * (atan(ad * lb / (h * rb)) - atan(ad * la / (h * ra))) -
+             ad * (atan(lb / h) - atan(la / h));
+    total += cr > 0.0 ? val : -val;
+  }
+  return total;
+}
+
+template <typename T>
+__device__ inline void load_tri(const Geom<T>& g, int i, double v[3][3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[k][c] = g.v[(int64_t)(3 * k + c) * g.n + i];
+}
+
+// a_ij of touching triangles: kGalQ x kGalQ Gauss points on T_i in collapsed coordinates
+// x = v0 + s (v1 - v0) + s t (v2 - v1), weight w_s w_t s |(v1 - v0) x (v2 - v1)|,
+// the inner integral over T_j in closed form.
+template <typename T>
+__device__ inline double galerkin_singular_part(const Geom<T>& g, const GaussRule& R, int i, int j,
+                                                int k0, int step) {
+  double ti[3][3], tj[3][3];
+  load_tri(g, i, ti);
+  load_tri(g, j, tj);
+  double a[3], b[3];
+  for (int c = 0; c < 3; ++c) {
+    a[c] = ti[1][c] - ti[0][c];
+    b[c] = ti[2][c] - ti[1][c];
+  }
+  const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2],
+               cz = a[0] * b[1] - a[1] * b[0];
+  const double jac = sqrt(cx * cx + cy * cy + cz * cz);
+  double acc = 0.0;
+  for (int k = k0; k < kGalQ * kGalQ; k += step) {
+    const int ks = k / kGalQ, kt = k % kGalQ;
+    const double s = R.x[ks], t = R.x[kt];
+    double x[3];
+    for (int c = 0; c < 3; ++c) x[c] = ti[0][c] + s * a[c] + s * t * b[c];
+    acc += R.w[ks] * R.w[kt] * s * jac * tri_inner_integral(x, tj);
+  }
+  return acc * 0.079577471545947667884441881686257181;   // 1/(4 pi)
+}
+template <typename T>
+__device__ inline double galerkin_singular(const Geom<T>& g, const GaussRule& R, int i, int j) {
+  return wsum(galerkin_singular_part(g, R, i, j, threadIdx.x & 63, 64));
+}
+
+
+// Do triangles i and j share a vertex (or coincide)?
+template <typename T>
+__device__ inline bool touching(const Geom<T>& g, int i, int j) {
+  if (i == j) return true;
+  const int32_t a0 = g.vid[i], a1 = g.vid[g.n + i], a2 = g.vid[2 * g.n + i];
+  const int32_t b0 = g.vid[j], b1 = g.vid[g.n + j], b2 = g.vid[2 * g.n + j];
+  return a0 == b0 || a0 == b1 || a0 == b2 || a1 == b0 || a1 == b1 || a1 == b2 || a2 == b0 ||
+         a2 == b1 || a2 == b2;
+}
+
+template <typename T>
+__device__ inline T entry_at(const Geom<T>& g, int i, int j) {
+  Src<T> s;
+  load_src(g, j, s);
+  return eval_entry(g.c[i], g.c[g.n + i], g.c[2 * g.n + i], i, s, j);
+}
+
+// Entries at arbitrary (application) index pairs, for checking: one
+// wavefront per pair (the singular Galerkin entries sum over its lanes).
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_entries(Geom<T> g, GaussRule R,
+                                                 const int32_t* __restrict__ inv_perm,
+                                                 const int32_t* __restrict__ rows,
+                                                 const int32_t* __restrict__ cols, int64_t cnt,
+                                                 double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t k = blockIdx.x * 4 + (threadIdx.x >> 6); k < cnt; k += (int64_t)gridDim.x * 4) {
+    const int i = inv_perm[rows[k]], j = inv_perm[cols[k]];
+    double v;
+    if (OP == kOpGalerkin && touching(g, i, j)) {
+      v = galerkin_singular(g, R, i, j);
+    } else {
+      Tgt<T, OP> t;
+      load_tgt(g, i, 0, t);
+      Src<T> s;
+      load_src(g, j, s);
+      v = (double)op_entry(t, i, s, j);
+    }
+    if (lane == 0) out[k] = v;
+  }
+}
+
+__global__ void k_inverse_perm(const int32_t* __restrict__ perm, int64_t n,
+                               int32_t* __restrict__ inv) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x)
+    inv[perm[p]] = (int32_t)p;
+}
+
+// ------------------------------------------------------------------ near field
+// Dense leaves of Algorithm 1, assembled in one batch (Sec. 3.3): one
+// workgroup per (dense block, row leaf) slice, written straight into the row
+// leaf's panel (ld x n, column-major, zero padding rows).
+struct LeafTab {
+  const int32_t* lo;     // first position of leaf
+  const int32_t* m;      // size
+  const int64_t* ldpre;  // prefix of ld over leaves (nleaf + 1 entries)
+  const int2* cl_leaves; // per cluster: first and last leaf
+};
+
+__device__ inline int leaf_ld(const LeafTab& L, int lf) {
+  return (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_near(Geom<T> g, const int32_t* __restrict__ sidx,
+                                              const int32_t* __restrict__ ib,
+                                              const int32_t* __restrict__ ilf, int64_t np,
+                                              const int2* __restrict__ dns,
+                                              const Cluster* __restrict__ cl, LeafTab L,
+                                              const int64_t* __restrict__ offI, T* __restrict__ D) {
+  // the slice's source triangles (columns, at most a leaf) and rows are
+  // staged in LDS once; entries read them from there.  Galerkin pairs that
+  // touch get 0 here and their value from k_near_singular.
+  constexpr bool GAL = OP == kOpGalerkin;
+  __shared__ Src<T> src[kMaxLeaf];
+  __shared__ Tgt<T, OP> tr[kMaxLeaf];
+  __shared__ int32_t vr[GAL ? 3 : 1][kMaxLeaf], vc[GAL ? 3 : 1][kMaxLeaf];
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const int32_t u = sidx[p];
+    const int b = ib[u], lf = ilf[u];
+    const Cluster sig = cl[dns[b].y];
+    const int n = sig.y - sig.x;
+    const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
+    T* dst = D + offI[p];
+    if (n <= kMaxLeaf) {                                // dense blocks are leaf pairs
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        load_src_u(g, sig.x + j, src[j]);
+        if (GAL)
+          for (int k = 0; k < 3; ++k) vc[k][j] = g.vid[(int64_t)k * g.n + sig.x + j];
+      }
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        load_tgt(g, lo, i, tr[i]);
+        if (GAL)
+          for (int k = 0; k < 3; ++k) vr[k][i] = g.vid[(int64_t)k * g.n + lo + i];
+      }
+      __syncthreads();
+      // entry e = i + ld j; (i, j) advance by a fixed step instead of a
+      // division per entry
+      const int di = (int)blockDim.x % ld, dj = (int)blockDim.x / ld;
+      int i = (int)threadIdx.x % ld, j = (int)threadIdx.x / ld;
+      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
+        T v = 0;
+        if (i < m) {
+          bool skip = false;
+          if (GAL) {
+            skip = lo + i == sig.x + j;
+            for (int a = 0; a < 3; ++a)
+              for (int c = 0; c < 3; ++c) skip = skip || vr[a][i] == vc[c][j];
+          }
+          if (!skip) {
+            const Src<T> sj = src[j];
+            v = op_entry(tr[i], lo + i, sj, sig.x + j);
+          }
+        }
+        dst[e] = v;
+        i += di;
+        j += dj;
+        if (i >= ld) {
+          i -= ld;
+          ++j;
+        }
+      }
+      __syncthreads();                                  // before the next slice is staged
+    } else {
+      for (int e = threadIdx.x; e < ld * n; e += blockDim.x) {
+        const int i = e % ld, j = e / ld;
+        T v = 0;
+        if (i < m && !(GAL && touching(g, lo + i, sig.x + j))) {
+          Tgt<T, OP> t;
+          load_tgt(g, lo, i, t);
+          Src<T> sj;
+          load_src(g, sig.x + j, sj);
+          v = op_entry(t, lo + i, sj, sig.x + j);
+        }
+        dst[e] = v;
+      }
+    }
+  }
+}
+
+// Singular Galerkin entries of the near field (pairs that share a vertex,
+// left at 0 by k_near): one workgroup per slice as in k_near.  Every
+// wavefront looks at 64 consecutive entries at a time and evaluates the
+// touching ones among them one after the other, all its lanes together
+// (the trip count of its loop is the same for all lanes).
+template <typename T>
+__global__ __launch_bounds__(256) void k_near_singular(Geom<T> g, GaussRule R,
+                                                       const int32_t* __restrict__ sidx,
+                                                       const int32_t* __restrict__ ib,
+                                                       const int32_t* __restrict__ ilf, int64_t np,
+                                                       const int2* __restrict__ dns,
+                                                       const Cluster* __restrict__ cl, LeafTab L,
+                                                       const int64_t* __restrict__ offI,
+                                                       T* __restrict__ D) {
+  __shared__ int32_t vr[3][kMaxLeaf], vc[3][kMaxLeaf];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const int32_t u = sidx[p];
+    const int b = ib[u], lf = ilf[u];
+    const Cluster sig = cl[dns[b].y];
+    const int n = sig.y - sig.x;
+    const int ld = leaf_ld(L, lf), m = L.m[lf], lo = L.lo[lf];
+    T* dst = D + offI[p];
+    const bool staged = n <= kMaxLeaf;
+    if (staged) {
+      for (int j = threadIdx.x; j < n; j += blockDim.x)
+        for (int k = 0; k < 3; ++k) vc[k][j] = g.vid[(int64_t)k * g.n + sig.x + j];
+      for (int i = threadIdx.x; i < m; i += blockDim.x)
+        for (int k = 0; k < 3; ++k) vr[k][i] = g.vid[(int64_t)k * g.n + lo + i];
+    }
+    __syncthreads();
+    for (int e0 = wave * 64; e0 < ld * n; e0 += blockDim.x) {
+      const int e = e0 + lane;
+      const int i = e % ld, j = e / ld;
+      bool t = false;
+      if (e < ld * n && i < m) {
+        if (staged) {
+          t = lo + i == sig.x + j;
+          for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) t = t || vr[a][i] == vc[c][j];
+        } else {
+          t = touching(g, lo + i, sig.x + j);
+        }
+      }
+      unsigned long long mask = __ballot(t);
+      while (mask) {
+        const int l = __ffsll(mask) - 1;
+        mask &= mask - 1;
+        const int el = e0 + l;
+        const double v = galerkin_singular(g, R, lo + el % ld, sig.x + el / ld);
+        if (lane == 0) dst[el] = (T)v;
+      }
+    }
+    __syncthreads();                                  // before the next slice is staged
+  }
+}
+
+// ------------------------------------------------------------------ ACA
 // Values that are equal in every lane, moved to scalar registers, so that
 // the compiler sees the branches on them as uniform.  The workgroup ACA and
 // the work queue branch only on such values: a barrier then never sits in
@@ -346,7 +642,7 @@ __device__ inline X pick(const X (&a)[Q], int q) {
 // column-major m x kcap, then V n x kcap; a lane only reads and writes its
 // own rows / columns of them, other lanes' values arrive by readlane.
 
-template <typename T, int Q>
+template <typename T, int Q, int OP>
 __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   constexpr int KB = Q == 4 ? 4 : 8;   // previous terms per batch of loads
   const int lane = threadIdx.x & 63;
@@ -374,8 +670,11 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
   bool cap_hit = false;
   while (true) {
     const int iq = istar >> 6, il = istar & 63;
-    const double xi = rdl_v(pick(px, iq), il), yi = rdl_v(pick(py, iq), il),
-                 zi = rdl_v(pick(pz, iq), il);
+    Tgt<T, OP> ti;
+    if constexpr (OP == kOpColloc)
+      ti = Tgt<T, OP>{rdl_v(pick(px, iq), il), rdl_v(pick(py, iq), il), rdl_v(pick(pz, iq), il)};
+    else
+      load_tgt(g, r0 + istar, 0, ti);
     // residual row  v~ = a(i*, :) - sum_l u_l[i*] v_l
     T val[Q];
 #pragma unroll
@@ -384,7 +683,7 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
       if (hc[q]) {
         Src<T> s;
         load_src(g, c0 + lane + 64 * q, s);
-        val[q] = eval_entry(xi, yi, zi, r0 + istar, s, c0 + lane + 64 * q);
+        val[q] = op_entry(ti, r0 + istar, s, c0 + lane + 64 * q);
       }
     }
     // the previous terms KB at a time: their loads are issued together (an
@@ -452,7 +751,15 @@ __device__ void aca_wave(const AcaArgs<T>& A, int b) {
     double wv[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      u[q] = hr[q] ? eval_entry(px[q], py[q], pz[q], r0 + lane + 64 * q, s, c0 + jstar) : (T)0;
+      u[q] = 0;
+      if (hr[q]) {
+        Tgt<T, OP> tq;
+        if constexpr (OP == kOpColloc)
+          tq = Tgt<T, OP>{px[q], py[q], pz[q]};
+        else
+          load_tgt(g, r0, lane + 64 * q, tq);
+        u[q] = op_entry(tq, r0 + lane + 64 * q, s, c0 + jstar);
+      }
       wv[q] = 0.0;
     }
     for (int l0 = 0; l0 < r; l0 += KB) {
@@ -551,7 +858,7 @@ __device__ inline Piv wg_piv(Piv a, Piv* lds, Piv* out) {
 constexpr int kTermBatch = 8;
 constexpr int kColUnroll = 1;
 
-template <typename T, int NT>
+template <typename T, int NT, int OP>
 __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int2 ts = A.blk[b];
@@ -570,7 +877,11 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
   while (true) {
     if (tid < r) sh.a[tid] = U[(int64_t)tid * m + istar];
     __syncthreads();
-    const double xi = g.c[r0 + istar], yi = g.c[g.n + r0 + istar], zi = g.c[2 * g.n + r0 + istar];
+    Tgt<T, OP> ti;
+    if constexpr (OP == kOpColloc)
+      ti = Tgt<T, OP>{g.c[r0 + istar], g.c[g.n + r0 + istar], g.c[2 * g.n + r0 + istar]};
+    else
+      load_tgt(g, r0 + istar, 0, ti);
     Piv pv{0, 0};
     // kColUnroll columns per thread at a time, so that their loads overlap
     // (indices past n - 1 are clamped and their results dropped)
@@ -585,7 +896,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
       }
 #pragma unroll
       for (int u = 0; u < kColUnroll; ++u)
-        val[u] = eval_entry(xi, yi, zi, r0 + istar, sj[u], c0 + jj[u]);
+        val[u] = op_entry(ti, r0 + istar, sj[u], c0 + jj[u]);
       for (int l0 = 0; l0 < r; l0 += kTermBatch) {
         T vb[kColUnroll][kTermBatch];
 #pragma unroll
@@ -678,9 +989,9 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
       for (int q = 0; q < kColUnroll; ++q) {
         ii[q] = min(i0 + q * NT, m - 1);
         const int i = ii[q];
-        const uint32_t ib8 = (uint32_t)i * 8u;
-        u[q] = eval_entry(ld_at(g.c + r0, ib8), ld_at(g.c + g.n + r0, ib8),
-                          ld_at(g.c + 2 * g.n + r0, ib8), r0 + i, s, c0 + jstar);
+        Tgt<T, OP> tq;
+        load_tgt(g, r0, i, tq);
+        u[q] = op_entry(tq, r0 + i, s, c0 + jstar);
         w[q] = 0.0;
       }
       for (int l0 = 0; l0 < r; l0 += kTermBatch) {
@@ -770,8 +1081,10 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
 // latch, no early continue: every block ends at the barrier below, so the
 // thread that fetches the next position has finished the current block (its
 // result stores included) before any thread reads the next position.
-template <typename T, int NT, int CLS>
-__global__ __launch_bounds__(NT, NT == 256 ? 4 : 1) void k_aca_wg(AcaArgs<T> A) {
+// Galerkin entries (49 kernel values each) hold the whole row triangle in
+// registers: half the occupancy, no spills.
+template <typename T, int NT, int CLS, int OP>
+__global__ __launch_bounds__(NT, NT == 256 ? (OP == kOpGalerkin ? 2 : 4) : 1) void k_aca_wg(AcaArgs<T> A) {
   __shared__ AcaShared<T, NT> sh;
   __shared__ int item_sh;
   while (true) {
@@ -779,7 +1092,7 @@ __global__ __launch_bounds__(NT, NT == 256 ? 4 : 1) void k_aca_wg(AcaArgs<T> A) 
     __syncthreads();
     const int64_t it = uni(item_sh);
     if (it >= A.cnt[CLS]) break;
-    aca_wg<T, NT>(A, A.list[CLS][it], sh);
+    aca_wg<T, NT, OP>(A, A.list[CLS][it], sh);
     __syncthreads();
   }
 }
@@ -787,8 +1100,9 @@ __global__ __launch_bounds__(NT, NT == 256 ? 4 : 1) void k_aca_wg(AcaArgs<T> A) 
 // Classes 2..4: one block per wavefront; every wavefront takes its own
 // blocks from the queue, NB consecutive (similar) blocks per fetch for the
 // small classes, which have millions of blocks (no barriers).
-template <typename T, int Q>
-__global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_aca_wave(AcaArgs<T> A) {
+template <typename T, int Q, int OP>
+__global__ __launch_bounds__(kAcaThreads, OP == kOpGalerkin ? 2 : (Q == 1 ? 4 : (Q == 2 ? 3 : 2)))
+void k_aca_wave(AcaArgs<T> A) {
   constexpr int c = Q == 4 ? 2 : (Q == 2 ? 3 : 4);
   constexpr int NB = Q == 4 ? 1 : (Q == 2 ? 2 : 4);
   const int lane = threadIdx.x & 63;
@@ -799,21 +1113,25 @@ __global__ __launch_bounds__(kAcaThreads, Q == 1 ? 4 : (Q == 2 ? 3 : 2)) void k_
     it = uni(it);
     if (it >= cnt) break;
     const int64_t end = std::min<int64_t>(it + NB, cnt);
-    for (int64_t k = it; k < end; ++k) aca_wave<T, Q>(A, A.list[c][k]);
+    for (int64_t k = it; k < end; ++k) aca_wave<T, Q, OP>(A, A.list[c][k]);
   }
 }
 
 // Class of every block (see kAcaClasses).  With mask, only blocks whose
-// mask entry is set get a class.  flags[c * nb + b] = (class == c).
+// mask entry is set get a class.  flags[c * nb + b] = (class == c).  With
+// wide_rows (Galerkin), every block above 64 goes to the 256-thread class:
+// the wavefront classes with 2 and 4 rows per lane and the 1,024-thread
+// class do not fit its registers.
 __global__ void k_aca_classes(const int2* __restrict__ blk, int64_t nb,
                               const Cluster* __restrict__ cl, const int64_t* __restrict__ mask,
-                              int64_t* __restrict__ flags) {
+                              int wide_rows, int64_t* __restrict__ flags) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
     const Cluster t = cl[ts.x], s = cl[ts.y];
     const int64_t mx = max(t.y - t.x, s.y - s.x);
     int c = mx > kAcaBig ? 0 : (mx > 256 ? 1 : (mx > 128 ? 2 : (mx > 64 ? 3 : 4)));
+    if (wide_rows && c != 4) c = 1;
     if (mask && !mask[b]) c = -1;
 #pragma unroll
     for (int k = 0; k < kAcaClasses; ++k) flags[k * nb + b] = (k == c) ? 1 : 0;
@@ -1249,14 +1567,14 @@ __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* 
 // ones) at rank cap kmax: class lists, then one queue launch per class,
 // largest class first.  flags, offs: kAcaClasses * nb int64 scratch; lists:
 // kAcaClasses * nb int32; head: kAcaClasses int.
-template <typename T>
+template <typename T, int OP>
 void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
              const AcaSlot* slot, int kmax, double eps, const int64_t* mask, int64_t* flags,
              int64_t* offs, int32_t* lists, int* head, int32_t* rank, int32_t* info,
              int64_t* tmp, hipStream_t s) {
   if (nb == 0) return;
   if (nb >= INT32_MAX) throw Error{HM_ERR_STATE, "ACA chunk of more than 2^31 blocks"};
-  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, mask, flags);
+  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, mask, OP == kOpGalerkin, flags);
   HM_LAUNCH_CHECK();
   for (int k = 0; k < kAcaClasses; ++k)
     scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
@@ -1291,26 +1609,33 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
     HM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0));
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)ncu * std::max(per_cu, 1)));
   };
-  if (cnt[0] > 0) {
-    k_aca_wg<T, 1024, 0><<<grid((const void*)k_aca_wg<T, 1024, 0>, 1024, cnt[0]), 1024, 0, s>>>(A);
-    HM_LAUNCH_CHECK();
+  if constexpr (OP == kOpColloc) {
+    if (cnt[0] > 0) {
+      k_aca_wg<T, 1024, 0, OP><<<grid((const void*)k_aca_wg<T, 1024, 0, OP>, 1024, cnt[0]), 1024,
+                                 0, s>>>(A);
+      HM_LAUNCH_CHECK();
+    }
   }
   if (cnt[1] > 0) {
-    k_aca_wg<T, 256, 1><<<grid((const void*)k_aca_wg<T, 256, 1>, 256, cnt[1]), 256, 0, s>>>(A);
+    k_aca_wg<T, 256, 1, OP><<<grid((const void*)k_aca_wg<T, 256, 1, OP>, 256, cnt[1]), 256, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
-  if (cnt[2] > 0) {
-    k_aca_wave<T, 4><<<grid((const void*)k_aca_wave<T, 4>, kAcaThreads, ceil_div(cnt[2], kAcaWaves)),
-                       kAcaThreads, 0, s>>>(A);
-    HM_LAUNCH_CHECK();
-  }
-  if (cnt[3] > 0) {
-    k_aca_wave<T, 2><<<grid((const void*)k_aca_wave<T, 2>, kAcaThreads, ceil_div(cnt[3], 2 * kAcaWaves)),
-                       kAcaThreads, 0, s>>>(A);
-    HM_LAUNCH_CHECK();
+  if constexpr (OP == kOpColloc) {
+    if (cnt[2] > 0) {
+      k_aca_wave<T, 4, OP><<<grid((const void*)k_aca_wave<T, 4, OP>, kAcaThreads,
+                                  ceil_div(cnt[2], kAcaWaves)),
+                             kAcaThreads, 0, s>>>(A);
+      HM_LAUNCH_CHECK();
+    }
+    if (cnt[3] > 0) {
+      k_aca_wave<T, 2, OP><<<grid((const void*)k_aca_wave<T, 2, OP>, kAcaThreads,
+                                  ceil_div(cnt[3], 2 * kAcaWaves)),
+                             kAcaThreads, 0, s>>>(A);
+      HM_LAUNCH_CHECK();
+    }
   }
   if (cnt[4] > 0) {
-    k_aca_wave<T, 1><<<grid((const void*)k_aca_wave<T, 1>, kAcaThreads, ceil_div(cnt[4], 4 * kAcaWaves)),
+    k_aca_wave<T, 1, OP><<<grid((const void*)k_aca_wave<T, 1, OP>, kAcaThreads, ceil_div(cnt[4], 4 * kAcaWaves)),
                        kAcaThreads, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
@@ -1394,15 +1719,46 @@ __global__ void k_widen_i32(const int32_t* __restrict__ a, int64_t n, int64_t* _
 
 // ------------------------------------------------------------------ host side
 template <typename T>
-void launch_entries(const Geom<T>& g, const int32_t* inv, const int32_t* rows, const int32_t* cols,
-                    int64_t cnt, double* out, hipStream_t s) {
-  k_entries<T><<<grid_for(cnt, 256), 256, 0, s>>>(g, inv, rows, cols, cnt, out);
+void launch_entries(const Geom<T>& g, int op, const int32_t* inv, const int32_t* rows,
+                    const int32_t* cols, int64_t cnt, double* out, hipStream_t s) {
+  const GaussRule R = gauss_rule01();
+  if (op == kOpGalerkin)
+    k_entries<T, kOpGalerkin><<<grid_for(cnt, 4, 1 << 20), 256, 0, s>>>(g, R, inv, rows, cols, cnt, out);
+  else
+    k_entries<T, kOpColloc><<<grid_for(cnt, 4, 1 << 20), 256, 0, s>>>(g, R, inv, rows, cols, cnt, out);
   HM_LAUNCH_CHECK();
 }
-template void launch_entries<float>(const Geom<float>&, const int32_t*, const int32_t*,
+template void launch_entries<float>(const Geom<float>&, int, const int32_t*, const int32_t*,
                                     const int32_t*, int64_t, double*, hipStream_t);
-template void launch_entries<double>(const Geom<double>&, const int32_t*, const int32_t*,
+template void launch_entries<double>(const Geom<double>&, int, const int32_t*, const int32_t*,
                                      const int32_t*, int64_t, double*, hipStream_t);
+
+// Gauss-Legendre nodes and weights on [0, 1]: the roots of the Legendre
+// polynomial P_q by Newton's method from the Chebyshev-like first guesses,
+// weights 2 / ((1 - x^2) P_q'(x)^2), both mapped from [-1, 1].
+GaussRule gauss_rule01() {
+  GaussRule R{};
+  const int q = kGalQ;
+  for (int k = 0; k < q; ++k) {
+    double x = std::cos(M_PI * (k + 0.75) / (q + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int l = 2; l <= q; ++l) {
+        const double p2 = ((2.0 * l - 1.0) * x * p1 - (l - 1.0) * p0) / l;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    R.x[k] = 0.5 * (x + 1.0);
+    R.w[k] = 1.0 / ((1.0 - x * x) * dp * dp);   // (2 / ((1 - x^2) P'^2)) / 2
+  }
+  return R;
+}
 
 void launch_inverse_perm(const int32_t* perm, int64_t n, int32_t* inv, hipStream_t s) {
   k_inverse_perm<<<grid_for(n, 256), 256, 0, s>>>(perm, n, inv);
@@ -1569,8 +1925,17 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   run_parts.push_back(runD);
   colmap_parts.push_back({colmapD, PD.cols});
   if (PD.np > 0) {
-    k_near<T><<<grid_for(PD.np, 1, 1 << 20), 256, 0, s>>>(g, PD.sidx, PD.ib, PD.ilf, PD.np,
-                                                          in.dns, in.cl, L, PD.offI, D);
+    const unsigned gn = grid_for(PD.np, 1, 1 << 20);
+    if (in.op == kOpGalerkin) {
+      k_near<T, kOpGalerkin><<<gn, 256, 0, s>>>(g, PD.sidx, PD.ib, PD.ilf, PD.np, in.dns, in.cl, L,
+                                                PD.offI, D);
+      HM_LAUNCH_CHECK();
+      k_near_singular<T><<<gn, 256, 0, s>>>(g, gauss_rule01(), PD.sidx, PD.ib, PD.ilf, PD.np,
+                                            in.dns, in.cl, L, PD.offI, D);
+    } else {
+      k_near<T, kOpColloc><<<gn, 256, 0, s>>>(g, PD.sidx, PD.ib, PD.ilf, PD.np, in.dns, in.cl, L,
+                                              PD.offI, D);
+    }
     HM_LAUNCH_CHECK();
   }
   // slice addresses of the dense items, by (block, row leaf)
@@ -1671,6 +2036,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     int64_t* rsize = ta.get<int64_t>(nl);
     int64_t* roff = ta.get<int64_t>(nl + 1);
     int* head = ta.get<int>(kAcaClasses);
+    const auto aca = in.op == kOpGalerkin ? run_aca<T, kOpGalerkin> : run_aca<T, kOpColloc>;
     int64_t b0 = 0;
     while (b0 < nl) {
       int64_t b1 = hoff.empty() ? nl : b0 + 1;
@@ -1680,7 +2046,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       k_slot_desc<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, k1, slot_off + b0,
                                                        slot0, pool, nullptr, desc + b0);
       HM_LAUNCH_CHECK();
-      run_aca<T>(g, in.lr + b0, nb, in.cl, desc + b0, k1, in.eps, nullptr, cflags, coffs, clists,
+      aca(g, in.lr + b0, nb, in.cl, desc + b0, k1, in.eps, nullptr, cflags, coffs, clists,
                  head, out.rank + b0, out.info + b0, tmp, s);
       T* pool2 = nullptr;
       if (k1 < kmax) {
@@ -1693,7 +2059,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
           k_slot_desc<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, kmax, roff, 0,
                                                            pool2, rmark, desc + b0);
           HM_LAUNCH_CHECK();
-          run_aca<T>(g, in.lr + b0, nb, in.cl, desc + b0, kmax, in.eps, rmark, cflags, coffs,
+          aca(g, in.lr + b0, nb, in.cl, desc + b0, kmax, in.eps, rmark, cflags, coffs,
                      clists, head, out.rank + b0, out.info + b0, tmp, s);
           ++out.aca_reruns;
         }

@@ -45,7 +45,7 @@ def _tri():
 @pytest.mark.parametrize("field,value", [
     ("leaf_size", 0), ("leaf_size", 65), ("max_rank", -1), ("max_rank", 257),
     ("precision", 7), ("eta", -1.0), ("eta", float("inf")), ("aca_eps", -1e-3),
-    ("aca_eps", float("nan")), ("mem_limit_bytes", -5), ("flags", 16), ("flags", 8)])
+    ("aca_eps", float("nan")), ("mem_limit_bytes", -5), ("flags", 16), ("flags", 32)])
 def test_invalid_params_rejected(field, value):
     V, T = _tri()
     p = hm.hm_params_default()
