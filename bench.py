@@ -22,6 +22,11 @@ and the CPU oracle baseline are extra keys.
 
 The CPU leg (the oracle's exact rows of the direct product, on a process
 pool) runs first, before the GPU is touched.
+
+--operator galerkin runs the same pass on the Galerkin matrix (piecewise
+constants, HM_GALERKIN) and solves it by CG (HM_SOLVE_CG), the paper's own
+discretisation and solver; its CPU leg and error reference are the Galerkin
+oracle's exact rows.
 """
 from __future__ import annotations
 
@@ -58,12 +63,12 @@ def _rows_worker(args):
     return _OP.matvec_rows(x, rows)
 
 
-def cpu_baseline(V, T, x, rows, workers):
+def cpu_baseline(V, T, x, rows, workers, operator="collocation"):
     """Oracle: exact rows of the dense product A x, over a process pool."""
     global _OP
     import multiprocessing as mp
-    from oracle import bem
-    _OP = bem.Operator(V, T)
+    from oracle import bem, galerkin
+    _OP = galerkin.GalerkinOperator(V, T) if operator == "galerkin" else bem.Operator(V, T)
     chunks = [rows[i::workers] for i in range(workers)]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
@@ -86,7 +91,7 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(level, leaf, eps, form, vec):
+def measured_traffic(level, leaf, eps, form, vec, operator="collocation"):
     """HBM bytes per launch of the dominant kernel from the stored counter
     summary, or None if it is missing, for another workload, or stale."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -100,7 +105,8 @@ def measured_traffic(level, leaf, eps, form, vec):
     try:
         if (kv["sources_sha256"] != sources_sha256() or int(kv["level"]) != level
                 or int(kv["leaf"]) != leaf or float(kv["eps"]) != eps or kv["form"] != form
-                or kv.get("vectors", "f64") != vec):
+                or kv.get("vectors", "f64") != vec
+                or kv.get("operator", "collocation") != operator):
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -156,17 +162,19 @@ def phase2_bytes(st, form, s_vec, s_acc, nrhs=1):
 # entry (the rsqrt counted as one).  ACA updates are not counted.  Packed FP32
 # instructions are disabled in every build, so the FP32 peak is the
 # non-packed vector rate, the same as FP64.
-FLOPS_PER_ENTRY = 66
+# A Galerkin entry is the same sum at each of the seven nodes of the row
+# triangle: 7 x 66 (its singular entries, about 13 per row, are not counted).
+FLOPS_PER_ENTRY = {"collocation": 66, "galerkin": 7 * 66}
 VALU_PEAK_TFLOPS = {"f32": 78.6, "f16": 78.6, "f64": 78.6}
 
 
-def setup_roofline(o, form):
+def setup_roofline(o, form, operator="collocation"):
     """ALU roofline of the near field + ACA phases: entry evaluations (dense
     entries + ACA rows and columns) x FLOPS_PER_ENTRY over their time."""
     st = o["stats"]
     ms = o["setup_phases_ms"]["near_field"] + o["setup_phases_ms"]["aca"]
     ent = st["dense_entries"] + st["aca_entry_evals"]
-    tf = ent * FLOPS_PER_ENTRY / (ms * 1e-3) / 1e12
+    tf = ent * FLOPS_PER_ENTRY[operator] / (ms * 1e-3) / 1e12
     return {"bound": "alu", "entries": ent, "entries_per_s": round(ent / (ms * 1e-3), 1),
             "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS[form], "unit": "TFLOP/s",
             "frac": round(tf / VALU_PEAK_TFLOPS[form], 5),
@@ -195,7 +203,7 @@ def run_form(hm, torch, V, T, args, spec, X, X1, f, keep):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     H = hm.HMatrix(V, T, leaf_size=args.leaf, eta=1.0, eps=eps, max_rank=64, precision=prec,
-                   profile=True)
+                   profile=True, operator=args.operator)
     setup_s = time.perf_counter() - t0
     st = H.stats()
     xv = X[vec]
@@ -212,7 +220,7 @@ def run_form(hm, torch, V, T, args, spec, X, X1, f, keep):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sig, info, status = H.solve(f, tol=args.gmres_tol, restart=100, max_iter=3000,
-                                refine=refine, inner_tol=args.inner_tol)
+                                refine=refine, inner_tol=args.inner_tol, method=spec["method"])
     solve_s = time.perf_counter() - t0
     if keep is not None:
         keep["y1"] = y1.double().cpu().numpy()
@@ -370,6 +378,8 @@ def main():
     ap.add_argument("--workload", default="single", choices=["single", "batch48"],
                     help="single: one icosphere (default); batch48: 48 perturbed spheres of "
                          "5,120 / 20,480 / 81,920 triangles in one handle, 8 right-hand sides")
+    ap.add_argument("--operator", default="collocation", choices=["collocation", "galerkin"],
+                    help="galerkin: the Galerkin matrix (HM_GALERKIN), solved by CG")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -388,11 +398,15 @@ def main():
 
     from synthetic import icosphere, mesh_sha256, normal_columns, sample_rows
     forms = args.forms.split(",")
+    gal = args.operator == "galerkin"
+    if gal and "--cpu-rows" not in sys.argv:
+        args.cpu_rows = 256            # a Galerkin row costs about seven collocation rows
     specs = []
     for p in forms:
         vec = args.vec if args.vec != "auto" else ("f64" if p == "f64" else "f32")
         specs.append(dict(form=p, eps=args.eps if args.eps is not None else DEFAULT_EPS[p],
-                          vec=vec, refine=p != "f64"))
+                          vec=vec, refine=p != "f64" and not gal,
+                          method="cg" if gal else "gmres"))
     V, T = icosphere(args.level)
     n = T.shape[0]
     X = normal_columns(n, 16, seed=0)
@@ -402,7 +416,7 @@ def main():
     # reference rows of A x1: the stored oracle rows (4,096) when they are for
     # this mesh, else the rows computed by the CPU leg below
     ref_rows, ref_y = None, None
-    if os.path.exists(GOLDEN_L8):
+    if os.path.exists(GOLDEN_L8) and not gal:
         g = np.load(GOLDEN_L8, allow_pickle=False)
         if str(g["mesh_sha256"]) == mesh_sha256(V, T) and int(g["x_seed"]) == 0:
             ref_rows, ref_y = g["rows"], g["y"][:, 0]
@@ -413,7 +427,7 @@ def main():
         workers = max(1, min(CPU_SHARE, len(os.sched_getaffinity(0))))
         print(f"# cpu leg: {rows.size} oracle rows at N={n} on {workers} processes",
               file=sys.stderr, flush=True)
-        y_cpu, t_cpu = cpu_baseline(V, T, x1, rows, workers)
+        y_cpu, t_cpu = cpu_baseline(V, T, x1, rows, workers, args.operator)
         cpu = dict(t=t_cpu, workers=workers, rows=rows.size)
         print(f"# cpu leg: {t_cpu:.1f} s", file=sys.stderr, flush=True)
         if ref_rows is None:
@@ -488,7 +502,8 @@ def main():
         "dtype": mf,
         "data": "synthetic",
         "config": {"workload": f"unit icosphere L={args.level} (N={n}) Laplace single-layer "
-                               f"collocation, leaf {args.leaf}, eta 1; timed form {mf} at ACA eps "
+                               f"{'Galerkin (piecewise constants), CG' if gal else 'collocation'}"
+                               f", leaf {args.leaf}, eta 1; timed form {mf} at ACA eps "
                                f"{main_spec['eps']:g} with {main_spec['vec']} vectors; product x: "
                                f"N(0,1) seed 0; solve f: N(0,1) seed 2 to relative residual "
                                f"{args.gmres_tol:g}; error on "
@@ -512,9 +527,9 @@ def main():
             "unit": "GB/s",
             "frac": round(M["phase2_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.level, args.leaf, main_spec["eps"], mf,
-                                        main_spec["vec"]),
+                                        main_spec["vec"], args.operator),
         },
-        "setup_roofline": {p: setup_roofline(out[p], p) for p in out},
+        "setup_roofline": {p: setup_roofline(out[p], p, args.operator) for p in out},
         "forms": out,
     }
     if cpu is not None:
@@ -526,7 +541,8 @@ def main():
             "unit": "GB/s",
             "cores": cpu["workers"],
             "kind": "oracle",
-            "sample": f"{rows.size} exact rows of the dense product A x (7-point rule, FP64) at "
+            "sample": f"{rows.size} exact rows of the dense product A x "
+                      f"({'Galerkin oracle' if gal else '7-point rule'}, FP64) at "
                       f"N={n} in {cpu['t']:.2f} s on {cpu['workers']} processes; full product "
                       f"extrapolated x{n / rows.size:.0f} to {full_s:.1f} s; reported as the "
                       f"{mf} H-matvec's algorithmic bytes / that time",
