@@ -518,32 +518,70 @@ __global__ __launch_bounds__(256) void k_fwd2_sum(MvLeaves L, const int32_t* __r
 }
 
 // ------------------------------------------------------------------ many right-hand sides on MFMA
-// With 8 or 16 right-hand sides in double, both forward phases are small
-// dense products with a long inner dimension: phase 1 is T_b = V_b^T X
-// (terms x right-hand sides, inner dimension = rows of sigma), phase 2 is
+// With 8 or 16 right-hand sides, both forward phases are small dense
+// products with a long inner dimension: phase 1 is T_b = V_b^T X (terms x
+// right-hand sides, inner dimension = rows of sigma), phase 2 is
 // Y_c += P Z (rows of the leaf x right-hand sides, inner dimension = panel
-// columns).  Both run on v_mfma_f64_16x16x4: C[16][16] += A[16][4] B[4][16]
-// with, for lane l, a = A[l % 16][l / 16], b = B[l / 16][l % 16], and item
-// j of the accumulator = C[4 j + l / 16][l % 16].  Stored values are
-// widened to double; accumulation is in double as on the vector path.
+// columns).  Both run on 16 x 16 x 4 matrix instructions, C[16][16] +=
+// A[16][4] B[4][16] with, for lane l, a = A[l % 16][l / 16] and
+// b = B[l / 16][l % 16]: v_mfma_f64_16x16x4 for double vectors (item j of
+// the accumulator = C[4 j + l / 16][l % 16]), v_mfma_f32_16x16x4 for float
+// vectors (item j = C[4 (l / 16) + j][l % 16]).  Stored values are widened
+// to the accumulation type, double or float as on the vector path.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ inline f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename A>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using V = f64x4;
+  // row of accumulator item j in lane group q = l / 16
+  __device__ static inline int row(int j, int q) { return 4 * j + q; }
+};
+template <>
+struct Mfma<float> {
+  using V = f32x4;
+  __device__ static inline int row(int j, int q) { return 4 * q + j; }
+};
 
-template <typename T>
-__device__ inline double widen(T v) { return (double)v; }
+template <typename A, typename T>
+__device__ inline A widen(T v) { return (A)v; }
 
-// Phase 1: one wavefront per admissible block, term tiles of 16 (up to four
-// per pass), rows in quads.  NTL term tiles of one pass: two row quads at a
-// time, every load unconditional (clamped to the slice, the value zeroed
-// outside it) and every product issued, so no branch surrounds an MFMA; a
-// quad past the slice contributes exact zeros; rows go in in order.
-template <typename T, int NR, int NTL>
-__device__ inline void fwd1x_pass(const LrMeta& M, const MvLeaves& L,
-                                  const double* __restrict__ zx, int tg, int r, int lr, int lq,
-                                  f64x4 (&acc)[4]) {
+// Four consecutive stored values (a 16-byte FP32 granule, two FP64
+// granules, an 8-byte FP16 granule), widened to A; streamed once per
+// product, so the loads are non-temporal.
+template <typename A, typename T>
+__device__ inline void load4(const T* p, A (&o)[4]) {
+  if constexpr (std::is_same<T, double>::value) {
+    const f64x2 u = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p));
+    const f64x2 v = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(p + 2));
+    o[0] = (A)u.x; o[1] = (A)u.y; o[2] = (A)v.x; o[3] = (A)v.y;
+  } else if constexpr (std::is_same<T, float>::value) {
+    const f32x4 u = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    o[0] = (A)u.x; o[1] = (A)u.y; o[2] = (A)u.z; o[3] = (A)u.w;
+  } else {
+    const f16x4 u = __builtin_nontemporal_load(reinterpret_cast<const f16x4*>(p));
+    o[0] = (A)u.x; o[1] = (A)u.y; o[2] = (A)u.z; o[3] = (A)u.w;
+  }
+}
+
+// Phase 1 for FP64 and FP16 stored factors: term tiles of 16 (up to four
+// per pass), rows in quads (lane group lq takes row 4 i + lq of quad i), two
+// quads at a time, every load unconditional (clamped to the slice, the value
+// zeroed outside it) and every product issued, so no branch surrounds an
+// MFMA; a quad past the slice contributes exact zeros; rows go in in order.
+// (For these two the granule form below was slower: 29 against 19 ms (FP64)
+// and 10.6 against 10.0 ms (FP16) for the 16-column phase at N = 1,310,720.)
+template <typename T, typename A, int NR, int NTL>
+__device__ inline void fwd1x_pass_rows(const LrMeta& M, const MvLeaves& L,
+                                       const A* __restrict__ zx, int tg, int r, int lr, int lq,
+                                       typename Mfma<A>::V (&acc)[4]) {
   constexpr int IU = 2;
   const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
   int lo = L.lo[M.sf];                    // the leaves of sigma are consecutive
@@ -551,18 +589,18 @@ __device__ inline void fwd1x_pass(const LrMeta& M, const MvLeaves& L,
     const int m = L.m[lf];
     const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
     for (int i00 = 0; i00 < m; i00 += 4 * IU) {
-      double bv[IU], av[IU][NTL];
+      A bv[IU], av[IU][NTL];
 #pragma unroll
       for (int u = 0; u < IU; ++u) {
         const int i = i00 + 4 * u + lq;
         const bool ok = i < m;
         const int ic = ok ? i : m - 1;
-        bv[u] = (ok && lr < NR) ? zx[(int64_t)(lo + ic) * NR + lr] : 0.0;
+        bv[u] = (ok && lr < NR) ? zx[(int64_t)(lo + ic) * NR + lr] : (A)0;
 #pragma unroll
         for (int t = 0; t < NTL; ++t) {
           const int term = tg + t * 16 + lr;
           const T v = S[(int64_t)min(term, r - 1) * ld + ic];
-          av[u][t] = (ok && term < r) ? widen(v) : 0.0;
+          av[u][t] = (ok && term < r) ? widen<A>(v) : (A)0;
         }
       }
 #pragma unroll
@@ -575,11 +613,74 @@ __device__ inline void fwd1x_pass(const LrMeta& M, const MvLeaves& L,
   }
 }
 
-template <typename T, int NR>
+// Phase 1 for FP32 stored factors: one wavefront per admissible block, term
+// tiles of 16 (up to four per pass), rows in tiles of 16.  The inner dimension may be summed in any
+// order, so lane (term lr, quad lq) reads the four consecutive rows
+// 4 lq .. 4 lq + 3 of a tile as one granule and feeds them to four
+// instructions: step e takes row 4 lq + e of the tile from lane group lq,
+// and the x values follow the same rows.  Four tiles are in flight, every
+// load unconditional (clamped to the slice, the value zeroed outside it)
+// and every product issued, so no branch surrounds an MFMA.  Rows in
+// [m, ld) of a slice are zero padding; granules that start at or past m
+// are zeroed.
+template <typename T, typename A, int NR, int NTL>
+__device__ inline void fwd1x_pass_gran(const LrMeta& M, const MvLeaves& L,
+                                       const A* __restrict__ zx, int tg, int r, int lr, int lq,
+                                       typename Mfma<A>::V (&acc)[4]) {
+  constexpr int IU = 4;
+  const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
+  int lo = L.lo[M.sf];                    // the leaves of sigma are consecutive
+  int tc[NTL];                            // clamped term of each tile
+  bool tok[NTL];
+#pragma unroll
+  for (int t = 0; t < NTL; ++t) {
+    const int term = tg + t * 16 + lr;
+    tok[t] = term < r;
+    tc[t] = tok[t] ? term : r - 1;
+  }
+  const bool rhs = lr < NR;
+  for (int lf = M.sf; lf <= M.sl; ++lf) {
+    const int m = L.m[lf];
+    const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
+    for (int i00 = 0; i00 < m; i00 += 16 * IU) {
+      A av[IU][NTL][4], bv[IU][4];
+#pragma unroll
+      for (int u = 0; u < IU; ++u) {
+        const int i0 = i00 + 16 * u + 4 * lq;       // first row of the lane's granule
+        const bool okg = i0 < m;
+        const int ig = okg ? i0 : 0;
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+          A v[4];
+          load4<A, T>(S + (int64_t)tc[t] * ld + ig, v);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) av[u][t][e] = (okg && tok[t]) ? v[e] : (A)0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool okr = rhs && i0 + e < m;
+          const A x = zx[(int64_t)(lo + (okr ? i0 + e : 0)) * NR + (rhs ? lr : 0)];
+          bv[u][e] = okr ? x : (A)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < IU; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av[u][t][e], bv[u][e], acc[t]);
+    }
+    S += (int64_t)ld * r;
+    lo += m;
+  }
+}
+
+template <typename T, typename A, int NR>
 __global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, int64_t nl,
-                                               MvLeaves L, const double* __restrict__ zx,
-                                               double* __restrict__ zt, int64_t n,
+                                               MvLeaves L, const A* __restrict__ zx,
+                                               A* __restrict__ zt, int64_t n,
                                                const float* __restrict__ su) {
+  using V = typename Mfma<A>::V;
   static_assert(NR == 8 || NR == 16, "MFMA phase 1 takes 8 or 16 right-hand sides");
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lq = lane >> 4;     // a: term lr, row lq; b: row lq, rhs lr
@@ -591,23 +692,32 @@ __global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, 
     if (r == 0) continue;
     for (int tg = 0; tg < r; tg += 64) {
       const int ntile = min(4, (r - tg + 15) / 16);
-      f64x4 acc[4];
+      V acc[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-      switch (ntile) {                        // uniform over the wavefront
-        case 1: fwd1x_pass<T, NR, 1>(M, L, zx, tg, r, lr, lq, acc); break;
-        case 2: fwd1x_pass<T, NR, 2>(M, L, zx, tg, r, lr, lq, acc); break;
-        case 3: fwd1x_pass<T, NR, 3>(M, L, zx, tg, r, lr, lq, acc); break;
-        default: fwd1x_pass<T, NR, 4>(M, L, zx, tg, r, lr, lq, acc); break;
+      for (int t = 0; t < 4; ++t) acc[t] = V{0, 0, 0, 0};
+      if constexpr (!std::is_same<T, float>::value) {
+        switch (ntile) {                      // uniform over the wavefront
+          case 1: fwd1x_pass_rows<T, A, NR, 1>(M, L, zx, tg, r, lr, lq, acc); break;
+          case 2: fwd1x_pass_rows<T, A, NR, 2>(M, L, zx, tg, r, lr, lq, acc); break;
+          case 3: fwd1x_pass_rows<T, A, NR, 3>(M, L, zx, tg, r, lr, lq, acc); break;
+          default: fwd1x_pass_rows<T, A, NR, 4>(M, L, zx, tg, r, lr, lq, acc); break;
+        }
+      } else {
+        switch (ntile) {
+          case 1: fwd1x_pass_gran<T, A, NR, 1>(M, L, zx, tg, r, lr, lq, acc); break;
+          case 2: fwd1x_pass_gran<T, A, NR, 2>(M, L, zx, tg, r, lr, lq, acc); break;
+          case 3: fwd1x_pass_gran<T, A, NR, 3>(M, L, zx, tg, r, lr, lq, acc); break;
+          default: fwd1x_pass_gran<T, A, NR, 4>(M, L, zx, tg, r, lr, lq, acc); break;
+        }
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         if (t < ntile) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const int term = tg + t * 16 + 4 * j + lq;
+            const int term = tg + t * 16 + Mfma<A>::row(j, lq);
             if (term < r && lr < NR) {
-              const double sc = su ? (double)su[M.toff + term] : 1.0;
+              const A sc = su ? (A)su[M.toff + term] : (A)1;
               zt[(n + M.toff + term) * NR + lr] = acc[t][j] * sc;
             }
           }
@@ -622,24 +732,24 @@ __global__ __launch_bounds__(256) void k_fwd1x(const LrMeta* __restrict__ meta, 
 // value zeroed outside it) and every product issued, so the loop has no
 // branch around an MFMA and the accumulators stay in place.  A quad past the
 // tile contributes exact zeros; the products go in in column order.
-template <typename E, int NR, int NT, int KQ>
+template <typename E, typename A, int NR, int NT, int KQ>
 __device__ inline void fwd2x_tile(const E* __restrict__ P, int64_t cbase, int ld, int tw,
-                                  const double* __restrict__ zs, int wave, int lr, int lq,
-                                  f64x4 (&acc)[4]) {
+                                  const A* __restrict__ zs, int wave, int lr, int lq,
+                                  typename Mfma<A>::V (&acc)[4]) {
   for (int q0 = wave; q0 * 4 < tw; q0 += 4 * KQ) {
-    double bv[KQ], av[KQ][NT];
+    A bv[KQ], av[KQ][NT];
 #pragma unroll
     for (int u = 0; u < KQ; ++u) {
       const int col = (q0 + 4 * u) * 4 + lq;
       const bool okc = col < tw;
       const int colc = okc ? col : tw - 1;
-      bv[u] = (okc && lr < NR) ? zs[colc * NR + lr] : 0.0;
+      bv[u] = (okc && lr < NR) ? zs[colc * NR + lr] : (A)0;
       const E* pc = P + (cbase + colc) * ld;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int row = t * 16 + lr;
         const E v = pc[min(row, ld - 1)];
-        av[u][t] = (okc && row < ld) ? widen(v) : 0.0;
+        av[u][t] = (okc && row < ld) ? widen<A>(v) : (A)0;
       }
     }
 #pragma unroll
@@ -649,15 +759,46 @@ __device__ inline void fwd2x_tile(const E* __restrict__ P, int64_t cbase, int ld
   }
 }
 
-template <typename E, int NR, int KQ>
+template <typename E, typename A, int NR, int KQ>
 __device__ inline void fwd2x_tile_nt(int nrt, const E* __restrict__ P, int64_t cbase, int ld,
-                                     int tw, const double* __restrict__ zs, int wave, int lr,
-                                     int lq, f64x4 (&acc)[4]) {
+                                     int tw, const A* __restrict__ zs, int wave, int lr,
+                                     int lq, typename Mfma<A>::V (&acc)[4]) {
   switch (nrt) {                                        // uniform over the workgroup
-    case 1: fwd2x_tile<E, NR, 1, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
-    case 2: fwd2x_tile<E, NR, 2, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
-    case 3: fwd2x_tile<E, NR, 3, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
-    default: fwd2x_tile<E, NR, 4, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    case 1: fwd2x_tile<E, A, NR, 1, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    case 2: fwd2x_tile<E, A, NR, 2, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    case 3: fwd2x_tile<E, A, NR, 3, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+    default: fwd2x_tile<E, A, NR, 4, KQ>(P, cbase, ld, tw, zs, wave, lr, lq, acc); break;
+  }
+}
+
+// The same with granule loads: lane (i = lr, column lq of a quad) reads
+// rows 4 i .. 4 i + 3 of its column at once and gives row 4 i + t to the
+// accumulator of tile t, so tile t holds the rows 4 i + t (i = 0..15) and
+// every panel column is one contiguous read of 16 lanes.  Lanes with
+// 4 i >= ld contribute zeros.
+template <typename E, typename A, int NR, int KQ>
+__device__ inline void fwd2x_gran(const E* __restrict__ P, int64_t cbase, int ld, int tw,
+                                  const A* __restrict__ zs, int wave, int lr, int lq,
+                                  typename Mfma<A>::V (&acc)[4]) {
+  const bool okr = 4 * lr < ld;
+  const int rg = okr ? 4 * lr : 0;
+  for (int q0 = wave; q0 * 4 < tw; q0 += 4 * KQ) {
+    A bv[KQ], av[KQ][4];
+#pragma unroll
+    for (int u = 0; u < KQ; ++u) {
+      const int col = (q0 + 4 * u) * 4 + lq;
+      const bool okc = col < tw;
+      const int colc = okc ? col : tw - 1;
+      bv[u] = (okc && lr < NR) ? zs[colc * NR + lr] : (A)0;
+      A v[4];
+      load4<A, E>(P + (cbase + colc) * ld + rg, v);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) av[u][t] = (okc && okr) ? v[t] : (A)0;
+    }
+#pragma unroll
+    for (int u = 0; u < KQ; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = mfma16(av[u][t], bv[u], acc[t]);
   }
 }
 
@@ -665,20 +806,21 @@ __device__ inline void fwd2x_tile_nt(int nrt, const E* __restrict__ P, int64_t c
 // LDS per tile, each wavefront takes column quads round-robin and keeps one
 // accumulator per 16-row tile of the leaf; the four wavefronts are added in
 // LDS in a fixed order.
-template <typename TD, typename TL, int NR>
+template <typename TD, typename TL, typename A, int NR, bool GR>
 __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvLeaves L,
                                                const Unit* __restrict__ units, int64_t nunits,
                                                const int32_t* __restrict__ colmap,
-                                               const double* __restrict__ z,
-                                               double* __restrict__ ypart, int ldmax) {
+                                               const A* __restrict__ z,
+                                               A* __restrict__ ypart, int ldmax) {
+  using V = typename Mfma<A>::V;
   static_assert(NR == 8 || NR == 16, "MFMA phase 2 takes 8 or 16 right-hand sides");
   constexpr int kQuads = 4;
   // the z tile and the final combination of the wavefronts share one LDS
   // buffer (the tile is consumed before the combination starts)
   constexpr int kTile = (4 * kMaxLeaf * NR) / NR;     // columns: 256
-  __shared__ double lbuf[4 * kMaxLeaf * NR];
-  double* zs = lbuf;
-  double (*ybuf)[kMaxLeaf][NR] = reinterpret_cast<double (*)[kMaxLeaf][NR]>(lbuf);
+  __shared__ A lbuf[4 * kMaxLeaf * NR];
+  A* zs = lbuf;
+  A (*ybuf)[kMaxLeaf][NR] = reinterpret_cast<A (*)[kMaxLeaf][NR]>(lbuf);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lq = lane >> 4;     // a: row lr, column lq; b: column lq, rhs lr
   const int64_t per = (nunits + kXcds - 1) / kXcds;
@@ -693,9 +835,9 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
     const Run rn = runs[(int64_t)U.run * L.nleaf + c];
     const bool dense = std::is_same<TD, TL>::value || U.run == 0;
     const int32_t* map = colmap + rn.col0 + U.a;
-    f64x4 acc[4];
+    V acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < 4; ++t) acc[t] = V{0, 0, 0, 0};
     for (int t0 = 0; t0 < U.w; t0 += kTile) {
       const int tw = min(kTile, U.w - t0);
       __syncthreads();                                  // the previous tile is consumed
@@ -705,26 +847,35 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
       }
       __syncthreads();
       const int64_t cbase = (int64_t)U.a + t0;          // first panel column of the tile
-      if (dense)
-        fwd2x_tile_nt<TD, NR, kQuads>(nrt, reinterpret_cast<const TD*>((uintptr_t)rn.data), cbase,
-                                      ld, tw, zs, wave, lr, lq, acc);
-      else
-        fwd2x_tile_nt<TL, NR, kQuads>(nrt, reinterpret_cast<const TL*>((uintptr_t)rn.data), cbase,
-                                      ld, tw, zs, wave, lr, lq, acc);
+      if constexpr (GR) {
+        if (dense)
+          fwd2x_gran<TD, A, NR, kQuads>(reinterpret_cast<const TD*>((uintptr_t)rn.data), cbase,
+                                        ld, tw, zs, wave, lr, lq, acc);
+        else
+          fwd2x_gran<TL, A, NR, kQuads>(reinterpret_cast<const TL*>((uintptr_t)rn.data), cbase,
+                                        ld, tw, zs, wave, lr, lq, acc);
+      } else {
+        if (dense)
+          fwd2x_tile_nt<TD, A, NR, kQuads>(nrt, reinterpret_cast<const TD*>((uintptr_t)rn.data),
+                                           cbase, ld, tw, zs, wave, lr, lq, acc);
+        else
+          fwd2x_tile_nt<TL, A, NR, kQuads>(nrt, reinterpret_cast<const TL*>((uintptr_t)rn.data),
+                                           cbase, ld, tw, zs, wave, lr, lq, acc);
+      }
     }
     __syncthreads();                                    // the last tile is consumed
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      if (t < nrt) {
+      if (GR || t < nrt) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int row = t * 16 + 4 * j + lq;
+          const int row = GR ? 4 * Mfma<A>::row(j, lq) + t : t * 16 + Mfma<A>::row(j, lq);
           if (row < kMaxLeaf && lr < NR) ybuf[wave][row][lr] = acc[t][j];
         }
       }
     }
     __syncthreads();
-    double* yp = ypart + u * ldmax * NR;
+    A* yp = ypart + u * ldmax * NR;
     for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
       const int row = e / NR, k = e % NR;
       yp[e] = ((ybuf[0][row][k] + ybuf[1][row][k]) + ybuf[2][row][k]) + ybuf[3][row][k];
@@ -1055,8 +1206,8 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
     if (P.nlr > 0) {
-      if constexpr (std::is_same<A, double>::value && (NR == 8 || NR == 16)) {
-        k_fwd1x<TL, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, z, P.n, P.su);
+      if constexpr (NR == 8 || NR == 16) {
+        k_fwd1x<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, z, P.n, P.su);
       } else if constexpr (NR >= 4) {
         k_fwd1m<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
       } else {
@@ -1070,9 +1221,12 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
     }
     const unsigned gu = (unsigned)std::min<int64_t>(ceil_div(P.nunits, kXcds) * kXcds, P.grid);
     if (P.nunits > 0) {
-      if constexpr (std::is_same<A, double>::value && (NR == 8 || NR == 16))
-        k_fwd2x<TD, TL, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, P.colmap, z,
-                                               static_cast<A*>(P.ypart), P.ldmax);
+      // double vectors on the FP64 matrix cores; with float vectors the
+      // vector kernel streams the panels faster than the FP32 instructions
+      if constexpr (NR == 8 || NR == 16)
+        k_fwd2x<TD, TL, A, NR, true><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits,
+                                                        P.colmap, z, static_cast<A*>(P.ypart),
+                                                        P.ldmax);
       else
         k_fwd2<TD, TL, A, NR><<<gu, 256, 0, s>>>(P.runs, P.L, P.units, P.nunits, P.colmap, z,
                                                  static_cast<A*>(P.ypart), P.ldmax);

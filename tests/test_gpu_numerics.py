@@ -166,7 +166,9 @@ def test_products_every_row_tile_count(nsub, leaf, ld, prec, eps, bound):
     """Leaves padded to ld = 8, 32, 40 and 64 rows: the 16-row tiles of the
     MFMA products (1..4), the pass counts of phase 1 and the granule rows of
     the one-column kernels all occur.  Forward and transposed products with
-    1, 8 and 16 right-hand sides, every column against the dense oracle."""
+    1, 8 and 16 right-hand sides, double vectors (and float vectors for the
+    FP32 form: the single-precision MFMA passes), every column against the
+    dense oracle."""
     import paper_1806_11558_amd as hm
     from oracle import bem
     from synthetic import icosphere, normal_columns
@@ -178,15 +180,17 @@ def test_products_every_row_tile_count(nsub, leaf, ld, prec, eps, bound):
     H = hm.HMatrix(V, T, leaf_size=leaf, eps=eps, precision=prec)
     lv = H.leaves()                               # (lo, size, ld) per leaf
     assert int(lv[:, 2].max()) == ld
+    vdts = (torch.float64, torch.float32) if prec == "f32" else (torch.float64,)
     for nrhs in (1, 8, 16):
         x = normal_columns(op.n, nrhs, seed=nrhs)
-        xt = torch.tensor(x[:, 0] if nrhs == 1 else x, device=DEV)
-        y = H.matvec(xt).cpu().numpy().reshape(op.n, -1)
-        yT = H.matvec_T(xt).cpu().numpy().reshape(op.n, -1)
         ref, refT = A @ x, A.T @ x
-        for k in range(nrhs):
-            assert rel2(y[:, k], ref[:, k]) <= bound, (nrhs, k)
-            assert rel2(yT[:, k], refT[:, k]) <= bound, (nrhs, k)
+        for vdt in vdts:
+            xt = torch.tensor(x[:, 0] if nrhs == 1 else x, dtype=vdt, device=DEV)
+            y = H.matvec(xt).double().cpu().numpy().reshape(op.n, -1)
+            yT = H.matvec_T(xt).double().cpu().numpy().reshape(op.n, -1)
+            for k in range(nrhs):
+                assert rel2(y[:, k], ref[:, k]) <= bound, (nrhs, k, vdt)
+                assert rel2(yT[:, k], refT[:, k]) <= bound, (nrhs, k, vdt)
     H.free()
 
 
@@ -205,13 +209,14 @@ def test_products_31_columns(prec, eps, bound):
     A = op.dense()
     H = hm.HMatrix(V, T, leaf_size=32, eps=eps, precision=prec)
     x = normal_columns(op.n, 31, seed=31)
-    xt = torch.tensor(x, device=DEV)
-    y = H.matvec(xt).cpu().numpy()
-    yT = H.matvec_T(xt).cpu().numpy()
     ref, refT = A @ x, A.T @ x
-    for k in range(31):
-        assert rel2(y[:, k], ref[:, k]) <= bound, k
-        assert rel2(yT[:, k], refT[:, k]) <= bound, k
+    for vdt in ((torch.float64, torch.float32) if prec == "f32" else (torch.float64,)):
+        xt = torch.tensor(x, dtype=vdt, device=DEV)
+        y = H.matvec(xt).double().cpu().numpy()
+        yT = H.matvec_T(xt).double().cpu().numpy()
+        for k in range(31):
+            assert rel2(y[:, k], ref[:, k]) <= bound, (k, vdt)
+            assert rel2(yT[:, k], refT[:, k]) <= bound, (k, vdt)
     H.free()
 
 
