@@ -273,7 +273,8 @@ def summarize(spec, rs, y_ref, rows):
 
 def run_batch48(args):
     """48 seeded perturbed spheres (seed g, level 4 + g mod 3) in one handle
-    (hm_build_batch, autotuned product schedule), FP32 form; one step =
+    (hm_build_batch, autotuned ACA binning and product schedule), FP32 form;
+    one step =
     build, 8-column products, GMRES with 8 right-hand sides per geometry
     (graph-replayed Arnoldi steps), free."""
     import torch
@@ -303,8 +304,9 @@ def run_batch48(args):
         solve = time.perf_counter() - t0
         st = H.stats()
         tune = H.tune_results().tolist()
+        aca = (H.aca_bins()[:, 1].tolist(), H.aca_tune().tolist())
         H.free()
-        return setup, ms, solve, info, int(status), st, tune
+        return setup, ms, solve, info, int(status), st, tune, aca
 
     for _ in range(args.warmup):
         step()
@@ -333,7 +335,8 @@ def run_batch48(args):
         "data": "synthetic",
         "config": {"workload": f"48 perturbed spheres (seed g, icosphere level 4 + g mod 3; "
                                f"N = {n} in one handle), leaf {args.leaf}, eta 1, ACA eps "
-                               f"{eps:g}, FP32 form, autotuned product schedule; 8 "
+                               f"{eps:g}, FP32 form, autotuned ACA binning and product "
+                               f"schedule; 8 "
                                f"right-hand sides N(0,1) seeds 1000 + g; graph GMRES to "
                                f"{tol:g}", "n": n, "nrhs": 8},
         "setup_s": round(setup, 4),
@@ -344,6 +347,9 @@ def run_batch48(args):
         "gmres_status": rs[-1][4],
         "gmres_rel_residual": rs[-1][3].rel_residual,
         "tune_unit_cols_ms": rs[-1][6],
+        "aca_bins": {"edges": [64, 128, 256, 1024, 2048, 4096, "inf"],
+                     "class": [hm.ACA_CLASSES[c] for c in rs[-1][7][0]],
+                     "tuned_bin_class_blocks_ms": rs[-1][7][1]},
         "stats": {k: st[k] for k in ("n_geom", "n_dense", "n_lr", "rank_max", "stored_bytes",
                                      "unit_cols", "aca_chunks")},
     }

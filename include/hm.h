@@ -79,10 +79,17 @@ typedef enum {
 #define HM_PROFILE 2      /* products record HIP events around each kernel on
                              the caller's stream and synchronise it at the
                              end of the call; totals via HM_Q_KERNEL_TIMES   */
-#define HM_AUTOTUNE 4     /* the build times the one-column product with
-                             each column-unit width of its schedule
-                             (512 .. 8192) on its own storage and keeps the
-                             fastest; measurements via HM_Q_TUNE             */
+#define HM_AUTOTUNE 4     /* the build picks two schedules by measurement:
+                             the ACA kernel class of every block size bin
+                             (each candidate class timed on a sample of the
+                             bin's blocks at the first-pass rank cap; via
+                             HM_Q_ACA_BINS / HM_Q_ACA_TUNE), and the
+                             column-unit width of the product (512 .. 8192,
+                             timed on the handle's own storage; via
+                             HM_Q_TUNE).  A tuned binning may change the ACA
+                             kernel of some blocks and with it the rounding
+                             of their factors (within the ACA tolerance), so
+                             two tuned builds need not agree bitwise       */
 #define HM_GALERKIN 8     /* the Galerkin matrix of Sec. 2.2 (eq.
                              linearSystem) with piecewise constants instead
                              of collocation at the centroids:
@@ -331,10 +338,18 @@ typedef enum {
   HM_Q_TUNE = 11,         /* double[k][2] (unit columns, ms per one-column
                              product) of every width the autotuner timed;
                              k = 0 without HM_AUTOTUNE                       */
-  HM_Q_DENSE_ENTRIES = 12 /* for dense block b = *(int64*)dst on entry (the
+  HM_Q_DENSE_ENTRIES = 12,/* for dense block b = *(int64*)dst on entry (the
                              order of HM_Q_DENSE_BLOCKS): its stored entries,
                              double[m][n] row-major, rows and columns in
                              Morton order of the block's clusters           */
+  HM_Q_ACA_BINS = 13,     /* int32[7][2] (largest max(m, n) of the size bin,
+                             kernel class) the batched ACA ran with; classes:
+                             0 one 1,024-thread workgroup per block, 1 one
+                             256-thread workgroup, 2, 3, 4 one wavefront with
+                             4, 2, 1 rows and columns per lane              */
+  HM_Q_ACA_TUNE = 14      /* double[k][4] (bin, class, sampled blocks, ms of
+                             one pass over them) of every candidate the ACA
+                             binning tuner timed; k = 0 without HM_AUTOTUNE */
 } hm_query_kind;
 
 #define HM_NPHASE 8        /* geometry, morton+sort, tree+boxes, partition,

@@ -527,7 +527,8 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
     if (p.mem_limit_bytes > 0) budget = std::min(budget, (p.mem_limit_bytes - h->bytes) / 3);
     SetupIn in{n, h->cl, h->cl_leaves, h->leaf_lo, h->leaf_m, h->ldpre, h->nleaf,
                h->dns, h->nd, h->lr, h->nl, p.max_rank > 0 ? p.max_rank : 64, p.aca_eps,
-               std::max<int64_t>(budget, 1 << 20), h->op};
+               std::max<int64_t>(budget, 1 << 20), h->op,
+               (p.flags & HM_AUTOTUNE) != 0};
     build_storage<T, TL>(g, in, h->sto, [h](size_t b) { return h->alloc(b); }, s);
     h->ms[4] = h->sto.ms_near;
     h->ms[5] = h->sto.ms_aca;
@@ -1325,6 +1326,28 @@ hm_status hm_query(hm_handle* h, int32_t what, void* dst, int64_t dst_bytes, int
         for (size_t k = 0; k < h->tune.size(); ++k) {
           o[2 * k] = h->tune[k][0];
           o[2 * k + 1] = h->tune[k][1];
+        }
+        return HM_OK;
+      }
+      case HM_Q_ACA_BINS: {
+        if (!check(kAcaBins * 8)) return arg_error("hm_query: destination too small");
+        int32_t* o = (int32_t*)dst;
+        for (int k = 0; k < kAcaBins; ++k) {
+          o[2 * k] = kAcaBinEdge[k];
+          o[2 * k + 1] = h->sto.bins.cls[k];
+        }
+        return HM_OK;
+      }
+      case HM_Q_ACA_TUNE: {
+        const int64_t b = (int64_t)h->sto.aca_tune.size() * 32;
+        if (!check(b)) return arg_error("hm_query: destination too small");
+        double* o = (double*)dst;
+        for (size_t k = 0; k < h->sto.aca_tune.size(); ++k) {
+          const AcaTuneRow& r = h->sto.aca_tune[k];
+          o[4 * k] = r.bin;
+          o[4 * k + 1] = r.cls;
+          o[4 * k + 2] = (double)r.blocks;
+          o[4 * k + 3] = r.ms;
         }
         return HM_OK;
       }

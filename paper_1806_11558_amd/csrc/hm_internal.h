@@ -178,6 +178,23 @@ struct MvPlan {
   MvProfile* prof;          // null unless profiling
 };
 
+// Binning of the batched ACA: blocks fall into size bins by max(m, n) (upper
+// edges kAcaBinEdge), and every bin is run by one kernel class: 0 one
+// 1,024-thread workgroup per block, 1 one 256-thread workgroup, 2..4 one
+// wavefront with 4, 2, 1 rows and columns per lane (up to 256, 128, 64).
+constexpr int kAcaBins = 7;
+constexpr int kAcaBinEdge[kAcaBins] = {64, 128, 256, 1024, 2048, 4096, 0x7fffffff};
+struct AcaBins {
+  int cls[kAcaBins];
+};
+// One measured candidate of the binning tuner: bin, kernel class, sampled
+// blocks and the time of one pass over them.
+struct AcaTuneRow {
+  int bin, cls;
+  int64_t blocks;
+  double ms;
+};
+
 // Inputs and outputs of the storage build (near field, ACA, panels).
 struct SetupIn {
   int64_t n;
@@ -195,6 +212,7 @@ struct SetupIn {
   double eps;
   int64_t pool_budget_bytes;   // upper bound for the ACA working pool
   int op;                      // kOpColloc or kOpGalerkin
+  bool tune_aca = false;       // time the ACA kernel classes per size bin, keep the fastest
 };
 struct Storage {
   int64_t D_elems = 0, dense_cols = 0;
@@ -220,6 +238,8 @@ struct Storage {
   int32_t* tbeg = nullptr;
   int64_t ntitems = 0;
   double ms_near = 0, ms_aca = 0, ms_pack = 0;
+  AcaBins bins{};                       // the binning the ACA ran with
+  std::vector<AcaTuneRow> aca_tune;     // the tuner's measurements (empty without it)
 };
 using Alloc = std::function<void*(size_t)>;
 // T: evaluation, ACA and dense storage type; TL: storage type of the

@@ -588,13 +588,12 @@ __device__ inline int piv_index(const Piv& p) {
   return (p.k == 0 && p.ni == 0) ? -1 : (int)(~p.ni);
 }
 
-// Size classes of the batched ACA, by max(m, n) of the block: 0 one
-// 1,024-thread workgroup per block (> kAcaBig), 1 one 256-thread workgroup
-// (> 256), 2..4 one wavefront per block with Q = 4, 2, 1 rows and columns
-// per lane (up to 256, 128, 64).  Each class is its own kernel (its own
-// register allocation) and its own work queue.
+// Kernel classes of the batched ACA: 0 one 1,024-thread workgroup per
+// block, 1 one 256-thread workgroup, 2..4 one wavefront per block with
+// Q = 4, 2, 1 rows and columns per lane (up to 256, 128, 64).  Each class is
+// its own kernel (its own register allocation) and its own work queue; the
+// size bins of the blocks are mapped to classes by an AcaBins table.
 constexpr int kAcaClasses = 5;
-constexpr int kAcaBig = 4096;
 constexpr int kAcaThreads = 256;
 constexpr int kAcaWaves = kAcaThreads / 64;
 
@@ -1117,21 +1116,30 @@ void k_aca_wave(AcaArgs<T> A) {
   }
 }
 
-// Class of every block (see kAcaClasses).  With mask, only blocks whose
-// mask entry is set get a class.  flags[c * nb + b] = (class == c).  With
-// wide_rows (Galerkin), every block above 64 goes to the 256-thread class:
-// the wavefront classes with 2 and 4 rows per lane and the 1,024-thread
-// class do not fit its registers.
+__device__ inline int aca_bin(int64_t mx) {
+  int k = 0;
+  while (k < kAcaBins - 1 && mx > kAcaBinEdge[k]) ++k;
+  return k;
+}
+
+// Largest max(m, n) a kernel class takes (the wavefront classes hold 64 Q
+// rows and columns).
+__host__ __device__ inline int64_t aca_class_cap(int c) {
+  return c == 2 ? 256 : (c == 3 ? 128 : (c == 4 ? 64 : INT64_MAX));
+}
+
+// Class of every block: the class of its size bin.  With mask, only blocks
+// whose mask entry is set get a class.  flags[c * nb + b] = (class == c).
 __global__ void k_aca_classes(const int2* __restrict__ blk, int64_t nb,
                               const Cluster* __restrict__ cl, const int64_t* __restrict__ mask,
-                              int wide_rows, int64_t* __restrict__ flags) {
+                              AcaBins bins, int64_t* __restrict__ flags) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
     const Cluster t = cl[ts.x], s = cl[ts.y];
     const int64_t mx = max(t.y - t.x, s.y - s.x);
-    int c = mx > kAcaBig ? 0 : (mx > 256 ? 1 : (mx > 128 ? 2 : (mx > 64 ? 3 : 4)));
-    if (wide_rows && c != 4) c = 1;
+    int c = bins.cls[aca_bin(mx)];
+    if (mx > aca_class_cap(c)) c = 1;                  // never with a valid binning
     if (mask && !mask[b]) c = -1;
 #pragma unroll
     for (int k = 0; k < kAcaClasses; ++k) flags[k * nb + b] = (k == c) ? 1 : 0;
@@ -1563,40 +1571,18 @@ __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* 
 }
 
 // ------------------------------------------------------------------ ACA launchers
-// The batched ACA over the blocks of a chunk (with mask: only the marked
-// ones) at rank cap kmax: class lists, then one queue launch per class,
-// largest class first.  flags, offs: kAcaClasses * nb int64 scratch; lists:
-// kAcaClasses * nb int32; head: kAcaClasses int.
+// Elements of a working slot at rank cap kcap: U (m x kcap) and V
+// (n x kcap), then m bytes of used-row flags, rounded up to 4 elements.
+template <typename T>
+__host__ __device__ inline int64_t slot_elems(int64_t m, int64_t n, int kcap) {
+  const int64_t flag_elems = (m + (int64_t)sizeof(T) - 1) / (int64_t)sizeof(T);
+  return (((int64_t)kcap * (m + n) + flag_elems) + 3) & ~(int64_t)3;
+}
+
+// One queue launch per kernel class with work, largest class first; A holds
+// the class lists and counts (head is zeroed here).
 template <typename T, int OP>
-void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
-             const AcaSlot* slot, int kmax, double eps, const int64_t* mask, int64_t* flags,
-             int64_t* offs, int32_t* lists, int* head, int32_t* rank, int32_t* info,
-             int64_t* tmp, hipStream_t s) {
-  if (nb == 0) return;
-  if (nb >= INT32_MAX) throw Error{HM_ERR_STATE, "ACA chunk of more than 2^31 blocks"};
-  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, mask, OP == kOpGalerkin, flags);
-  HM_LAUNCH_CHECK();
-  for (int k = 0; k < kAcaClasses; ++k)
-    scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
-  int64_t cnt[kAcaClasses];
-  HM_HIP(hipMemcpyAsync(cnt, tmp, kAcaClasses * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HM_HIP(hipStreamSynchronize(s));
-  k_split_lists<<<grid_for(nb, 256), 256, 0, s>>>(flags, offs, nb, lists);
-  HM_LAUNCH_CHECK();
-  AcaArgs<T> A{};
-  A.g = g;
-  A.blk = blk;
-  A.cl = cl;
-  A.slot = slot;
-  for (int k = 0; k < kAcaClasses; ++k) {
-    A.list[k] = lists + k * nb;
-    A.cnt[k] = cnt[k];
-  }
-  A.head = head;
-  A.kmax = kmax;
-  A.eps = eps;
-  A.rank = rank;
-  A.info = info;
+void launch_aca_classes(const AcaArgs<T>& A, int* head, hipStream_t s) {
   HM_HIP(hipMemsetAsync(head, 0, kAcaClasses * sizeof(int), s));
   int dev = 0, ncu = 0;
   HM_HIP(hipGetDevice(&dev));
@@ -1609,6 +1595,7 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
     HM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0));
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(work, (int64_t)ncu * std::max(per_cu, 1)));
   };
+  const int64_t* cnt = A.cnt;
   if constexpr (OP == kOpColloc) {
     if (cnt[0] > 0) {
       k_aca_wg<T, 1024, 0, OP><<<grid((const void*)k_aca_wg<T, 1024, 0, OP>, 1024, cnt[0]), 1024,
@@ -1641,6 +1628,191 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
   }
 }
 
+// The batched ACA over the blocks of a chunk (with mask: only the marked
+// ones) at rank cap kmax: class lists from the binning, then the class
+// launches.  flags, offs: kAcaClasses * nb int64 scratch; lists:
+// kAcaClasses * nb int32; head: kAcaClasses int.
+template <typename T, int OP>
+void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
+             const AcaSlot* slot, int kmax, double eps, const int64_t* mask, const AcaBins& bins,
+             int64_t* flags, int64_t* offs, int32_t* lists, int* head, int32_t* rank,
+             int32_t* info, int64_t* tmp, hipStream_t s) {
+  if (nb == 0) return;
+  if (nb >= INT32_MAX) throw Error{HM_ERR_STATE, "ACA chunk of more than 2^31 blocks"};
+  k_aca_classes<<<grid_for(nb, 256), 256, 0, s>>>(blk, nb, cl, mask, bins, flags);
+  HM_LAUNCH_CHECK();
+  for (int k = 0; k < kAcaClasses; ++k)
+    scan_excl_i64(flags + k * nb, offs + k * nb, nb, tmp + k, s);
+  int64_t cnt[kAcaClasses];
+  HM_HIP(hipMemcpyAsync(cnt, tmp, kAcaClasses * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HM_HIP(hipStreamSynchronize(s));
+  k_split_lists<<<grid_for(nb, 256), 256, 0, s>>>(flags, offs, nb, lists);
+  HM_LAUNCH_CHECK();
+  AcaArgs<T> A{};
+  A.g = g;
+  A.blk = blk;
+  A.cl = cl;
+  A.slot = slot;
+  for (int k = 0; k < kAcaClasses; ++k) {
+    A.list[k] = lists + k * nb;
+    A.cnt[k] = cnt[k];
+  }
+  A.head = head;
+  A.kmax = kmax;
+  A.eps = eps;
+  A.rank = rank;
+  A.info = info;
+  launch_aca_classes<T, OP>(A, head, s);
+}
+
+// The binning the library uses without tuning: wavefront classes up to 256
+// (one, two or four rows per lane), 256-thread workgroups up to 4,096 and
+// 1,024-thread workgroups above.  Galerkin entries keep the row triangle in
+// registers: the wavefront classes with two and four rows per lane and the
+// 1,024-thread class do not fit them, so every block above 64 goes to the
+// 256-thread class.
+AcaBins default_aca_bins(int op) {
+  if (op == kOpGalerkin) return AcaBins{{4, 1, 1, 1, 1, 1, 1}};
+  return AcaBins{{4, 3, 2, 1, 1, 1, 0}};
+}
+
+// Kernel classes the tuner tries for a bin.
+std::vector<int> aca_bin_candidates(int bin, int op) {
+  if (op == kOpGalerkin) return {bin == 0 ? 4 : 1};
+  switch (bin) {
+    case 0: return {4};
+    case 1: return {3, 1};
+    case 2: return {2, 1};
+    default: return {1, 0};
+  }
+}
+
+__global__ void k_block_bins(const int2* __restrict__ blk, int64_t nb,
+                             const Cluster* __restrict__ cl, int32_t* __restrict__ bin) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int2 ts = blk[b];
+    const Cluster t = cl[ts.x], s = cl[ts.y];
+    bin[b] = aca_bin(max(t.y - t.x, s.y - s.x));
+  }
+}
+
+// desc[list[k]] = {pool + off[k], kcap} for the blocks of a list.
+template <typename T>
+__global__ void k_list_desc(const int32_t* __restrict__ list, int64_t cnt,
+                            const int2* __restrict__ blk, const Cluster* __restrict__ cl, int kmax,
+                            const int64_t* __restrict__ off, T* pool, AcaSlot* __restrict__ desc) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < cnt;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int b = list[k];
+    const int2 ts = blk[b];
+    const Cluster t = cl[ts.x], s = cl[ts.y];
+    AcaSlot d;
+    d.ptr = (uint64_t)(uintptr_t)(pool + off[k]);
+    d.kc = min(kmax, min(t.y - t.x, s.y - s.x));
+    d.pad = 0;
+    desc[b] = d;
+  }
+}
+
+// The binning tuner: for every size bin with more than one candidate class,
+// a sample of its blocks (every st-th block in list order, at most
+// kTuneSample, and no more than the working pool holds) is run through each
+// candidate's kernel at the first-pass rank cap, twice, and the second pass
+// is timed with HIP events; the fastest class is kept.  The sample's ranks
+// and slots are overwritten by the real run.
+constexpr int64_t kTuneSample = 16384;
+
+template <typename T, int OP>
+AcaBins tune_aca_bins(const Geom<T>& g, const SetupIn& in, int k1, double eps, T* pool,
+                      int64_t pool_elems, AcaSlot* desc, int* head, int32_t* rank, int32_t* info,
+                      std::vector<AcaTuneRow>& rows, hipStream_t s) {
+  AcaBins bins = default_aca_bins(OP);
+  const int64_t nl = in.nl;
+  std::vector<int32_t> hb(nl);
+  std::vector<int2> hlr(nl);
+  std::vector<Cluster> hcl;
+  {
+    int32_t* db = dalloc_t<int32_t>(nl, s);
+    k_block_bins<<<grid_for(nl, 256), 256, 0, s>>>(in.lr, nl, in.cl, db);
+    HM_LAUNCH_CHECK();
+    HM_HIP(hipMemcpyAsync(hb.data(), db, nl * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipMemcpyAsync(hlr.data(), in.lr, nl * sizeof(int2), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    dfree(db, s);
+    int ncl = 0;
+    for (const int2& b : hlr) ncl = std::max(ncl, std::max(b.x, b.y) + 1);
+    hcl.resize(ncl);
+    HM_HIP(hipMemcpyAsync(hcl.data(), in.cl, ncl * sizeof(Cluster), hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<std::vector<int32_t>> members(kAcaBins);
+  for (int64_t b = 0; b < nl; ++b) members[hb[b]].push_back((int32_t)b);
+  int32_t* dlist = dalloc_t<int32_t>(kTuneSample, s);
+  int64_t* doff = dalloc_t<int64_t>(kTuneSample, s);
+  hipEvent_t e0, e1;
+  HM_HIP(hipEventCreate(&e0));
+  HM_HIP(hipEventCreate(&e1));
+  for (int bin = 0; bin < kAcaBins; ++bin) {
+    const std::vector<int> cand = aca_bin_candidates(bin, OP);
+    const std::vector<int32_t>& mem = members[bin];
+    if (cand.size() < 2 || mem.empty()) continue;
+    // the sample and its slots, laid out from the start of the pool
+    const int64_t st = std::max<int64_t>(1, ((int64_t)mem.size() + kTuneSample - 1) / kTuneSample);
+    std::vector<int32_t> smp;
+    std::vector<int64_t> off;
+    int64_t used = 0;
+    for (size_t k = 0; k < mem.size(); k += (size_t)st) {
+      const int2 ts = hlr[mem[k]];
+      const int64_t m = hcl[ts.x].y - hcl[ts.x].x, n = hcl[ts.y].y - hcl[ts.y].x;
+      const int64_t e = slot_elems<T>(m, n, (int)std::min<int64_t>(k1, std::min(m, n)));
+      if (used + e > pool_elems) break;
+      smp.push_back(mem[k]);
+      off.push_back(used);
+      used += e;
+    }
+    if (smp.empty()) continue;
+    const int64_t ns = (int64_t)smp.size();
+    HM_HIP(hipMemcpyAsync(dlist, smp.data(), ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HM_HIP(hipMemcpyAsync(doff, off.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    k_list_desc<T><<<grid_for(ns, 256), 256, 0, s>>>(dlist, ns, in.lr, in.cl, k1, doff, pool,
+                                                      desc);
+    HM_LAUNCH_CHECK();
+    double best = 0.0;
+    for (int c : cand) {
+      AcaArgs<T> A{};
+      A.g = g;
+      A.blk = in.lr;
+      A.cl = in.cl;
+      A.slot = desc;
+      A.list[c] = dlist;
+      A.cnt[c] = ns;
+      A.head = head;
+      A.kmax = k1;
+      A.eps = eps;
+      A.rank = rank;
+      A.info = info;
+      launch_aca_classes<T, OP>(A, head, s);            // warm-up (code loading, caches)
+      HM_HIP(hipEventRecord(e0, s));
+      launch_aca_classes<T, OP>(A, head, s);
+      HM_HIP(hipEventRecord(e1, s));
+      HM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      rows.push_back(AcaTuneRow{bin, c, ns, (double)ms});
+      if (c == cand.front() || ms < best) {
+        best = ms;
+        bins.cls[bin] = c;
+      }
+    }
+  }
+  HM_HIP(hipEventDestroy(e0));
+  HM_HIP(hipEventDestroy(e1));
+  dfree(dlist, s);
+  dfree(doff, s);
+  return bins;
+}
+
 // Largest possible rank of every block: min(kmax, m, n).
 __global__ void k_term_caps(const int2* __restrict__ blk, int64_t nb, const Cluster* __restrict__ cl,
                             int kmax, int64_t* __restrict__ kc) {
@@ -1650,14 +1822,6 @@ __global__ void k_term_caps(const int2* __restrict__ blk, int64_t nb, const Clus
     const Cluster t = cl[ts.x], s = cl[ts.y];
     kc[b] = min((int64_t)kmax, (int64_t)min(t.y - t.x, s.y - s.x));
   }
-}
-
-// Elements of a working slot at rank cap kcap: U (m x kcap) and V
-// (n x kcap), then m bytes of used-row flags, rounded up to 4 elements.
-template <typename T>
-__device__ inline int64_t slot_elems(int64_t m, int64_t n, int kcap) {
-  const int64_t flag_elems = (m + (int64_t)sizeof(T) - 1) / (int64_t)sizeof(T);
-  return (((int64_t)kcap * (m + n) + flag_elems) + 3) & ~(int64_t)3;
 }
 
 // Working-slot sizes (elements) of all blocks at rank cap kmax.
@@ -2037,6 +2201,13 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     int64_t* roff = ta.get<int64_t>(nl + 1);
     int* head = ta.get<int>(kAcaClasses);
     const auto aca = in.op == kOpGalerkin ? run_aca<T, kOpGalerkin> : run_aca<T, kOpColloc>;
+    out.bins = default_aca_bins(in.op);
+    if (in.tune_aca) {
+      const auto tune = in.op == kOpGalerkin ? tune_aca_bins<T, kOpGalerkin>
+                                             : tune_aca_bins<T, kOpColloc>;
+      out.bins = tune(g, in, k1, in.eps, pool, pool_elems, desc, head, out.rank, out.info,
+                      out.aca_tune, s);
+    }
     int64_t b0 = 0;
     while (b0 < nl) {
       int64_t b1 = hoff.empty() ? nl : b0 + 1;
@@ -2046,7 +2217,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       k_slot_desc<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, k1, slot_off + b0,
                                                        slot0, pool, nullptr, desc + b0);
       HM_LAUNCH_CHECK();
-      aca(g, in.lr + b0, nb, in.cl, desc + b0, k1, in.eps, nullptr, cflags, coffs, clists,
+      aca(g, in.lr + b0, nb, in.cl, desc + b0, k1, in.eps, nullptr, out.bins, cflags, coffs, clists,
                  head, out.rank + b0, out.info + b0, tmp, s);
       T* pool2 = nullptr;
       if (k1 < kmax) {
@@ -2059,7 +2230,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
           k_slot_desc<T><<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl, kmax, roff, 0,
                                                            pool2, rmark, desc + b0);
           HM_LAUNCH_CHECK();
-          aca(g, in.lr + b0, nb, in.cl, desc + b0, kmax, in.eps, rmark, cflags, coffs,
+          aca(g, in.lr + b0, nb, in.cl, desc + b0, kmax, in.eps, rmark, out.bins, cflags, coffs,
                      clists, head, out.rank + b0, out.info + b0, tmp, s);
           ++out.aca_reruns;
         }
