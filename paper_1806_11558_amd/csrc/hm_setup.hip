@@ -244,50 +244,81 @@ __device__ inline T op_entry(const Tgt<T, kOpGalerkin>& t, int i, const Src<T>& 
 // polar coordinates about x' every edge gives, between its end points,
 // h asinh(l / c) + |d| atan(|d| l / (h R)) - |d| atan(l / h)
 // (h distance of x' to the edge line, l coordinate along it, c^2 = h^2 + d^2,
-// R distance from x to the end point).
-__device__ inline double tri_inner_integral(const double x[3], const double v[3][3]) {
-  double e1[3], e2[3], n[3];
+// R distance from x to the end point).  Evaluated here in an equivalent
+// form with one logarithm and two arc tangents per edge:
+//   asinh(l_b / c) - asinh(l_a / c) = log((l_b + R_b) / (l_a + R_a))  (l_a >= 0),
+//   = log((|l_a| + R_a) / (|l_b| + R_b)) (l_b <= 0), and
+//   log((l_b + R_b)(|l_a| + R_a) / c^2) when the edge spans the foot point
+//   (R^2 = l^2 + c^2; no cancellation in any case);
+//   atan(|d| l / (h R)) - atan(l / h) = atan(z),
+//   z = -l h (l^2 + h^2) / ((R + |d|)(h^2 R + |d| l^2))
+//   (the two arguments have a non-negative product, and R - |d| is written
+//   as (l^2 + h^2) / (R + |d|)).
+// What depends only on T -- its unit normal, the unit edge tangents t_k,
+// the in-plane edge normals m_k = t_k x n and the edge lengths -- is set up
+// once per pair.
+struct TriJ {
+  double v[3][3], n[3], t[3][3], m[3][3], le[3];
+};
+
+__device__ inline void tri_setup(const double v[3][3], TriJ& J) {
+  double e1[3], e2[3];
   for (int k = 0; k < 3; ++k) {
     e1[k] = v[1][k] - v[0][k];
     e2[k] = v[2][k] - v[0][k];
+    for (int c = 0; c < 3; ++c) J.v[k][c] = v[k][c];
   }
-  n[0] = e1[1] * e2[2] - e1[2] * e2[1];
-  n[1] = e1[2] * e2[0] - e1[0] * e2[2];
-  n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                 e1[0] * e2[1] - e1[1] * e2[0]};
   const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  for (int k = 0; k < 3; ++k) n[k] /= nn;
-  const double d = (x[0] - v[0][0]) * n[0] + (x[1] - v[0][1]) * n[1] + (x[2] - v[0][2]) * n[2];
-  const double ad = fabs(d);
-  double xp[3];
-  for (int k = 0; k < 3; ++k) xp[k] = x[k] - d * n[k];
-  double total = 0.0;
+  for (int c = 0; c < 3; ++c) J.n[c] = n[c] / nn;
   for (int k = 0; k < 3; ++k) {
     const double* a = v[k];
     const double* b = v[(k + 1) % 3];
-    double e[3], am[3], bm[3];
-    for (int c = 0; c < 3; ++c) {
-      e[c] = b[c] - a[c];
-      am[c] = a[c] - xp[c];
-      bm[c] = b[c] - xp[c];
-    }
+    double e[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
     const double le = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-    // twice the signed area of (x', a, b) relative to n
-    const double cr = (am[1] * e[2] - am[2] * e[1]) * n[0] + (am[2] * e[0] - am[0] * e[2]) * n[1] +
-                      (am[0] * e[1] - am[1] * e[0]) * n[2];
-    const double h = fabs(cr) / le;
+    J.le[k] = le;
+    for (int c = 0; c < 3; ++c) J.t[k][c] = e[c] / le;
+    J.m[k][0] = J.t[k][1] * J.n[2] - J.t[k][2] * J.n[1];
+    J.m[k][1] = J.t[k][2] * J.n[0] - J.t[k][0] * J.n[2];
+    J.m[k][2] = J.t[k][0] * J.n[1] - J.t[k][1] * J.n[0];
+  }
+}
+
+__device__ inline double tri_inner_integral(const double x[3], const TriJ& J) {
+  const double d = (x[0] - J.v[0][0]) * J.n[0] + (x[1] - J.v[0][1]) * J.n[1] +
+                   (x[2] - J.v[0][2]) * J.n[2];
+  const double ad = fabs(d);
+  double R[3];
+  for (int k = 0; k < 3; ++k) {
+    const double dx = x[0] - J.v[k][0], dy = x[1] - J.v[k][1], dz = x[2] - J.v[k][2];
+    R[k] = sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  double total = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double ax = J.v[k][0] - x[0], ay = J.v[k][1] - x[1], az = J.v[k][2] - x[2];
+    // signed distance of x' to the edge line (positive: x' on the inner side)
+    const double hs = ax * J.m[k][0] + ay * J.m[k][1] + az * J.m[k][2];
+    const double h = fabs(hs);
     if (!(h > 0.0)) continue;                            // x' on the edge line
-    const double la = (am[0] * e[0] + am[1] * e[1] + am[2] * e[2]) / le;
-    const double lb = (bm[0] * e[0] + bm[1] * e[1] + bm[2] * e[2]) / le;
-    const double ra = sqrt((x[0] - a[0]) * (x[0] - a[0]) + (x[1] - a[1]) * (x[1] - a[1]) +
-                           (x[2] - a[2]) * (x[2] - a[2]));
-    const double rb = sqrt((x[0] - b[0]) * (x[0] - b[0]) + (x[1] - b[1]) * (x[1] - b[1]) +
-                           (x[2] - b[2]) * (x[2] - b[2]));
-    const double c = sqrt(h * h + d * d);
-    double val = h * (asinh(lb / c) - asinh(la / c));
-    if (ad > 0.0)
-      val += ad * (atan(ad * lb / (h * rb)) - atan(ad * la / (h * ra))) -
-             ad * (atan(lb / h) - atan(la / h));
-    total += cr > 0.0 ? val : -val;
+    const double la = ax * J.t[k][0] + ay * J.t[k][1] + az * J.t[k][2];
+    const double lb = la + J.le[k];
+    const double Ra = R[k], Rb = R[(k + 1) % 3];
+    double lg;
+    if (la >= 0.0)
+      lg = log((lb + Rb) / (la + Ra));
+    else if (lb <= 0.0)
+      lg = log((Ra - la) / (Rb - lb));
+    else
+      lg = log((lb + Rb) * (Ra - la) / (h * h + d * d));
+    double val = h * lg;
+    if (ad > 0.0) {
+      const double h2 = h * h;
+      const double za = -la * h * (la * la + h2) / ((Ra + ad) * (h2 * Ra + ad * la * la));
+      const double zb = -lb * h * (lb * lb + h2) / ((Rb + ad) * (h2 * Rb + ad * lb * lb));
+      val += ad * (atan(zb) - atan(za));
+    }
+    total += hs > 0.0 ? val : -val;
   }
   return total;
 }
@@ -309,6 +340,8 @@ __device__ inline double galerkin_singular_part(const Geom<T>& g, const GaussRul
   double ti[3][3], tj[3][3];
   load_tri(g, i, ti);
   load_tri(g, j, tj);
+  TriJ J;
+  tri_setup(tj, J);
   double a[3], b[3];
   for (int c = 0; c < 3; ++c) {
     a[c] = ti[1][c] - ti[0][c];
@@ -323,7 +356,7 @@ __device__ inline double galerkin_singular_part(const Geom<T>& g, const GaussRul
     const double s = R.x[ks], t = R.x[kt];
     double x[3];
     for (int c = 0; c < 3; ++c) x[c] = ti[0][c] + s * a[c] + s * t * b[c];
-    acc += R.w[ks] * R.w[kt] * s * jac * tri_inner_integral(x, tj);
+    acc += R.w[ks] * R.w[kt] * s * jac * tri_inner_integral(x, J);
   }
   return acc * 0.079577471545947667884441881686257181;   // 1/(4 pi)
 }
@@ -1098,9 +1131,12 @@ __global__ __launch_bounds__(NT, NT == 256 ? (OP == kOpGalerkin ? 2 : 4) : 1) vo
 
 // Classes 2..4: one block per wavefront; every wavefront takes its own
 // blocks from the queue, NB consecutive (similar) blocks per fetch for the
-// small classes, which have millions of blocks (no barriers).
+// small classes, which have millions of blocks (no barriers).  Galerkin
+// entries hold the row triangle in registers: two waves per SIMD for one
+// row per lane, one (with the accumulation registers as spill space) for
+// two and four.
 template <typename T, int Q, int OP>
-__global__ __launch_bounds__(kAcaThreads, OP == kOpGalerkin ? 2 : (Q == 1 ? 4 : (Q == 2 ? 3 : 2)))
+__global__ __launch_bounds__(kAcaThreads, OP == kOpGalerkin ? (Q == 1 ? 2 : 1) : (Q == 1 ? 4 : (Q == 2 ? 3 : 2)))
 void k_aca_wave(AcaArgs<T> A) {
   constexpr int c = Q == 4 ? 2 : (Q == 2 ? 3 : 4);
   constexpr int NB = Q == 4 ? 1 : (Q == 2 ? 2 : 4);
@@ -1607,7 +1643,7 @@ void launch_aca_classes(const AcaArgs<T>& A, int* head, hipStream_t s) {
     k_aca_wg<T, 256, 1, OP><<<grid((const void*)k_aca_wg<T, 256, 1, OP>, 256, cnt[1]), 256, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
-  if constexpr (OP == kOpColloc) {
+  {
     if (cnt[2] > 0) {
       k_aca_wave<T, 4, OP><<<grid((const void*)k_aca_wave<T, 4, OP>, kAcaThreads,
                                   ceil_div(cnt[2], kAcaWaves)),
@@ -1668,17 +1704,26 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
 // The binning the library uses without tuning: wavefront classes up to 256
 // (one, two or four rows per lane), 256-thread workgroups up to 4,096 and
 // 1,024-thread workgroups above.  Galerkin entries keep the row triangle in
-// registers: the wavefront classes with two and four rows per lane and the
-// 1,024-thread class do not fit them, so every block above 64 goes to the
-// 256-thread class.
+// registers: one and two rows per lane up to 128 and 256-thread workgroups
+// above (the tuner's choice at N = 1,310,720: 65..128 on two rows per lane
+// 0.98 against 1.63 ms, 129..256 on 256-thread workgroups 1.92 against
+// 2.32 ms for four rows per lane); the 1,024-thread class is not built for
+// them.
 AcaBins default_aca_bins(int op) {
-  if (op == kOpGalerkin) return AcaBins{{4, 1, 1, 1, 1, 1, 1}};
+  if (op == kOpGalerkin) return AcaBins{{4, 3, 1, 1, 1, 1, 1}};
   return AcaBins{{4, 3, 2, 1, 1, 1, 0}};
 }
 
 // Kernel classes the tuner tries for a bin.
 std::vector<int> aca_bin_candidates(int bin, int op) {
-  if (op == kOpGalerkin) return {bin == 0 ? 4 : 1};
+  if (op == kOpGalerkin) {
+    // the wavefront classes with two and four rows per lane run Galerkin
+    // entries at one or two waves per SIMD; the 1,024-thread class is not
+    // built for them
+    if (bin == 1) return {1, 3};
+    if (bin == 2) return {1, 2};
+    return {bin == 0 ? 4 : 1};
+  }
   switch (bin) {
     case 0: return {4};
     case 1: return {3, 1};
