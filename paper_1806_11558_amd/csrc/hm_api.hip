@@ -291,6 +291,8 @@ struct hm_handle {
     P.colmap = sto.colmap;
     P.meta = sto.meta;
     P.nlr = nl;
+    P.meta1 = sto.meta1;
+    P.nu1 = sto.nu1;
     P.ucol = sto.ucol;
     P.tbeg = sto.tbeg;
     P.titems = sto.titems;

@@ -121,12 +121,18 @@ struct Run {
 // Per admissible block: V factor address, rank, offset of its terms in t,
 // first/last leaf of its column (sf, sl) and row (tf, tl) cluster, and the
 // first entry of its U slices in the per-(block, row leaf) records.
+// The V factor of a block is stored in column-leaf slices, each ld x r
+// column-major; slice lf starts vw * (ldpre[lf] - ldpre[sf]) elements after
+// vptr: blocks that share a column cluster (whose leaves share one ld) lie
+// side by side in panels of vw = the sum of their ranks columns, a block
+// alone has vw = r.  The same record with r = a chunk of a panel's columns
+// describes a work unit of the forward phase 1.
 struct LrMeta {
   uint64_t vptr;
   int32_t r, toff, sf, sl, tf, tl;
   int64_t ub;
   int32_t vld;   // ld shared by all column-leaf slices, 0 if they differ
-  int32_t pad;
+  int32_t vw;    // slice width: columns between the slices of one leaf and the next
 };
 // Column-leaf item of the transposed product: kind 0 = columns of a dense
 // slice (partial dots at w[src ..]), kind 1 = V slice at `data` (w = rank,
@@ -164,6 +170,8 @@ struct MvPlan {
   const int32_t* colmap;
   const LrMeta* meta;
   int64_t nlr;
+  const LrMeta* meta1;      // work units of the forward phase 1 (panel column chunks)
+  int64_t nu1;
   const int64_t* ucol;
   const int32_t* tbeg;      // column leaf -> first transposed item (nleaf + 1)
   const TItem* titems;
@@ -219,6 +227,8 @@ struct Storage {
   int32_t* rank = nullptr;
   int32_t* info = nullptr;
   LrMeta* meta = nullptr;
+  LrMeta* meta1 = nullptr;   // forward phase-1 units
+  int64_t nu1 = 0;
   int64_t* ucol = nullptr;
   uint64_t* uptr = nullptr;
   int64_t lr_elems = 0, toff_total = 0, nchunks = 0, u_items = 0, aca_reruns = 0;

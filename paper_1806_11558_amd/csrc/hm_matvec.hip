@@ -171,7 +171,7 @@ __device__ inline void fwd1_uniform(const LrMeta& M, const MvLeaves& L, const A*
   int off[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) off[q] = min(q * C + cg, r - 1) * ld + g * G;
-  const int sstride = ld * r;
+  const int sstride = ld * M.vw;
   const T* Sl = reinterpret_cast<const T*>((uintptr_t)M.vptr);
   int lo = L.lo[M.sf];                       // the leaves of sigma are consecutive
   for (int lf = M.sf; lf <= M.sl; ++lf, Sl += sstride) {
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                                               MvLeaves L, A* __restrict__ z, int64_t n,
                                               const float* __restrict__ su) {
   constexpr int G = Gran<T>::G;
-  constexpr int PMAX = NR == 1 ? 4 : (NR <= 4 ? 2 : 1);
+  constexpr int PMAX = NR <= 2 ? 4 : (NR <= 4 ? 2 : 1);
   const int lane = threadIdx.x & 63;
   // wave-uniform block index: descriptors and leaf data come in by scalar loads
   const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
             }
             fwd1_flush<A, NR>(p, g, R, j0, C, rc, lane, tl);
           }
-          Sl += (int64_t)ld * r;
+          Sl += (int64_t)ld * M.vw;
         }
         if (t0 + 64 < r && lane < rc) {       // every chunk but the last one
           const A sc = su ? (A)su[M.toff + t0 + lane] : (A)1;
@@ -341,7 +341,7 @@ __device__ inline void fwd1m_block(const LrMeta& M, const MvLeaves& L, A* __rest
           }
         }
       }
-      S += (int64_t)ld * r;
+      S += (int64_t)ld * M.vw;
     }
     if (ok) {
       const A sc = su ? (A)su[M.toff + j] : sc0;
@@ -608,7 +608,7 @@ __device__ inline void fwd1x_pass_rows(const LrMeta& M, const MvLeaves& L,
 #pragma unroll
         for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av[u][t], bv[u], acc[t]);
     }
-    S += (int64_t)ld * r;
+    S += (int64_t)ld * M.vw;
     lo += m;
   }
 }
@@ -670,7 +670,7 @@ __device__ inline void fwd1x_pass_gran(const LrMeta& M, const MvLeaves& L,
 #pragma unroll
           for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av[u][t][e], bv[u][e], acc[t]);
     }
-    S += (int64_t)ld * r;
+    S += (int64_t)ld * M.vw;
     lo += m;
   }
 }
@@ -1205,13 +1205,15 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   // round-robin over the XCDs
   const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
-    if (P.nlr > 0) {
+    // phase 1 over its work units (column chunks of the V panels)
+    const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nu1, 4), 1 << 20));
+    if (P.nu1 > 0) {
       if constexpr (NR == 8 || NR == 16) {
-        k_fwd1x<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, z, P.n, P.su);
+        k_fwd1x<TL, A, NR><<<g1, 256, 0, s>>>(P.meta1, P.nu1, P.L, z, z, P.n, P.su);
       } else if constexpr (NR >= 4) {
-        k_fwd1m<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
+        k_fwd1m<TL, A, NR><<<g1, 256, 0, s>>>(P.meta1, P.nu1, P.L, z, P.n, P.su);
       } else {
-        k_fwd1<TL, A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.L, z, P.n, P.su);
+        k_fwd1<TL, A, NR><<<g1, 256, 0, s>>>(P.meta1, P.nu1, P.L, z, P.n, P.su);
       }
       HM_LAUNCH_CHECK();
     }

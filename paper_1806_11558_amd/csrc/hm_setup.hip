@@ -1380,14 +1380,16 @@ __global__ __launch_bounds__(256) void k_u_scales(const int2* __restrict__ blk, 
   }
 }
 
-// V factor of every block, contiguous: its column-leaf slices in leaf order,
-// converted to TL (|v| <= 1 by the pivot normalisation, so no scale).
+// V factor of every block: its column-leaf slices (ld x r, column-major)
+// at varena + vbase[b] + vw[b] (ldpre[lf] - ldpre[sf]), converted to TL
+// (|v| <= 1 by the pivot normalisation, so no scale).
 template <typename T, typename TL>
 __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, int64_t nb,
                                                 const Cluster* __restrict__ cl, LeafTab L,
                                                 const int32_t* __restrict__ rank,
                                                 const AcaSlot* __restrict__ slot,
-                                                const int64_t* __restrict__ voff,
+                                                const int64_t* __restrict__ vbase,
+                                                const int32_t* __restrict__ vw,
                                                 TL* __restrict__ varena,
                                                 uint64_t* __restrict__ vptr) {
   // one wavefront per block (most are a few hundred values)
@@ -1398,12 +1400,13 @@ __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, in
     const Cluster tau = cl[ts.x], sig = cl[ts.y];
     const int m = tau.y - tau.x, n = sig.y - sig.x, r = rank[b];
     const T* Vw = reinterpret_cast<const T*>((uintptr_t)slot[b].ptr) + (int64_t)slot[b].kc * m;
-    TL* dst = varena + voff[b];
+    TL* dst = varena + vbase[b];
     if (lane == 0) vptr[b] = (uint64_t)(uintptr_t)dst;
     const int2 ls = L.cl_leaves[ts.y];
+    const int w = vw[b];
     for (int lf = ls.x; lf <= ls.y; ++lf) {
       const int ld = leaf_ld(L, lf), ml = L.m[lf], off = L.lo[lf] - sig.x;
-      TL* d = dst + (int64_t)r * (L.ldpre[lf] - L.ldpre[ls.x]);
+      TL* d = dst + (int64_t)w * (L.ldpre[lf] - L.ldpre[ls.x]);
       const int tot = ld * r;
       for (int e0 = lane; e0 < tot; e0 += 512) {
         T v[8];
@@ -1422,13 +1425,141 @@ __global__ __launch_bounds__(256) void k_pack_v(const int2* __restrict__ blk, in
   }
 }
 
-// V arena size of every block: r * LD(sigma).
-__global__ void k_v_sizes(const int2* __restrict__ blk, int64_t nb, const int32_t* __restrict__ rank,
-                          LeafTab L, int64_t* __restrict__ sz) {
+// ---- column-cluster groups of the V factors.  The blocks of a chunk are
+// sorted by column cluster; blocks that share it (and whose column leaves
+// share one ld) form a group whose V slices lie side by side in one panel
+// per column leaf (ld x W, W = the group's terms), in sorted order, with
+// consecutive terms in t.  Blocks whose column leaves differ in ld stay
+// alone (W = r).
+
+// Sort key of every block: its column cluster, or 2^31 + b (alone).
+__global__ void k_group_keys(const int2* __restrict__ blk, int64_t nb,
+                             const int2* __restrict__ cl_leaves, const int64_t* __restrict__ ldpre,
+                             uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
-    const int2 ls = L.cl_leaves[blk[b].y];
-    sz[b] = (int64_t)rank[b] * (L.ldpre[ls.y + 1] - L.ldpre[ls.x]);
+    const int sg = blk[b].y;
+    const int2 ls = cl_leaves[sg];
+    const int64_t ld0 = ldpre[ls.x + 1] - ldpre[ls.x];
+    bool uni = true;
+    for (int lf = ls.x + 1; lf <= ls.y && uni; ++lf) uni = (ldpre[lf + 1] - ldpre[lf]) == ld0;
+    key[b] = uni ? (uint64_t)sg : ((uint64_t)1 << 31) + (uint64_t)b;
+    idx[b] = (int32_t)b;
+  }
+}
+
+// Ranks in sorted order, and 1 at the first position of every group.
+__global__ void k_group_marks(const uint64_t* __restrict__ key, const int32_t* __restrict__ idx,
+                              int64_t nb, const int32_t* __restrict__ rank,
+                              int64_t* __restrict__ rk, int64_t* __restrict__ first) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nb;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    rk[k] = rank[idx[k]];
+    first[k] = (k == 0 || key[k] != key[k - 1]) ? 1 : 0;
+  }
+}
+
+// Group table: first sorted position of every group (gpos[k] = groups
+// before position k).
+__global__ void k_group_starts(const int64_t* __restrict__ first, const int64_t* __restrict__ gpos,
+                               int64_t nb, int64_t* __restrict__ gstart) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nb;
+       k += (int64_t)gridDim.x * blockDim.x)
+    if (first[k]) gstart[gpos[k]] = k;
+}
+
+// Per group: its width W (terms) and the size of its panels, W * LD(sigma).
+__global__ void k_group_sizes(const int64_t* __restrict__ gstart, int64_t ng, int64_t nb,
+                              const int64_t* __restrict__ tsort, const int32_t* __restrict__ idx,
+                              const int2* __restrict__ blk, const int2* __restrict__ cl_leaves,
+                              const int64_t* __restrict__ ldpre, int64_t* __restrict__ gw,
+                              int64_t* __restrict__ gsz) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = gstart[g], e = g + 1 < ng ? gstart[g + 1] : nb;
+    const int64_t w = tsort[e] - tsort[a];
+    const int2 ls = cl_leaves[blk[idx[a]].y];
+    gw[g] = w;
+    gsz[g] = w * (ldpre[ls.y + 1] - ldpre[ls.x]);
+  }
+}
+
+// Per block: its term offset (sorted order), the start of its first slice
+// in the V arena and the slice width of its group.
+__global__ void k_block_vlayout(const int32_t* __restrict__ idx, const int64_t* __restrict__ gpos,
+                                const int64_t* __restrict__ first, int64_t nb,
+                                const int64_t* __restrict__ tsort,
+                                const int64_t* __restrict__ gstart, const int64_t* __restrict__ gw,
+                                const int64_t* __restrict__ goff, const int2* __restrict__ blk,
+                                const int2* __restrict__ cl_leaves,
+                                const int64_t* __restrict__ ldpre, int64_t* __restrict__ toff,
+                                int64_t* __restrict__ vbase, int32_t* __restrict__ vw) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nb;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int b = idx[k];
+    const int64_t g = gpos[k] + first[k] - 1;
+    const int64_t col = tsort[k] - tsort[gstart[g]];
+    const int2 ls = cl_leaves[blk[b].y];
+    toff[b] = tsort[k];
+    vbase[b] = goff[g] + col * (ldpre[ls.x + 1] - ldpre[ls.x]);
+    vw[b] = (int32_t)gw[g];
+  }
+}
+
+// Work units of the forward phase 1 per group: its panel columns in chunks
+// of at most uw(ld) (a group whose leaves differ in ld is one block: one
+// unit).
+__device__ inline int unit_cols(int64_t ld, int gran) {
+  return (int)min((int64_t)64, 256 * (int64_t)gran / ld);
+}
+__global__ void k_group_units(const int64_t* __restrict__ gstart, int64_t ng,
+                              const uint64_t* __restrict__ key, const int32_t* __restrict__ idx,
+                              const int64_t* __restrict__ gw, const int2* __restrict__ blk,
+                              const int2* __restrict__ cl_leaves, const int64_t* __restrict__ ldpre,
+                              int gran, int64_t* __restrict__ cnt) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = gstart[g];
+    const int64_t w = gw[g];
+    if (key[a] >= ((uint64_t)1 << 31)) {
+      cnt[g] = w > 0 ? 1 : 0;
+    } else {
+      const int2 ls = cl_leaves[blk[idx[a]].y];
+      const int uw = unit_cols(ldpre[ls.x + 1] - ldpre[ls.x], gran);
+      cnt[g] = (w + uw - 1) / uw;
+    }
+  }
+}
+
+__global__ void k_emit_units(const int64_t* __restrict__ gstart, int64_t ng,
+                             const uint64_t* __restrict__ key, const int32_t* __restrict__ idx,
+                             const int64_t* __restrict__ gw, const int64_t* __restrict__ goff,
+                             const int64_t* __restrict__ uoff, const int64_t* __restrict__ tsort,
+                             int64_t toff_base, const LrMeta* __restrict__ meta, int gran,
+                             uint64_t varena, int esize, LrMeta* __restrict__ units) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = gstart[g];
+    const int64_t w = gw[g];
+    if (w == 0) continue;
+    const LrMeta B = meta[idx[a]];                      // the group's first block
+    if (key[a] >= ((uint64_t)1 << 31)) {
+      units[uoff[g]] = B;
+      continue;
+    }
+    const int64_t ld = B.vld;
+    const int uw = unit_cols(ld, gran);
+    int64_t o = uoff[g];
+    for (int64_t c0 = 0; c0 < w; c0 += uw, ++o) {
+      LrMeta U = B;
+      U.vptr = varena + (uint64_t)((goff[g] + c0 * ld) * esize);
+      U.r = (int32_t)min((int64_t)uw, w - c0);
+      U.toff = (int32_t)(toff_base + tsort[a] + c0);
+      U.tf = U.tl = 0;
+      U.ub = 0;
+      U.vw = (int32_t)w;
+      units[o] = U;
+    }
   }
 }
 
@@ -1468,8 +1599,8 @@ __global__ void k_drec(const int32_t* __restrict__ sidx, const int32_t* __restri
 __global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* __restrict__ cl_leaves,
                           const int64_t* __restrict__ ldpre, const int32_t* __restrict__ rank,
                           const int64_t* __restrict__ toff, int64_t toff_base,
-                          const uint64_t* __restrict__ vptr, const int64_t* __restrict__ ub,
-                          LrMeta* __restrict__ meta) {
+                          const uint64_t* __restrict__ vptr, const int32_t* __restrict__ vw,
+                          const int64_t* __restrict__ ub, LrMeta* __restrict__ meta) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
        b += (int64_t)gridDim.x * blockDim.x) {
     const int2 ts = blk[b];
@@ -1487,7 +1618,7 @@ __global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* 
     bool uni = true;
     for (int lf = ls.x + 1; lf <= ls.y && uni; ++lf) uni = (ldpre[lf + 1] - ldpre[lf]) == ld0;
     M.vld = uni ? (int32_t)ld0 : 0;
-    M.pad = 0;
+    M.vw = vw[b];
     meta[b] = M;
   }
 }
@@ -1531,7 +1662,7 @@ __global__ void k_titem_expand(const int2* __restrict__ dns, int64_t nd, int64_t
     } else {
       const LrMeta M = meta[b - nd];
       for (int cf = M.sf; cf <= M.sl; ++cf, ++o) {
-        const uint64_t d = M.vptr + (uint64_t)((int64_t)M.r * (L.ldpre[cf] - L.ldpre[M.sf]) * esize);
+        const uint64_t d = M.vptr + (uint64_t)((int64_t)M.vw * (L.ldpre[cf] - L.ldpre[M.sf]) * esize);
         out[o] = TItem{d, (int64_t)M.toff, M.r, 1};
         key[o] = (uint64_t)cf;
         idx[o] = (int32_t)o;
@@ -1599,7 +1730,7 @@ __global__ void k_unpack(const int2* __restrict__ lr, int64_t b, const Cluster* 
     if (isu)
       sl = reinterpret_cast<const TL*>((uintptr_t)uptr[M.ub + (lf - lf0)]);
     else
-      sl = reinterpret_cast<const TL*>((uintptr_t)M.vptr) + (int64_t)r * (L.ldpre[lf] - L.ldpre[lf0]);
+      sl = reinterpret_cast<const TL*>((uintptr_t)M.vptr) + (int64_t)M.vw * (L.ldpre[lf] - L.ldpre[lf0]);
     TO v = (TO)sl[(int64_t)l * leaf_ld(L, lf) + (pos - L.lo[lf])];
     if (isu && su) v *= (TO)su[M.toff + l];
     out[e] = v;
@@ -1920,12 +2051,6 @@ __global__ void k_rerun_marks(const int2* __restrict__ blk, int64_t nb, const Cl
   }
 }
 
-__global__ void k_widen_i32(const int32_t* __restrict__ a, int64_t n, int64_t* __restrict__ out) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    out[e] = a[e];
-}
-
 // ------------------------------------------------------------------ host side
 template <typename T>
 void launch_entries(const Geom<T>& g, int op, const int32_t* inv, const int32_t* rows,
@@ -2127,6 +2252,7 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   HM_LAUNCH_CHECK();
   std::vector<Run*> run_parts;
   std::vector<std::pair<int32_t*, int64_t>> colmap_parts;
+  std::vector<std::pair<LrMeta*, int64_t>> unit_parts;      // forward phase-1 units per chunk
   Run* runD = keep.get<Run>(nleaf);
   k_runs<<<grid_for(nleaf, 256), 256, 0, s>>>(PD.col0, PD.W, PD.poff, nleaf, (uint64_t)(uintptr_t)D,
                                               esize, 0, runD);
@@ -2236,8 +2362,8 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
     int32_t* clists = ta.get<int32_t>(kAcaClasses * nl);
     int64_t* toffc = ta.get<int64_t>(nl + 1);
     int64_t* rk64 = ta.get<int64_t>(nl);
-    int64_t* vsz = ta.get<int64_t>(nl);
     int64_t* voff = ta.get<int64_t>(nl + 1);
+    int32_t* vwid = ta.get<int32_t>(nl + 1);
     uint64_t* vptr = ta.get<uint64_t>(nl);
     int64_t* oU = ta.get<int64_t>(nl + 1);
     AcaSlot* desc = ta.get<AcaSlot>(nl);
@@ -2282,23 +2408,65 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       }
       HM_HIP(hipStreamSynchronize(s));
       const auto tp = clk::now();
-      // term offsets in t
-      k_widen_i32<<<grid_for(nb, 256), 256, 0, s>>>(out.rank + b0, nb, rk64);
+      // column-cluster groups: term offsets in t (sorted order) and the V
+      // panel layout
+      Temps tg{s, {}};
+      uint64_t* gkey = tg.get<uint64_t>(nb);
+      int32_t* gidx = tg.get<int32_t>(nb);
+      int64_t* gfirst = tg.get<int64_t>(nb);
+      int64_t* gpos = tg.get<int64_t>(nb + 1);
+      int64_t* tsort = tg.get<int64_t>(nb + 1);
+      k_group_keys<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, in.ldpre, gkey,
+                                                     gidx);
       HM_LAUNCH_CHECK();
-      const int64_t terms = scan_total(rk64, toffc, nb, tmp, s);
+      radix_sort_u64_i32(gkey, gidx, nb, 32, s);
+      k_group_marks<<<grid_for(nb, 256), 256, 0, s>>>(gkey, gidx, nb, out.rank + b0, rk64, gfirst);
+      HM_LAUNCH_CHECK();
+      scan_excl_i64(rk64, tsort, nb, tsort + nb, s);
+      const int64_t terms = d2h_i64(tsort + nb, s);
+      const int64_t ngr = scan_total(gfirst, gpos, nb, tmp, s);
+      int64_t* gstart = tg.get<int64_t>(ngr + 1);
+      int64_t* gw = tg.get<int64_t>(ngr + 1);
+      int64_t* gsz = tg.get<int64_t>(ngr + 1);
+      int64_t* goff = tg.get<int64_t>(ngr + 1);
+      int64_t* gcnt = tg.get<int64_t>(ngr + 1);
+      int64_t* guoff = tg.get<int64_t>(ngr + 1);
+      k_group_starts<<<grid_for(nb, 256), 256, 0, s>>>(gfirst, gpos, nb, gstart);
+      HM_LAUNCH_CHECK();
+      k_group_sizes<<<grid_for(ngr, 256), 256, 0, s>>>(gstart, ngr, nb, tsort, gidx, in.lr + b0,
+                                                       in.cl_leaves, in.ldpre, gw, gsz);
+      HM_LAUNCH_CHECK();
+      const int64_t velems = scan_total(gsz, goff, ngr, tmp, s);
+      k_block_vlayout<<<grid_for(nb, 256), 256, 0, s>>>(gidx, gpos, gfirst, nb, tsort, gstart, gw,
+                                                        goff, in.lr + b0, in.cl_leaves, in.ldpre,
+                                                        toffc, voff, vwid);
+      HM_LAUNCH_CHECK();
       // V factors
-      k_v_sizes<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, out.rank + b0, L, vsz);
-      HM_LAUNCH_CHECK();
-      const int64_t velems = scan_total(vsz, voff, nb, tmp, s);
       TL* varena = static_cast<TL*>(alloc((size_t)velems * lsize));
       k_pack_v<T, TL><<<grid_for(nb, 4, 1 << 20), 256, 0, s>>>(in.lr + b0, nb, in.cl, L,
                                                                out.rank + b0, desc + b0, voff,
-                                                               varena, vptr);
+                                                               vwid, varena, vptr);
       HM_LAUNCH_CHECK();
       k_lr_meta<<<grid_for(nb, 256), 256, 0, s>>>(in.lr + b0, nb, in.cl_leaves, in.ldpre,
-                                                  out.rank + b0, toffc, toff_base, vptr, ub + b0,
-                                                  out.meta + b0);
+                                                  out.rank + b0, toffc, toff_base, vptr, vwid,
+                                                  ub + b0, out.meta + b0);
       HM_LAUNCH_CHECK();
+      // phase-1 units of the chunk
+      {
+        const int gran = sizeof(TL) == 8 ? 2 : 4;
+        k_group_units<<<grid_for(ngr, 256), 256, 0, s>>>(gstart, ngr, gkey, gidx, gw, in.lr + b0,
+                                                         in.cl_leaves, in.ldpre, gran, gcnt);
+        HM_LAUNCH_CHECK();
+        const int64_t nu = scan_total(gcnt, guoff, ngr, tmp, s);
+        LrMeta* um = keep.get<LrMeta>(nu + 1);
+        k_emit_units<<<grid_for(ngr, 256), 256, 0, s>>>(gstart, ngr, gkey, gidx, gw, goff, guoff,
+                                                        tsort, toff_base, out.meta + b0, gran,
+                                                        (uint64_t)(uintptr_t)varena, lsize, um);
+        HM_LAUNCH_CHECK();
+        unit_parts.push_back({um, nu});
+      }
+      HM_HIP(hipStreamSynchronize(s));
+      tg.release();
       // U slices in row-leaf panels
       Temps tu{s, {}};
       PanelSet PU;
@@ -2347,6 +2515,19 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   }
   out.toff_total = toff_base;
   if (toff_base >= INT32_MAX) throw Error{HM_ERR_STATE, "more than 2^31 low-rank terms"};
+  {
+    int64_t nu = 0;
+    for (auto& up : unit_parts) nu += up.second;
+    out.nu1 = nu;
+    out.meta1 = static_cast<LrMeta*>(alloc((size_t)(nu + 1) * sizeof(LrMeta)));
+    int64_t o = 0;
+    for (auto& up : unit_parts) {
+      if (up.second)
+        HM_HIP(hipMemcpyAsync(out.meta1 + o, up.first, up.second * sizeof(LrMeta),
+                              hipMemcpyDeviceToDevice, s));
+      o += up.second;
+    }
+  }
   out.ms_aca = ms_since(t0) - ms_pack;
 
   // ---- product plan: runs, column map, transposed items
