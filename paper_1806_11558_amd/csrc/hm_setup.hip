@@ -1627,14 +1627,21 @@ __global__ void k_lr_meta(const int2* __restrict__ blk, int64_t nb, const int2* 
 // Per column leaf: every dense block whose column cluster contains it gives
 // one item per row leaf (its columns' partial dots in w), every admissible
 // block one V slice.
-__global__ void k_titem_counts(const int2* __restrict__ dns, int64_t nd, const int2* __restrict__ lr,
+// The V side comes from the phase-1 units (column chunks of the V panels:
+// wider items than single blocks, with consecutive terms).
+__global__ void k_titem_counts(const int2* __restrict__ dns, int64_t nd, const LrMeta* __restrict__ units,
                                int64_t nl, const int2* __restrict__ cl_leaves,
                                int64_t* __restrict__ cnt) {
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nd + nl;
        b += (int64_t)gridDim.x * blockDim.x) {
-    const int2 ts = (b < nd) ? dns[b] : lr[b - nd];
-    const int2 lt = cl_leaves[ts.x], ls = cl_leaves[ts.y];
-    cnt[b] = (b < nd) ? (int64_t)(lt.y - lt.x + 1) * (ls.y - ls.x + 1) : (ls.y - ls.x + 1);
+    if (b < nd) {
+      const int2 ts = dns[b];
+      const int2 lt = cl_leaves[ts.x], ls = cl_leaves[ts.y];
+      cnt[b] = (int64_t)(lt.y - lt.x + 1) * (ls.y - ls.x + 1);
+    } else {
+      const LrMeta& U = units[b - nd];
+      cnt[b] = U.sl - U.sf + 1;
+    }
   }
 }
 
@@ -2551,18 +2558,19 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
   }
   {
     Temps tt{s, {}};
-    const int64_t nb_all = in.nd + nl;
+    const int64_t nb_all = in.nd + out.nu1;
     int64_t* cnt = tt.get<int64_t>(nb_all);
     int64_t* off = tt.get<int64_t>(nb_all + 1);
-    k_titem_counts<<<grid_for(nb_all, 256), 256, 0, s>>>(in.dns, in.nd, in.lr, nl, in.cl_leaves, cnt);
+    k_titem_counts<<<grid_for(nb_all, 256), 256, 0, s>>>(in.dns, in.nd, out.meta1, out.nu1,
+                                                         in.cl_leaves, cnt);
     HM_LAUNCH_CHECK();
     out.ntitems = scan_total(cnt, off, nb_all, tmp, s);
     if (out.ntitems >= INT32_MAX) throw Error{HM_ERR_STATE, "more than 2^31 transposed items"};
     TItem* raw = tt.get<TItem>(out.ntitems);
     uint64_t* key = tt.get<uint64_t>(out.ntitems);
     int32_t* idx = tt.get<int32_t>(out.ntitems);
-    k_titem_expand<<<grid_for(nb_all, 64), 64, 0, s>>>(in.dns, in.nd, nl, in.cl, L, off, invD, oD,
-                                                       gcolD, out.meta, lsize, raw, key, idx);
+    k_titem_expand<<<grid_for(nb_all, 64), 64, 0, s>>>(in.dns, in.nd, out.nu1, in.cl, L, off, invD,
+                                                       oD, gcolD, out.meta1, lsize, raw, key, idx);
     HM_LAUNCH_CHECK();
     radix_sort_u64_i32(key, idx, out.ntitems, bits_for(nleaf), s);
     out.titems = static_cast<TItem*>(alloc((out.ntitems + 1) * sizeof(TItem)));
