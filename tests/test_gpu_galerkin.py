@@ -201,3 +201,27 @@ def test_interior_error_falls_with_h(ico):
         H.free()
     assert eps[0] > eps[1] > eps[2]
     assert math.log2(eps[0] / eps[1]) >= 2.5 and math.log2(eps[1] / eps[2]) >= 2.5
+
+
+def test_fixed_rank_mode(gal3):
+    """The paper's fixed-rank ACA (Sec. 4.1, rank k) on the Galerkin matrix:
+    aca_eps = 0 gives every admissible block min(k, m, n) terms (k = 32 also
+    runs the rerun past the first-pass cap of 24), and the product error
+    against the dense Galerkin matrix falls as k grows."""
+    import paper_1806_11558_amd as hm
+    from synthetic import normal_columns
+    V, T, op, A = gal3
+    x = normal_columns(op.n, 1, seed=2)[:, 0]
+    ref = A @ x
+    errs = []
+    for k in (2, 4, 8, 32):
+        say("galerkin fixed rank", k)
+        H = hm.HMatrix(V, T, leaf_size=16, eta=1.0, eps=0.0, max_rank=k, operator="galerkin")
+        lr = H.lr_blocks()
+        cap = np.minimum(k, np.minimum(lr[:, 1] - lr[:, 0], lr[:, 3] - lr[:, 2]))
+        assert np.all(lr[:, 4] <= cap) and np.mean(lr[:, 4] == cap) > 0.99
+        y = H.matvec(torch.tensor(x, device=DEV)).cpu().numpy()
+        errs.append(rel2(y, ref))
+        H.free()
+    say("fixed-rank errors", errs)
+    assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-7
