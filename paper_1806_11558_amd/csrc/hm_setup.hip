@@ -178,27 +178,6 @@ __device__ inline void load_tgt(const Geom<T>& g, int base, int k, Tgt<T, kOpGal
   t.aw = ld_at(g.aw + base, bt);
 }
 
-// The value of lane l of every member (l wavefront-uniform).
-template <typename T>
-__device__ inline Tgt<T, kOpColloc> rdl_tgt(const Tgt<T, kOpColloc>& a, int l) {
-  return Tgt<T, kOpColloc>{rdl_v(a.x, l), rdl_v(a.y, l), rdl_v(a.z, l)};
-}
-template <typename T>
-__device__ inline Tgt<T, kOpGalerkin> rdl_tgt(const Tgt<T, kOpGalerkin>& a, int l) {
-  Tgt<T, kOpGalerkin> r;
-  r.x = rdl_v(a.x, l);
-  r.y = rdl_v(a.y, l);
-  r.z = rdl_v(a.z, l);
-#pragma unroll
-  for (int q = 0; q < kNQ; ++q) {
-    r.ox[q] = rdl_v(a.ox[q], l);
-    r.oy[q] = rdl_v(a.oy[q], l);
-    r.oz[q] = rdl_v(a.oz[q], l);
-  }
-  r.aw = rdl_v(a.aw, l);
-  return r;
-}
-
 // Galerkin entry of two triangles that share no vertex:
 // |T_i| |T_j| / (4 pi) sum_p w_p sum_q w_q / |x_ip - y_jq| (Radon's rule on
 // both triangles, Sec. 2.2), the centroid difference in double.
@@ -374,13 +353,6 @@ __device__ inline bool touching(const Geom<T>& g, int i, int j) {
   const int32_t b0 = g.vid[j], b1 = g.vid[g.n + j], b2 = g.vid[2 * g.n + j];
   return a0 == b0 || a0 == b1 || a0 == b2 || a1 == b0 || a1 == b1 || a1 == b2 || a2 == b0 ||
          a2 == b1 || a2 == b2;
-}
-
-template <typename T>
-__device__ inline T entry_at(const Geom<T>& g, int i, int j) {
-  Src<T> s;
-  load_src(g, j, s);
-  return eval_entry(g.c[i], g.c[g.n + i], g.c[2 * g.n + i], i, s, j);
 }
 
 // Entries at arbitrary (application) index pairs, for checking: one
