@@ -225,3 +225,40 @@ def test_fixed_rank_mode(gal3):
         H.free()
     say("fixed-rank errors", errs)
     assert errs[0] > errs[1] > errs[2] > errs[3] and errs[3] < 1e-7
+
+
+def test_batch_and_fp16_forms(ico):
+    """Two meshes in one Galerkin handle (hm_build_batch: vertex indices of
+    the second mesh are offset, so no pair across the meshes touches) give
+    the products of the two single-mesh handles, block by block; the
+    FP16-factor form at eps 1e-4 is within 10 eps of the dense Galerkin
+    matrix."""
+    import paper_1806_11558_amd as hm
+    from oracle import galerkin
+    from synthetic import normal_columns
+    meshes = [ico(2), ico(3)]
+    sizes = [t.shape[0] for _, t in meshes]
+    x = normal_columns(sum(sizes), 2, seed=4)
+    say("galerkin batch", sizes)
+    Hb = hm.HMatrix.batch(meshes, leaf_size=32, eps=1e-8, operator="galerkin")
+    yb = Hb.matvec(torch.tensor(x, device=DEV)).cpu().numpy()
+    o = 0
+    for (V, T), k in zip(meshes, sizes):
+        H = hm.HMatrix(V, T, leaf_size=32, eps=1e-8, operator="galerkin")
+        y = H.matvec(torch.tensor(x[o:o + k], device=DEV)).cpu().numpy()
+        assert rel2(yb[o:o + k], y) <= 1e-12
+        H.free()
+        o += k
+    Hb.free()
+    V, T = ico(3)
+    A = galerkin.GalerkinOperator(V, T).dense()
+    say("galerkin f16")
+    H = hm.HMatrix(V, T, leaf_size=32, eps=1e-4, precision="f16", operator="galerkin")
+    for vdt in (torch.float64, torch.float32):
+        xt = torch.tensor(x[:A.shape[0]], dtype=vdt, device=DEV)
+        y = H.matvec(xt).double().cpu().numpy()
+        yT = H.matvec_T(xt).double().cpu().numpy()
+        for k in range(2):
+            assert rel2(y[:, k], A @ x[:A.shape[0], k]) <= 10 * 1e-4
+            assert rel2(yT[:, k], A.T @ x[:A.shape[0], k]) <= 10 * 1e-4
+    H.free()
