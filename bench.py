@@ -347,7 +347,7 @@ def run_batch48(args):
         "gmres_status": rs[-1][4],
         "gmres_rel_residual": rs[-1][3].rel_residual,
         "tune_unit_cols_ms": rs[-1][6],
-        "aca_bins": {"edges": [64, 128, 256, 1024, 2048, 4096, "inf"],
+        "aca_bins": {"edges": [64, 128, 256, 512, 1024, 2048, 4096, "inf"],
                      "class": [hm.ACA_CLASSES[c] for c in rs[-1][7][0]],
                      "tuned_bin_class_blocks_ms": rs[-1][7][1]},
         "stats": {k: st[k] for k in ("n_geom", "n_dense", "n_lr", "rank_max", "stored_bytes",

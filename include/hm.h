@@ -342,11 +342,12 @@ typedef enum {
                              order of HM_Q_DENSE_BLOCKS): its stored entries,
                              double[m][n] row-major, rows and columns in
                              Morton order of the block's clusters           */
-  HM_Q_ACA_BINS = 13,     /* int32[7][2] (largest max(m, n) of the size bin,
+  HM_Q_ACA_BINS = 13,     /* int32[8][2] (largest max(m, n) of the size bin,
                              kernel class) the batched ACA ran with; classes:
                              0 one 1,024-thread workgroup per block, 1 one
                              256-thread workgroup, 2, 3, 4 one wavefront with
-                             4, 2, 1 rows and columns per lane              */
+                             4, 2, 1 rows and columns per lane, 5 one
+                             128-thread workgroup                           */
   HM_Q_ACA_TUNE = 14      /* double[k][4] (bin, class, sampled blocks, ms of
                              one pass over them) of every candidate the ACA
                              binning tuner timed; k = 0 without HM_AUTOTUNE */

@@ -20,7 +20,7 @@ HM_GALERKIN = 8
 (HM_Q_STATS, HM_Q_MORTON, HM_Q_PERM, HM_Q_CLUSTERS, HM_Q_BOXES, HM_Q_DENSE_BLOCKS,
  HM_Q_LR_BLOCKS, HM_Q_LEAVES, HM_Q_TIMINGS, HM_Q_LR_FACTORS, HM_Q_KERNEL_TIMES,
  HM_Q_TUNE, HM_Q_DENSE_ENTRIES, HM_Q_ACA_BINS, HM_Q_ACA_TUNE) = range(15)
-ACA_CLASSES = ("wg1024", "wg256", "wave4", "wave2", "wave1")
+ACA_CLASSES = ("wg1024", "wg256", "wave4", "wave2", "wave1", "wg128")
 HM_NPHASE = 8
 HM_NKERNEL = 8
 KERNELS = ("fwd_gather", "fwd_vtx", "fwd_unused", "fwd_panels",
@@ -370,9 +370,9 @@ class HMatrix:
         return out.reshape(-1, 2)
 
     def aca_bins(self) -> np.ndarray:
-        """int32[7][2]: (largest max(m, n) of the size bin, ACA kernel class)
+        """int32[8][2]: (largest max(m, n) of the size bin, ACA kernel class)
         the build ran with (classes in ACA_CLASSES order)."""
-        return hm_query(self._h, HM_Q_ACA_BINS, np.zeros((7, 2), dtype=np.int32))
+        return hm_query(self._h, HM_Q_ACA_BINS, np.zeros((8, 2), dtype=np.int32))
 
     def aca_tune(self) -> np.ndarray:
         """double[k][4] (bin, class, sampled blocks, ms) of every candidate the

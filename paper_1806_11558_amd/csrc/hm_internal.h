@@ -189,9 +189,10 @@ struct MvPlan {
 // Binning of the batched ACA: blocks fall into size bins by max(m, n) (upper
 // edges kAcaBinEdge), and every bin is run by one kernel class: 0 one
 // 1,024-thread workgroup per block, 1 one 256-thread workgroup, 2..4 one
-// wavefront with 4, 2, 1 rows and columns per lane (up to 256, 128, 64).
-constexpr int kAcaBins = 7;
-constexpr int kAcaBinEdge[kAcaBins] = {64, 128, 256, 1024, 2048, 4096, 0x7fffffff};
+// wavefront with 4, 2, 1 rows and columns per lane (up to 256, 128, 64),
+// 5 one 128-thread workgroup.
+constexpr int kAcaBins = 8;
+constexpr int kAcaBinEdge[kAcaBins] = {64, 128, 256, 512, 1024, 2048, 4096, 0x7fffffff};
 struct AcaBins {
   int cls[kAcaBins];
 };

@@ -595,10 +595,11 @@ __device__ inline int piv_index(const Piv& p) {
 
 // Kernel classes of the batched ACA: 0 one 1,024-thread workgroup per
 // block, 1 one 256-thread workgroup, 2..4 one wavefront per block with
-// Q = 4, 2, 1 rows and columns per lane (up to 256, 128, 64).  Each class is
-// its own kernel (its own register allocation) and its own work queue; the
-// size bins of the blocks are mapped to classes by an AcaBins table.
-constexpr int kAcaClasses = 5;
+// Q = 4, 2, 1 rows and columns per lane (up to 256, 128, 64), 5 one
+// 128-thread workgroup.  Each class is its own kernel (its own register
+// allocation) and its own work queue; the size bins of the blocks are mapped
+// to classes by an AcaBins table.
+constexpr int kAcaClasses = 6;
 constexpr int kAcaThreads = 256;
 constexpr int kAcaWaves = kAcaThreads / 64;
 
@@ -1088,7 +1089,7 @@ __device__ void aca_wg(const AcaArgs<T>& A, int b, AcaShared<T, NT>& sh) {
 // Galerkin entries (49 kernel values each) hold the whole row triangle in
 // registers: half the occupancy, no spills.
 template <typename T, int NT, int CLS, int OP>
-__global__ __launch_bounds__(NT, NT == 256 ? (OP == kOpGalerkin ? 2 : 4) : 1) void k_aca_wg(AcaArgs<T> A) {
+__global__ __launch_bounds__(NT, NT == 1024 ? 1 : (OP == kOpGalerkin ? 2 : 4)) void k_aca_wg(AcaArgs<T> A) {
   __shared__ AcaShared<T, NT> sh;
   __shared__ int item_sh;
   while (true) {
@@ -1753,6 +1754,10 @@ void launch_aca_classes(const AcaArgs<T>& A, int* head, hipStream_t s) {
     k_aca_wg<T, 256, 1, OP><<<grid((const void*)k_aca_wg<T, 256, 1, OP>, 256, cnt[1]), 256, 0, s>>>(A);
     HM_LAUNCH_CHECK();
   }
+  if (cnt[5] > 0) {
+    k_aca_wg<T, 128, 5, OP><<<grid((const void*)k_aca_wg<T, 128, 5, OP>, 128, cnt[5]), 128, 0, s>>>(A);
+    HM_LAUNCH_CHECK();
+  }
   {
     if (cnt[2] > 0) {
       k_aca_wave<T, 4, OP><<<grid((const void*)k_aca_wave<T, 4, OP>, kAcaThreads,
@@ -1811,17 +1816,21 @@ void run_aca(const Geom<T>& g, const int2* blk, int64_t nb, const Cluster* cl,
   launch_aca_classes<T, OP>(A, head, s);
 }
 
-// The binning the library uses without tuning: wavefront classes up to 256
-// (one, two or four rows per lane), 256-thread workgroups up to 4,096 and
-// 1,024-thread workgroups above.  Galerkin entries keep the row triangle in
-// registers: one and two rows per lane up to 128 and 256-thread workgroups
-// above (the tuner's choice at N = 1,310,720: 65..128 on two rows per lane
-// 0.98 against 1.63 ms, 129..256 on 256-thread workgroups 1.92 against
-// 2.32 ms for four rows per lane); the 1,024-thread class is not built for
-// them.
+// The binning the library uses without tuning, from the tuner's choices at
+// N = 1,310,720 (FP32): wavefront classes up to 256 (one, two or four rows
+// per lane), 128-thread workgroups up to 1,024 (257..512: 1.46 against
+// 1.98 ms for 256-thread workgroups on a sample of 16,151 blocks; 513..1,024:
+// 2.47 against 2.70 ms), 256-thread workgroups up to 4,096 and 1,024-thread
+// workgroups above.  Galerkin entries keep the row triangle in registers:
+// one and two rows per lane up to 128, 128-thread workgroups up to 1,024 and
+// 256-thread workgroups above (65..128 on two rows per lane 0.96 against
+// 1.07 ms for 128 threads and 1.64 for 256; 129..256 on 128 threads 1.56
+// against 1.91 for 256 threads and 2.32 for four rows per lane; 257..512
+// 2.24 against 2.79; 513..1,024 3.78 against 4.10); the 1,024-thread class
+// is not built for them.
 AcaBins default_aca_bins(int op) {
-  if (op == kOpGalerkin) return AcaBins{{4, 3, 1, 1, 1, 1, 1}};
-  return AcaBins{{4, 3, 2, 1, 1, 1, 0}};
+  if (op == kOpGalerkin) return AcaBins{{4, 3, 5, 5, 5, 1, 1, 1}};
+  return AcaBins{{4, 3, 2, 5, 5, 1, 1, 0}};
 }
 
 // Kernel classes the tuner tries for a bin.
@@ -1830,15 +1839,19 @@ std::vector<int> aca_bin_candidates(int bin, int op) {
     // the wavefront classes with two and four rows per lane run Galerkin
     // entries at one or two waves per SIMD; the 1,024-thread class is not
     // built for them
-    if (bin == 1) return {1, 3};
-    if (bin == 2) return {1, 2};
-    return {bin == 0 ? 4 : 1};
+    if (bin == 0) return {4};
+    if (bin == 1) return {1, 3, 5};
+    if (bin == 2) return {1, 2, 5};
+    if (bin <= 4) return {1, 5};
+    return {1};
   }
   switch (bin) {
     case 0: return {4};
-    case 1: return {3, 1};
-    case 2: return {2, 1};
-    default: return {1, 0};
+    case 1: return {3, 1, 5};
+    case 2: return {2, 1, 5};
+    case 3:
+    case 4: return {1, 5, 0};
+    default: return {1, 0, 5};
   }
 }
 
