@@ -41,15 +41,24 @@ __global__ __launch_bounds__(kGT) void k_dots(const double* __restrict__ Q, int6
   }
 }
 
-// out[k * nr + c] = sum_tile part[(k * tiles + tile) * nr + c]
-__global__ void k_dots_final(const double* __restrict__ part, int nk, int tiles, int nr,
-                             double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nk * nr) return;
-  const int k = e / nr, c = e % nr;
+// out[k * nr + c] = sum_tile part[(k * tiles + tile) * nr + c]: one
+// wavefront per output, lane l adding tiles l, l + 64, ... in order, then a
+// fixed shuffle tree (the same order every call).
+__device__ inline double tile_sum(const double* __restrict__ part, int k, int c, int tiles,
+                                  int nr) {
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int t = 0; t < tiles; ++t) s += part[((int64_t)k * tiles + t) * nr + c];
-  out[e] = s;
+  for (int t = lane; t < tiles; t += 64) s += part[((int64_t)k * tiles + t) * nr + c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  return s;
+}
+__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ part, int nk,
+                                                    int tiles, int nr,
+                                                    double* __restrict__ out) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (e >= nk * nr) return;                          // uniform over the wavefront
+  const double s = tile_sum(part, e / nr, e % nr, tiles, nr);
+  if ((threadIdx.x & 63) == 0) out[e] = s;
 }
 
 // w[i][c] -= sum_{k < nk} Q[k][i][c] h[k][c]   (h on the device)
@@ -137,15 +146,15 @@ __global__ __launch_bounds__(kGT) void k_dots_dev(const double* __restrict__ Q, 
   }
 }
 
-__global__ void k_dots_final_dev(const double* __restrict__ part, const int* __restrict__ jd,
-                                 int nkmax, int tiles, int nr, double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_dots_final_dev(const double* __restrict__ part,
+                                                        const int* __restrict__ jd, int nkmax,
+                                                        int tiles, int nr,
+                                                        double* __restrict__ out) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int nk = jd[0] + 1;
-  if (e >= nk * nr || e >= nkmax * nr) return;
-  const int k = e / nr, c = e % nr;
-  double s = 0.0;
-  for (int t = 0; t < tiles; ++t) s += part[((int64_t)k * tiles + t) * nr + c];
-  out[e] = s;
+  if (e >= nk * nr || e >= nkmax * nr) return;       // uniform over the wavefront
+  const double s = tile_sum(part, e / nr, e % nr, tiles, nr);
+  if ((threadIdx.x & 63) == 0) out[e] = s;
 }
 
 __global__ void k_orth_update_dev(const double* __restrict__ Q, int64_t ldq,
@@ -227,8 +236,8 @@ void gmres_dots_dev(const double* Q, int64_t ldq, const int* jd, int nkmax, cons
   dim3 grid(tiles, nkmax);
   k_dots_dev<<<grid, kGT, 0, s>>>(Q, ldq, jd, w, n, nr, tiles, part);
   HM_LAUNCH_CHECK();
-  k_dots_final_dev<<<(unsigned)ceil_div(nkmax * nr, 256), 256, 0, s>>>(part, jd, nkmax, tiles, nr,
-                                                                        out);
+  k_dots_final_dev<<<(unsigned)ceil_div(nkmax * nr, 4), 256, 0, s>>>(part, jd, nkmax, tiles, nr,
+                                                                      out);
   HM_LAUNCH_CHECK();
 }
 void gmres_orth_update_dev(const double* Q, int64_t ldq, const double* h, const int* jd,
@@ -250,7 +259,7 @@ void gmres_dots(const double* Q, int64_t ldq, int nk, const double* w, int64_t n
   dim3 grid(tiles, nk);
   k_dots<<<grid, kGT, 0, s>>>(Q, ldq, w, n, nr, tiles, part);
   HM_LAUNCH_CHECK();
-  k_dots_final<<<(unsigned)ceil_div(nk * nr, 256), 256, 0, s>>>(part, nk, tiles, nr, out);
+  k_dots_final<<<(unsigned)ceil_div(nk * nr, 4), 256, 0, s>>>(part, nk, tiles, nr, out);
   HM_LAUNCH_CHECK();
 }
 void gmres_orth_update(const double* Q, int64_t ldq, const double* h, int nk, int64_t n, int nr,
