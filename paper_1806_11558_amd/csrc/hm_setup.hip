@@ -1481,9 +1481,14 @@ __global__ void k_block_vlayout(const int32_t* __restrict__ idx, const int64_t* 
 
 // Work units of the forward phase 1 per group: its panel columns in chunks
 // of at most uw(ld) (a group whose leaves differ in ld is one block: one
-// unit).
+// unit).  uw is the widest chunk that the one-pass form of the phase-1
+// kernel takes: R = ld / gran lanes per column, C = 64 / R columns per
+// load (rounded down), four loads per lane.  (A width of 1024 / ld that
+// ignored the rounding sent every full unit of ld = 40, 48 or 60 to the
+// slice-by-slice form.)
 __device__ inline int unit_cols(int64_t ld, int gran) {
-  return (int)min((int64_t)64, 256 * (int64_t)gran / ld);
+  const int64_t R = ld / gran > 0 ? ld / gran : 1;
+  return (int)min((int64_t)64, 4 * (64 / R));
 }
 __global__ void k_group_units(const int64_t* __restrict__ gstart, int64_t ng,
                               const uint64_t* __restrict__ key, const int32_t* __restrict__ idx,
