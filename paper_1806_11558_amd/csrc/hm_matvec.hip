@@ -209,7 +209,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
                                               MvLeaves L, A* __restrict__ z, int64_t n,
                                               const float* __restrict__ su) {
   constexpr int G = Gran<T>::G;
-  constexpr int PMAX = NR <= 2 ? 4 : (NR <= 4 ? 2 : 1);
+  // loads per lane of the one-pass form; the phase-1 units of FP16 slices
+  // are sized for eight, of FP32 and FP64 ones for four
+  constexpr int PMAX = (NR == 1 && sizeof(T) == 2) ? 8 : (NR <= 2 ? 4 : (NR <= 4 ? 2 : 1));
   const int lane = threadIdx.x & 63;
   // wave-uniform block index: descriptors and leaf data come in by scalar loads
   const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -242,8 +244,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
         case 3:
           if constexpr (PMAX >= 3) fwd1_uniform<T, A, NR, 3>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
           break;
-        default:
+        case 4:
           if constexpr (PMAX >= 4) fwd1_uniform<T, A, NR, 4>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
+        case 5:
+          if constexpr (PMAX >= 5) fwd1_uniform<T, A, NR, 5>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
+        case 6:
+          if constexpr (PMAX >= 6) fwd1_uniform<T, A, NR, 6>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
+        case 7:
+          if constexpr (PMAX >= 7) fwd1_uniform<T, A, NR, 7>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
+          break;
+        default:
+          if constexpr (PMAX >= 8) fwd1_uniform<T, A, NR, 8>(M, L, z, r, ld, R, C, cg, g, act, lane, tl);
           break;
       }
     } else {

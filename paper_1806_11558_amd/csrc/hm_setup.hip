@@ -1481,20 +1481,20 @@ __global__ void k_block_vlayout(const int32_t* __restrict__ idx, const int64_t* 
 
 // Work units of the forward phase 1 per group: its panel columns in chunks
 // of at most uw(ld) (a group whose leaves differ in ld is one block: one
-// unit).  uw is the widest chunk that the one-pass form of the phase-1
-// kernel takes: R = ld / gran lanes per column, C = 64 / R columns per
-// load (rounded down), four loads per lane.  (A width of 1024 / ld that
-// ignored the rounding sent every full unit of ld = 40, 48 or 60 to the
-// slice-by-slice form.)
-__device__ inline int unit_cols(int64_t ld, int gran) {
+// unit).  uw is the widest chunk that the one-pass form of the one-column
+// phase-1 kernel takes: R = ld / gran lanes per column, C = 64 / R columns
+// per load (rounded down), `passes` loads per lane.  (A width of 1024 / ld
+// that ignored the rounding sent every full unit of ld = 40, 48 or 60 to
+// the slice-by-slice form.)
+__device__ inline int unit_cols(int64_t ld, int gran, int passes) {
   const int64_t R = ld / gran > 0 ? ld / gran : 1;
-  return (int)min((int64_t)64, 4 * (64 / R));
+  return (int)min((int64_t)64, passes * (64 / R));
 }
 __global__ void k_group_units(const int64_t* __restrict__ gstart, int64_t ng,
                               const uint64_t* __restrict__ key, const int32_t* __restrict__ idx,
                               const int64_t* __restrict__ gw, const int2* __restrict__ blk,
                               const int2* __restrict__ cl_leaves, const int64_t* __restrict__ ldpre,
-                              int gran, int64_t* __restrict__ cnt) {
+                              int gran, int passes, int64_t* __restrict__ cnt) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
        g += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a = gstart[g];
@@ -1503,7 +1503,7 @@ __global__ void k_group_units(const int64_t* __restrict__ gstart, int64_t ng,
       cnt[g] = w > 0 ? 1 : 0;
     } else {
       const int2 ls = cl_leaves[blk[idx[a]].y];
-      const int uw = unit_cols(ldpre[ls.x + 1] - ldpre[ls.x], gran);
+      const int uw = unit_cols(ldpre[ls.x + 1] - ldpre[ls.x], gran, passes);
       cnt[g] = (w + uw - 1) / uw;
     }
   }
@@ -1513,7 +1513,7 @@ __global__ void k_emit_units(const int64_t* __restrict__ gstart, int64_t ng,
                              const uint64_t* __restrict__ key, const int32_t* __restrict__ idx,
                              const int64_t* __restrict__ gw, const int64_t* __restrict__ goff,
                              const int64_t* __restrict__ uoff, const int64_t* __restrict__ tsort,
-                             int64_t toff_base, const LrMeta* __restrict__ meta, int gran,
+                             int64_t toff_base, const LrMeta* __restrict__ meta, int gran, int passes,
                              uint64_t varena, int esize, LrMeta* __restrict__ units) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ng;
        g += (int64_t)gridDim.x * blockDim.x) {
@@ -1526,7 +1526,7 @@ __global__ void k_emit_units(const int64_t* __restrict__ gstart, int64_t ng,
       continue;
     }
     const int64_t ld = B.vld;
-    const int uw = unit_cols(ld, gran);
+    const int uw = unit_cols(ld, gran, passes);
     int64_t o = uoff[g];
     for (int64_t c0 = 0; c0 < w; c0 += uw, ++o) {
       LrMeta U = B;
@@ -2450,15 +2450,20 @@ void build_storage(const Geom<T>& g, const SetupIn& in, Storage& out, const Allo
       HM_LAUNCH_CHECK();
       // phase-1 units of the chunk
       {
+        // rows per granule and loads per lane of the one-column phase-1
+        // kernel (FP16 slices: eight loads of 8 bytes)
         const int gran = sizeof(TL) == 8 ? 2 : 4;
+        const int passes = sizeof(TL) == 2 ? 8 : 4;
         k_group_units<<<grid_for(ngr, 256), 256, 0, s>>>(gstart, ngr, gkey, gidx, gw, in.lr + b0,
-                                                         in.cl_leaves, in.ldpre, gran, gcnt);
+                                                         in.cl_leaves, in.ldpre, gran, passes,
+                                                         gcnt);
         HM_LAUNCH_CHECK();
         const int64_t nu = scan_total(gcnt, guoff, ngr, tmp, s);
         LrMeta* um = keep.get<LrMeta>(nu + 1);
         k_emit_units<<<grid_for(ngr, 256), 256, 0, s>>>(gstart, ngr, gkey, gidx, gw, goff, guoff,
                                                         tsort, toff_base, out.meta + b0, gran,
-                                                        (uint64_t)(uintptr_t)varena, lsize, um);
+                                                        passes, (uint64_t)(uintptr_t)varena, lsize,
+                                                        um);
         HM_LAUNCH_CHECK();
         unit_parts.push_back({um, nu});
       }
