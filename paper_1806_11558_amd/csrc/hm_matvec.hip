@@ -632,16 +632,51 @@ __device__ inline void fwd1x_pass_rows(const LrMeta& M, const MvLeaves& L,
 // order, so lane (term lr, quad lq) reads the four consecutive rows
 // 4 lq .. 4 lq + 3 of a tile as one granule and feeds them to four
 // instructions: step e takes row 4 lq + e of the tile from lane group lq,
-// and the x values follow the same rows.  Four tiles are in flight, every
-// load unconditional (clamped to the slice, the value zeroed outside it)
-// and every product issued, so no branch surrounds an MFMA.  Rows in
+// and the x values follow the same rows.  Up to four tiles are in flight,
+// every load unconditional (clamped to the slice, the value zeroed outside
+// it) and every product issued, so no branch surrounds an MFMA.  Rows in
 // [m, ld) of a slice are zero padding; granules that start at or past m
-// are zeroed.
+// are zeroed.  A leaf's rows go in groups of four tiles and a last group of
+// as many tiles as remain (three for the 40-row leaves of a sphere, where
+// a fixed group of four spent a quarter of its loads and products on
+// padding).
+template <typename T, typename A, int NR, int NTL, int IU>
+__device__ inline void fwd1x_tiles_gran(const T* __restrict__ S, int ld, int m, int i00,
+                                        const A* __restrict__ zx, int lo, const int (&tc)[NTL],
+                                        const bool (&tok)[NTL], bool rhs, int lr, int lq,
+                                        typename Mfma<A>::V (&acc)[4]) {
+  A av[IU][NTL][4], bv[IU][4];
+#pragma unroll
+  for (int u = 0; u < IU; ++u) {
+    const int i0 = i00 + 16 * u + 4 * lq;       // first row of the lane's granule
+    const bool okg = i0 < m;
+    const int ig = okg ? i0 : 0;
+#pragma unroll
+    for (int t = 0; t < NTL; ++t) {
+      A v[4];
+      load4<A, T>(S + (int64_t)tc[t] * ld + ig, v);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) av[u][t][e] = (okg && tok[t]) ? v[e] : (A)0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool okr = rhs && i0 + e < m;
+      const A x = zx[(int64_t)(lo + (okr ? i0 + e : 0)) * NR + (rhs ? lr : 0)];
+      bv[u][e] = okr ? x : (A)0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < IU; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av[u][t][e], bv[u][e], acc[t]);
+}
+
 template <typename T, typename A, int NR, int NTL>
 __device__ inline void fwd1x_pass_gran(const LrMeta& M, const MvLeaves& L,
                                        const A* __restrict__ zx, int tg, int r, int lr, int lq,
                                        typename Mfma<A>::V (&acc)[4]) {
-  constexpr int IU = 4;
   const T* S = reinterpret_cast<const T*>((uintptr_t)M.vptr);
   int lo = L.lo[M.sf];                    // the leaves of sigma are consecutive
   int tc[NTL];                            // clamped term of each tile
@@ -656,33 +691,14 @@ __device__ inline void fwd1x_pass_gran(const LrMeta& M, const MvLeaves& L,
   for (int lf = M.sf; lf <= M.sl; ++lf) {
     const int m = L.m[lf];
     const int ld = (int)(L.ldpre[lf + 1] - L.ldpre[lf]);
-    for (int i00 = 0; i00 < m; i00 += 16 * IU) {
-      A av[IU][NTL][4], bv[IU][4];
-#pragma unroll
-      for (int u = 0; u < IU; ++u) {
-        const int i0 = i00 + 16 * u + 4 * lq;       // first row of the lane's granule
-        const bool okg = i0 < m;
-        const int ig = okg ? i0 : 0;
-#pragma unroll
-        for (int t = 0; t < NTL; ++t) {
-          A v[4];
-          load4<A, T>(S + (int64_t)tc[t] * ld + ig, v);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) av[u][t][e] = (okg && tok[t]) ? v[e] : (A)0;
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool okr = rhs && i0 + e < m;
-          const A x = zx[(int64_t)(lo + (okr ? i0 + e : 0)) * NR + (rhs ? lr : 0)];
-          bv[u][e] = okr ? x : (A)0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < IU; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int t = 0; t < NTL; ++t) acc[t] = mfma16(av[u][t][e], bv[u][e], acc[t]);
+    int i00 = 0;
+    for (; i00 + 64 <= m; i00 += 64)
+      fwd1x_tiles_gran<T, A, NR, NTL, 4>(S, ld, m, i00, zx, lo, tc, tok, rhs, lr, lq, acc);
+    switch ((m - i00 + 15) / 16) {        // uniform over the wavefront
+      case 1: fwd1x_tiles_gran<T, A, NR, NTL, 1>(S, ld, m, i00, zx, lo, tc, tok, rhs, lr, lq, acc); break;
+      case 2: fwd1x_tiles_gran<T, A, NR, NTL, 2>(S, ld, m, i00, zx, lo, tc, tok, rhs, lr, lq, acc); break;
+      case 3: fwd1x_tiles_gran<T, A, NR, NTL, 3>(S, ld, m, i00, zx, lo, tc, tok, rhs, lr, lq, acc); break;
+      default: break;
     }
     S += (int64_t)ld * M.vw;
     lo += m;
