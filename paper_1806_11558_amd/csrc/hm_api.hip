@@ -451,7 +451,7 @@ void build_impl(hm_handle* h, const double* V_host, int64_t nv, const int32_t* T
 
   // ---- geometry in Morton order
   h->c = h->alloc_t<double>(3 * n);
-  h->o = h->alloc(3 * kNQ * n * sizeof(T));
+  h->o = h->alloc(3 * kNV * n * sizeof(T));
   h->aw = h->alloc(n * sizeof(T));
   h->sf = h->alloc(n * sizeof(T));
   launch_geom_sorted<T>(V, Tri, h->perm, n, h->c, (T*)h->o, (T*)h->aw, (T*)h->sf, s);

@@ -105,9 +105,12 @@ __global__ void k_morton(const double* __restrict__ C, int64_t n, int64_t off, i
 }
 
 // Quadrature data and self-terms in Morton order.  For position p the source
-// triangle is t = perm[p]; node y_q = (l0 v0 + l1 v1) + l2 v2 is stored as
-// the offset y_q - c in the storage type, so that a distance |x_i - y_jq| is
-// formed as (x_i - c_j) - (y_jq - c_j) with the large part in double.
+// triangle is t = perm[p]; its vertex offsets d_k = v_k - c are stored in
+// the storage type, and the nodes of the rule are c and c + beta d_k (beta1
+// for nodes 1..3, beta2 for 4..6), so that a distance |x_i - y_jq| is formed
+// as (x_i - c_j) - beta d_k with the large part in double.  Nine values per
+// triangle instead of the 21 node offsets: the entry kernels, which stream
+// these records, read 64 bytes per source in FP32 instead of 116.
 //
 // Self-term (x_i inside the flat triangle): the triangle is split at x_i over
 // its edges; with h the distance of x_i to an edge line and l_a, l_b the
@@ -117,12 +120,6 @@ template <typename T>
 __global__ void k_geom_sorted(const double* __restrict__ V, const int32_t* __restrict__ Tri,
                               const int32_t* __restrict__ perm, int64_t n, double* __restrict__ c,
                               T* __restrict__ o, T* __restrict__ aw, T* __restrict__ sf) {
-  const double bary[kNQ][3] = {
-      {1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0},
-      {Radon7::a1, Radon7::a1, Radon7::b1}, {Radon7::a1, Radon7::b1, Radon7::a1},
-      {Radon7::b1, Radon7::a1, Radon7::a1},
-      {Radon7::a2, Radon7::a2, Radon7::b2}, {Radon7::a2, Radon7::b2, Radon7::a2},
-      {Radon7::b2, Radon7::a2, Radon7::a2}};
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = perm[p];
@@ -139,14 +136,11 @@ __global__ void k_geom_sorted(const double* __restrict__ V, const int32_t* __res
       cc[d] = ((v[0][d] + v[1][d]) + v[2][d]) / 3.0;
       c[d * n + p] = cc[d];
     }
+    // vertex offsets d_k = v_k - c; the rule's nodes are c and c + beta d_k
 #pragma unroll
-    for (int q = 0; q < kNQ; ++q) {
+    for (int k = 0; k < kNV; ++k)
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        double y = (bary[q][0] * v[0][d] + bary[q][1] * v[1][d]) + bary[q][2] * v[2][d];
-        o[(int64_t)(d * kNQ + q) * n + p] = (T)(y - cc[d]);
-      }
-    }
+      for (int d = 0; d < 3; ++d) o[(int64_t)(d * kNV + k) * n + p] = (T)(v[k][d] - cc[d]);
     const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
     const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
     const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],

@@ -28,6 +28,7 @@ void set_error(const std::string& msg);
 // ---------------------------------------------------------------- constants
 constexpr int kMortonBits = 21;
 constexpr int kNQ = 7;              // quadrature nodes of the triangle rule
+constexpr int kNV = 3;              // vertices of a triangle
 constexpr int kMaxLeaf = 64;        // leaf clusters fit one wavefront
 constexpr int kMaxRank = 256;
 constexpr int64_t kAcaPoolCap = int64_t(40) << 30;  // bytes of ACA working slots at once
@@ -35,6 +36,9 @@ constexpr int kAcaFirstRank = 24;   // rank cap of the first ACA pass (slot size
 
 // Radon's seven-point degree-5 rule: weights normalised to sum to one.
 // Node q = 0 is the centroid; nodes 1..3 use (a1, a1, b1), 4..6 (a2, a2, b2).
+// A node with barycentric weights (a, a, b), b on vertex v, lies at
+// c + (b - a) (v - c) (c the centroid; 2a + b = 1): beta1 = b1 - a1 =
+// (1 + sqrt 15) / 7 and beta2 = b2 - a2 = (1 - sqrt 15) / 7.
 struct Radon7 {
   static constexpr double s15 = 3.872983346207416885179265399782399611;  // sqrt(15)
   static constexpr double a1 = (6.0 - s15) / 21.0;
@@ -44,14 +48,17 @@ struct Radon7 {
   static constexpr double w0 = 9.0 / 40.0;
   static constexpr double w1 = (155.0 - s15) / 1200.0;
   static constexpr double w2 = (155.0 + s15) / 1200.0;
+  static constexpr double beta1 = (1.0 + s15) / 7.0;
+  static constexpr double beta2 = (1.0 - s15) / 7.0;
 };
 
 
 // ---------------------------------------------------------------- device data
 // Geometry in Morton order, structure of arrays.
 //   c   : double[3][n]     centroids (collocation points)
-//   o   : T[3*7][n]        quadrature node minus centroid, x for q=0..6,
-//                          then y, then z
+//   o   : T[3*3][n]        vertex minus centroid, d_k = v_k - c: x of
+//                          k = 0..2, then y, then z (the six outer nodes
+//                          of the rule are c + beta d_k)
 //   aw  : T[n]             |T_j| / (4 pi)
 //   sf  : T[n]             analytic self-term a_jj
 //   v   : double[9][n]     vertices (v0 xyz, v1 xyz, v2 xyz), Galerkin only

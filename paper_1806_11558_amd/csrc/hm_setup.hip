@@ -20,10 +20,12 @@
 namespace hm {
 
 // ------------------------------------------------------------------ entries
+// Source triangle j: centroid, vertex offsets d_k = v_k - c (the nodes of
+// the rule are c and c + beta d_k), |T_j| / (4 pi) and the self-term.
 template <typename T>
 struct Src {
   double cx, cy, cz;
-  T ox[kNQ], oy[kNQ], oz[kNQ];
+  T dx[kNV], dy[kNV], dz[kNV];
   T aw, sf;
 };
 
@@ -45,10 +47,10 @@ __device__ inline void load_src(const Geom<T>& g, int j, Src<T>& s) {
   s.cy = g.c[g.n + j];
   s.cz = g.c[2 * g.n + j];
 #pragma unroll
-  for (int q = 0; q < kNQ; ++q) {
-    s.ox[q] = g.o[(int64_t)q * g.n + j];
-    s.oy[q] = g.o[(int64_t)(kNQ + q) * g.n + j];
-    s.oz[q] = g.o[(int64_t)(2 * kNQ + q) * g.n + j];
+  for (int k = 0; k < kNV; ++k) {
+    s.dx[k] = g.o[(int64_t)k * g.n + j];
+    s.dy[k] = g.o[(int64_t)(kNV + k) * g.n + j];
+    s.dz[k] = g.o[(int64_t)(2 * kNV + k) * g.n + j];
   }
   s.aw = g.aw[j];
   s.sf = g.sf[j];
@@ -64,10 +66,10 @@ __device__ inline void load_src_u(const Geom<T>& g, int j, Src<T>& s) {
   s.cy = ld_at(g.c + g.n, bd);
   s.cz = ld_at(g.c + 2 * g.n, bd);
 #pragma unroll
-  for (int q = 0; q < kNQ; ++q) {
-    s.ox[q] = ld_at(g.o + (int64_t)q * g.n, bt);
-    s.oy[q] = ld_at(g.o + (int64_t)(kNQ + q) * g.n, bt);
-    s.oz[q] = ld_at(g.o + (int64_t)(2 * kNQ + q) * g.n, bt);
+  for (int k = 0; k < kNV; ++k) {
+    s.dx[k] = ld_at(g.o + (int64_t)k * g.n, bt);
+    s.dy[k] = ld_at(g.o + (int64_t)(kNV + k) * g.n, bt);
+    s.dz[k] = ld_at(g.o + (int64_t)(2 * kNV + k) * g.n, bt);
   }
   s.aw = ld_at(g.aw, bt);
   s.sf = ld_at(g.sf, bt);
@@ -81,6 +83,27 @@ __device__ inline void load_src_u(const Geom<T>& g, int j, Src<T>& s) {
 __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline double rsq(double x) { return 1.0 / sqrt(x); }
 
+// sum_q w_q / |p - y_q| over the seven nodes of source s, with p the point
+// minus the source's centroid: node 0 at offset 0, nodes 1..3 at beta1 d_k
+// and 4..6 at beta2 d_k (k = 2, 1, 0: the vertex that carries weight b).
+template <typename T>
+__device__ inline T rule7(T px, T py, T pz, const Src<T>& s) {
+  const T b1 = (T)Radon7::beta1, b2 = (T)Radon7::beta2;
+  const T a0 = rsq(px * px + py * py + pz * pz);
+  T a1 = 0, a2 = 0;
+#pragma unroll
+  for (int k = kNV - 1; k >= 0; --k) {
+    const T ex = px - b1 * s.dx[k], ey = py - b1 * s.dy[k], ez = pz - b1 * s.dz[k];
+    a1 += rsq(ex * ex + ey * ey + ez * ez);
+  }
+#pragma unroll
+  for (int k = kNV - 1; k >= 0; --k) {
+    const T ex = px - b2 * s.dx[k], ey = py - b2 * s.dy[k], ez = pz - b2 * s.dz[k];
+    a2 += rsq(ex * ex + ey * ey + ez * ez);
+  }
+  return (T)Radon7::w0 * a0 + (T)Radon7::w1 * a1 + (T)Radon7::w2 * a2;
+}
+
 // a(i, j) = |T_j|/(4 pi) sum_q w_q / |x_i - y_jq| for i != j (seven-point
 // Radon rule on the single-layer kernel of Sec. 2.1), the analytic self-term
 // for i == j.  Positions i, j are Morton positions; (xi, yi, zi) = x_i.
@@ -88,16 +111,7 @@ template <typename T>
 __device__ inline T eval_entry(double xi, double yi, double zi, int i, const Src<T>& s, int j) {
   if (i == j) return s.sf;
   const T dx = (T)(xi - s.cx), dy = (T)(yi - s.cy), dz = (T)(zi - s.cz);
-  T acc[3] = {0, 0, 0};
-#pragma unroll
-  for (int q = 0; q < kNQ; ++q) {
-    const T ex = dx - s.ox[q], ey = dy - s.oy[q], ez = dz - s.oz[q];
-    const T r = rsq(ex * ex + ey * ey + ez * ez);
-    acc[q == 0 ? 0 : (q <= 3 ? 1 : 2)] += r;
-  }
-  const T w =
-      (T)Radon7::w0 * acc[0] + (T)Radon7::w1 * acc[1] + (T)Radon7::w2 * acc[2];
-  return w * s.aw;
+  return rule7(dx, dy, dz, s) * s.aw;
 }
 
 // ---- wavefront primitives (gfx9 DPP).  The row-of-16 butterfly (quad
@@ -151,7 +165,7 @@ struct Tgt<T, kOpColloc> {
 template <typename T>
 struct Tgt<T, kOpGalerkin> {
   double x, y, z;
-  T ox[kNQ], oy[kNQ], oz[kNQ];
+  T dx[kNV], dy[kNV], dz[kNV];     // vertex offsets, as in Src
   T aw;
 };
 
@@ -170,10 +184,10 @@ __device__ inline void load_tgt(const Geom<T>& g, int base, int k, Tgt<T, kOpGal
   t.y = ld_at(g.c + g.n + base, b8);
   t.z = ld_at(g.c + 2 * g.n + base, b8);
 #pragma unroll
-  for (int q = 0; q < kNQ; ++q) {
-    t.ox[q] = ld_at(g.o + (int64_t)q * g.n + base, bt);
-    t.oy[q] = ld_at(g.o + (int64_t)(kNQ + q) * g.n + base, bt);
-    t.oz[q] = ld_at(g.o + (int64_t)(2 * kNQ + q) * g.n + base, bt);
+  for (int k = 0; k < kNV; ++k) {
+    t.dx[k] = ld_at(g.o + (int64_t)k * g.n + base, bt);
+    t.dy[k] = ld_at(g.o + (int64_t)(kNV + k) * g.n + base, bt);
+    t.dz[k] = ld_at(g.o + (int64_t)(2 * kNV + k) * g.n + base, bt);
   }
   t.aw = ld_at(g.aw + base, bt);
 }
@@ -184,20 +198,17 @@ __device__ inline void load_tgt(const Geom<T>& g, int base, int k, Tgt<T, kOpGal
 template <typename T>
 __device__ inline T eval_far_g(const Tgt<T, kOpGalerkin>& t, const Src<T>& s) {
   const T dx = (T)(t.x - s.cx), dy = (T)(t.y - s.cy), dz = (T)(t.z - s.cz);
-  T outer[3] = {0, 0, 0};
+  const T b1 = (T)Radon7::beta1, b2 = (T)Radon7::beta2;
+  // outer nodes of T_i in the same order as the inner ones
+  const T o0 = rule7(dx, dy, dz, s);
+  T o1 = 0, o2 = 0;
 #pragma unroll
-  for (int p = 0; p < kNQ; ++p) {
-    const T px = dx + t.ox[p], py = dy + t.oy[p], pz = dz + t.oz[p];
-    T acc[3] = {0, 0, 0};
+  for (int k = kNV - 1; k >= 0; --k)
+    o1 += rule7(dx + b1 * t.dx[k], dy + b1 * t.dy[k], dz + b1 * t.dz[k], s);
 #pragma unroll
-    for (int q = 0; q < kNQ; ++q) {
-      const T ex = px - s.ox[q], ey = py - s.oy[q], ez = pz - s.oz[q];
-      acc[q == 0 ? 0 : (q <= 3 ? 1 : 2)] += rsq(ex * ex + ey * ey + ez * ez);
-    }
-    outer[p == 0 ? 0 : (p <= 3 ? 1 : 2)] +=
-        (T)Radon7::w0 * acc[0] + (T)Radon7::w1 * acc[1] + (T)Radon7::w2 * acc[2];
-  }
-  const T sum = (T)Radon7::w0 * outer[0] + (T)Radon7::w1 * outer[1] + (T)Radon7::w2 * outer[2];
+  for (int k = kNV - 1; k >= 0; --k)
+    o2 += rule7(dx + b2 * t.dx[k], dy + b2 * t.dy[k], dz + b2 * t.dz[k], s);
+  const T sum = (T)Radon7::w0 * o0 + (T)Radon7::w1 * o1 + (T)Radon7::w2 * o2;
   return sum * (t.aw * s.aw) * (T)12.566370614359172954;   // |T_i||T_j|/(4 pi) = 4 pi aw_i aw_j
 }
 
