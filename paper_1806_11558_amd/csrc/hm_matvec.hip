@@ -1013,60 +1013,95 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, MvLea
 }
 
 // s_b[l] = sum over the row leaves of b of w[ucol + l]  ->  z[n + toff + l].
-// One wavefront per block.  With r <= 16 (32) the wavefront splits into four
-// (two) groups of 16 (32) lanes, lane = (group, term); group g adds the row
-// leaves q = g, g + groups, ... and the groups are added by shifts at the end.
-// Ranks above 64 take their terms 64 at a time.
+// The sums of one block, lane = (group, term): with r <= 16 (32) the
+// wavefront splits into four (two) groups of 16 (32) lanes; group g adds the
+// row leaves q = g, g + groups, ... and the groups are added by shifts at
+// the end.  Ranks above 64 take their terms 64 at a time.
+template <typename A, int NR>
+__device__ inline void tr_sums_block(const LrMeta& M, const int64_t* __restrict__ ucol,
+                                     const A* __restrict__ w, A* __restrict__ z, int64_t n,
+                                     const float* __restrict__ su, int lane) {
+  const int nk = M.tl - M.tf + 1;
+  const int gw = M.r <= 16 ? 16 : (M.r <= 32 ? 32 : 64);   // uniform over the wavefront
+  const int ng = 64 / gw, grp = lane / gw;
+  for (int t0 = 0; t0 < M.r; t0 += 64) {
+    const int l = t0 + lane % gw;
+    const bool ok = l < M.r;
+    A acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0;
+    if (ok) {
+      // four row leaves per step with their loads in flight together
+      int q = grp;
+      for (; q + 3 * ng < nk; q += 4 * ng) {
+        A v[4][NR];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          load_row<A, NR>(w + (ucol[M.ub + q + u * ng] + l) * NR, v[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) acc[k] += v[u][k];
+      }
+      for (; q < nk; q += ng) {
+        const int64_t col = ucol[M.ub + q] + l;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
+      }
+    }
+    for (int sh = gw; sh < 64; sh <<= 1) {
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const A o = __shfl_down(acc[k], sh, 64);
+        acc[k] += o;
+      }
+    }
+    if (grp == 0 && ok) {
+      const A sc = su ? (A)su[M.toff + l] : (A)1;
+#pragma unroll
+      for (int k = 0; k < NR; ++k) z[(n + M.toff + l) * NR + k] = acc[k] * sc;
+    }
+  }
+}
+
+// One wavefront per four consecutive blocks.  When all four have rank <= 16
+// (most blocks: the small ones), each 16-lane group takes one block and adds
+// its row leaves in order, so the four dependent chains (descriptor, column
+// offsets, sums, store) overlap; otherwise the wavefront takes the four
+// blocks one after another as above.
 template <typename A, int NR>
 __global__ __launch_bounds__(256) void k_tr_sums(const LrMeta* __restrict__ meta, int64_t nl,
                                                  const int64_t* __restrict__ ucol,
                                                  const A* __restrict__ w, A* __restrict__ z,
                                                  int64_t n, const float* __restrict__ su) {
   const int lane = threadIdx.x & 63;
-  // wave-uniform block index: descriptors and leaf data come in by scalar loads
   const int64_t wid = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nw = (int64_t)gridDim.x * 4;
-  for (int64_t b = wid; b < nl; b += nw) {
-    const LrMeta M = meta[b];
-    const int nk = M.tl - M.tf + 1;
-    const int gw = M.r <= 16 ? 16 : (M.r <= 32 ? 32 : 64);   // uniform over the wavefront
-    const int ng = 64 / gw, grp = lane / gw;
-    for (int t0 = 0; t0 < M.r; t0 += 64) {
-      const int l = t0 + lane % gw;
-      const bool ok = l < M.r;
-      A acc[NR];
+  const int64_t nq = (nl + 3) / 4;
+  const int grp = lane >> 4, l = lane & 15;
+  for (int64_t qd = wid; qd < nq; qd += nw) {
+    const int64_t b = qd * 4 + grp;
+    const bool has = b < nl;
+    const LrMeta M = meta[has ? b : nl - 1];
+    if (__all(!has || M.r <= 16)) {                     // uniform over the wavefront
+      if (has && l < M.r) {
+        const int nk = M.tl - M.tf + 1;
+        A acc[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) acc[k] = 0;
-      if (ok) {
-        // four row leaves per step with their loads in flight together
-        int q = grp;
-        for (; q + 3 * ng < nk; q += 4 * ng) {
-          A v[4][NR];
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            load_row<A, NR>(w + (ucol[M.ub + q + u * ng] + l) * NR, v[u]);
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int k = 0; k < NR; ++k) acc[k] += v[u][k];
-        }
-        for (; q < nk; q += ng) {
+        for (int k = 0; k < NR; ++k) acc[k] = 0;
+        for (int q = 0; q < nk; ++q) {
           const int64_t col = ucol[M.ub + q] + l;
 #pragma unroll
           for (int k = 0; k < NR; ++k) acc[k] += w[col * NR + k];
         }
-      }
-      for (int sh = gw; sh < 64; sh <<= 1) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-          const A o = __shfl_down(acc[k], sh, 64);
-          acc[k] += o;
-        }
-      }
-      if (grp == 0 && ok) {
         const A sc = su ? (A)su[M.toff + l] : (A)1;
 #pragma unroll
         for (int k = 0; k < NR; ++k) z[(n + M.toff + l) * NR + k] = acc[k] * sc;
+      }
+    } else {
+      for (int g = 0; g < 4; ++g) {
+        const int64_t bg = qd * 4 + g;
+        if (bg < nl) tr_sums_block<A, NR>(meta[bg], ucol, w, z, n, su, lane);
       }
     }
   }
@@ -1231,9 +1266,6 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
   k_gather<VT, A><<<grid_for(P.n * NR, 256, 4096), 256, 0, s>>>(x, nrhs, k0, NR, P.perm, P.n, z);
   HM_LAUNCH_CHECK();
   if (pr) HM_HIP(hipEventRecord(pr->ev[1], s));
-  // blocks differ widely in size and come largest first, so they stay
-  // round-robin over the XCDs
-  const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nlr, 4), 1 << 20));
   if (!transposed) {
     // phase 1 over its work units (column chunks of the V panels)
     const unsigned g1 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P.nu1, 4), 1 << 20));
@@ -1275,7 +1307,11 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
     }
     if (pr) HM_HIP(hipEventRecord(pr->ev[2], s));
     if (P.nlr > 0) {
-      k_tr_sums<A, NR><<<gb, 256, 0, s>>>(P.meta, P.nlr, P.ucol, w, z, P.n, P.su);
+      // four blocks per wavefront, four wavefronts per workgroup; blocks
+      // come largest first and stay round-robin over the XCDs
+      const unsigned gq =
+          (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ceil_div(P.nlr, 4), 4), 1 << 20));
+      k_tr_sums<A, NR><<<gq, 256, 0, s>>>(P.meta, P.nlr, P.ucol, w, z, P.n, P.su);
       HM_LAUNCH_CHECK();
     }
     if (pr) HM_HIP(hipEventRecord(pr->ev[3], s));
