@@ -421,17 +421,14 @@ class HMatrix:
         """Plain U (m x r) and V (n x r) of low-rank block b."""
         blk = self.lr_blocks()[b]
         m, n, r = int(blk[1] - blk[0]), int(blk[3] - blk[2]), int(blk[4])
-        buf = np.zeros(max(r * (m + n), 1), dtype=self.storage_dtype)
-        buf.view(np.int64)[0] = b if buf.itemsize == 8 else 0
-        if buf.itemsize != 8:
-            # the block index travels in the first 8 bytes of the buffer
-            raw = np.zeros(max(r * (m + n), 2), dtype=np.float32)
-            raw.view(np.int64)[0] = b
-            _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, raw.ctypes.data, raw.nbytes, None))
-            buf = raw[: r * (m + n)]
-        else:
-            _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, buf.ctypes.data, buf.nbytes, None))
-            buf = buf[: r * (m + n)]
+        size = np.dtype(self.storage_dtype).itemsize
+        nbytes = r * (m + n) * size
+        # the block index travels in the first 8 bytes of the buffer, which
+        # holds at least those 8 bytes whatever the rank
+        raw = np.zeros(max(nbytes, 8), dtype=np.uint8)
+        raw[:8].view(np.int64)[0] = b
+        _check(lib().hm_query(self._h, HM_Q_LR_FACTORS, raw.ctypes.data, raw.nbytes, None))
+        buf = raw[:nbytes].view(self.storage_dtype)
         U = buf[: m * r].reshape(r, m).T.astype(np.float64)
         V = buf[m * r:].reshape(r, n).T.astype(np.float64)
         return U, V

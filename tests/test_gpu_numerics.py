@@ -161,6 +161,35 @@ def test_edge_sizes(level, nsub, leaf):
     H.free()
 
 
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-8), ("f32", 1e-6)])
+def test_lr_factors_odd_sizes(prec, eps):
+    """Stored factors of blocks with odd row and column counts (777
+    triangles, leaf 13), read back through HM_Q_LR_FACTORS, against the
+    exact blocks within 10 eps; blocks of every rank parity, rank 0
+    included when one occurs."""
+    import paper_1806_11558_amd as hm
+    from oracle import bem
+    from synthetic import icosphere
+    V, T = icosphere(3)
+    T = T[:777]
+    op = bem.Operator(V, T)
+    A = op.dense()
+    H = hm.HMatrix(V, T, leaf_size=13, eps=eps, precision=prec)
+    perm = H.perm()
+    lb = H.lr_blocks()
+    odd = np.nonzero(((lb[:, 1] - lb[:, 0]) + (lb[:, 3] - lb[:, 2])) % 2 == 1)[0]
+    say("lr factors odd sizes", prec, len(odd), "of", len(lb))
+    assert len(odd) > 0
+    for b in odd[:40].tolist():
+        r0, r1, c0, c1, rank, cap = lb[b]
+        U, Vf = H.lr_factors(int(b))
+        assert U.shape == (r1 - r0, rank) and Vf.shape == (c1 - c0, rank)
+        Ab = A[np.ix_(perm[r0:r1], perm[c0:c1])]
+        err = np.linalg.norm(Ab - U @ Vf.T) / np.linalg.norm(Ab)
+        assert err <= 10 * eps, (b, rank, err)
+    H.free()
+
+
 @pytest.mark.parametrize("nsub,leaf,ld", [(1000, 8, 8), (1000, 32, 32), (1280, 64, 40),
                                            (1000, 64, 64)])
 @pytest.mark.parametrize("prec,eps,bound", [("f64", 1e-8, 1e-7), ("f32", 1e-6, 1e-5)])
