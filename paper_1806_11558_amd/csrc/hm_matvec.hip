@@ -513,16 +513,18 @@ __global__ __launch_bounds__(256) void k_fwd2(const Run* __restrict__ runs, MvLe
 }
 
 // y rows of every leaf = sum of its units' partial rows (in unit order),
-// scattered to application order.
+// scattered to application order.  One wavefront per leaf (a leaf has at
+// most 64 rows).
 template <typename A, typename VT, int NR>
 __global__ __launch_bounds__(256) void k_fwd2_sum(MvLeaves L, const int32_t* __restrict__ ubeg,
                                                   const A* __restrict__ ypart, int ldmax,
                                                   const int32_t* __restrict__ perm,
                                                   VT* __restrict__ y, int nrhs, int k0) {
-  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < L.nleaf; c += (int64_t)gridDim.x * 4) {
     const int m = L.m[c], lo = L.lo[c];
     const int u0 = ubeg[c], u1 = ubeg[c + 1];
-    for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
+    for (int e = lane; e < m * NR; e += 64) {
       const int row = e / NR, k = e % NR;
       A v = 0;
       for (int u = u0; u < u1; ++u) v += ypart[(int64_t)u * ldmax * NR + e];
@@ -1243,10 +1245,11 @@ template <typename A, typename VT, int NR>
 __global__ __launch_bounds__(256) void k_tr2_sum(MvLeaves L, int S, const A* __restrict__ ypart,
                                                  int ldmax, const int32_t* __restrict__ perm,
                                                  VT* __restrict__ y, int nrhs, int k0) {
-  for (int64_t c = blockIdx.x; c < L.nleaf; c += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < L.nleaf; c += (int64_t)gridDim.x * 4) {
     const int m = L.m[c], lo = L.lo[c];
     const A* yp = ypart + c * S * ldmax * NR;
-    for (int e = threadIdx.x; e < m * NR; e += blockDim.x) {
+    for (int e = lane; e < m * NR; e += 64) {
       const int row = e / NR, k = e % NR;
       A v = 0;
       for (int sp = 0; sp < S; ++sp) v += yp[(int64_t)sp * ldmax * NR + e];
@@ -1296,7 +1299,7 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
                                                  static_cast<A*>(P.ypart), P.ldmax);
       HM_LAUNCH_CHECK();
     }
-    k_fwd2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(P.L.nleaf, P.grid), 256, 0, s>>>(
+    k_fwd2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(ceil_div(P.L.nleaf, 4), P.grid), 256, 0, s>>>(
         P.L, P.ubeg, static_cast<const A*>(P.ypart), P.ldmax, P.perm, y, nrhs, k0);
     HM_LAUNCH_CHECK();
   } else {
@@ -1325,7 +1328,7 @@ static void mv_chunk(const MvPlan& P, const VT* x, VT* y, int nrhs, int k0, bool
                                             S, static_cast<A*>(P.ypart), P.ldmax);
     HM_LAUNCH_CHECK();
     if (S > 1) {
-      k_tr2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(P.L.nleaf, P.grid), 256, 0, s>>>(
+      k_tr2_sum<A, VT, NR><<<(unsigned)std::min<int64_t>(ceil_div(P.L.nleaf, 4), P.grid), 256, 0, s>>>(
           P.L, S, static_cast<const A*>(P.ypart), P.ldmax, P.perm, y, nrhs, k0);
       HM_LAUNCH_CHECK();
     }
