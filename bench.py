@@ -170,7 +170,10 @@ VALU_PEAK_TFLOPS = {"f32": 78.6, "f16": 78.6, "f64": 78.6}
 
 def setup_roofline(o, form, operator="collocation"):
     """ALU roofline of the near field + ACA phases: entry evaluations (dense
-    entries + ACA rows and columns) x FLOPS_PER_ENTRY over their time."""
+    entries + ACA rows and columns) x FLOPS_PER_ENTRY over their time.  The
+    fraction of the ALU peak is a lower bound on how well the setup uses the
+    chip: the counters show the ACA's workgroup classes bound by the bytes
+    they stream and its wavefront classes by step latency (`note`)."""
     st = o["stats"]
     ms = o["setup_phases_ms"]["near_field"] + o["setup_phases_ms"]["aca"]
     ent = st["dense_entries"] + st["aca_entry_evals"]
@@ -178,7 +181,10 @@ def setup_roofline(o, form, operator="collocation"):
     return {"bound": "alu", "entries": ent, "entries_per_s": round(ent / (ms * 1e-3), 1),
             "achieved": round(tf, 3), "peak": VALU_PEAK_TFLOPS[form], "unit": "TFLOP/s",
             "frac": round(tf / VALU_PEAK_TFLOPS[form], 5),
-            "phases": "near_field + aca", "ms": round(ms, 3)}
+            "phases": "near_field + aca", "ms": round(ms, 3),
+            "note": "ACA workgroup classes (blocks above 256) stream source records and "
+                    "earlier terms at 6-7.5 TB/s by FETCH_SIZE; wavefront classes are bound "
+                    "by step latency (profiles/setup_k_aca_k_near_f32_icosphere_L8_traffic.md)"}
 
 
 def _timed(torch, fn, reps):
