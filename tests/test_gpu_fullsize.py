@@ -125,6 +125,30 @@ def test_l8_fp32_structure_rows_and_columns(l8):
     H.free()
 
 
+def test_l8_fp64_rows_columns_and_solve(l8):
+    """The FP64 form at the full size (the metric's comparison form): 4,096
+    exact rows of H x and H^T x within 10 eps, and plain GMRES in double to
+    a relative residual of 1e-8, checked again by an independent product."""
+    import paper_1806_11558_amd as hm
+    from synthetic import normal_columns
+    V, T, X, rows, y_ref, yT_ref = l8
+    n = T.shape[0]
+    eps = EPS["f64"]
+    say("fullsize L8 f64 eps", eps, "N =", n)
+    H = hm.HMatrix(V, T, leaf_size=64, eta=1.0, eps=eps, max_rank=64, precision="f64")
+    assert H.stats()["cap_hits"] == 0
+    _l8_products(H, X, rows, y_ref, yT_ref, eps, ("f64",))
+    f = torch.tensor(normal_columns(n, 1, seed=2)[:, 0], device=DEV)
+    say("L8 f64 solve")
+    s, info, st = H.solve(f, tol=1e-8, restart=100, max_iter=3000)
+    say("L8 f64 solve:", info.iters, "steps, residual", info.rel_residual)
+    assert st == hm.HM_OK and info.rel_residual <= 1e-8
+    r = f - H.matvec(s)
+    assert float(torch.linalg.norm(r) / torch.linalg.norm(f)) <= 1.01e-8
+    H.free()
+    hm.release_memory()
+
+
 def test_l8_fp16_rows_columns_and_refined_solve(l8):
     import paper_1806_11558_amd as hm
     from synthetic import normal_columns
