@@ -10,7 +10,9 @@ double and with float vectors.
 
 N = 81,920 (icosphere L=6): 96 rows and columns, computed here by the oracle.
 N = 1,310,720 (L=8): 4,096 rows and columns, written by
-tests/golden/make_fullsize_refs.py (oracle only).
+tests/golden/make_fullsize_refs.py (oracle only); for the Galerkin matrix
+256 rows and columns, written by tests/golden/make_galerkin_refs.py (oracle
+only).
 """
 import os
 
@@ -25,6 +27,8 @@ DEV = "cuda:0"
 EPS = {"f64": 1e-6, "f32": 1e-6, "f16": 1e-4}
 GOLDEN_L8 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                          "icosphere_L8_refs.npz")
+GOLDEN_GAL_L8 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "galerkin_icosphere_L8_refs.npz")
 
 
 def _vecs(prec):
@@ -169,5 +173,25 @@ def test_l8_fp16_rows_columns_and_refined_solve(l8):
     assert st == hm.HM_OK and info.rel_residual <= 1e-8 and info.ir_steps >= 2
     r = f - H.matvec(s)
     assert float(torch.linalg.norm(r) / torch.linalg.norm(f)) <= 1.01e-8
+    H.free()
+    hm.release_memory()
+
+
+def test_l8_galerkin_rows_and_columns():
+    """The Galerkin matrix (HM_GALERKIN, FP32, eps 1e-6) at N = 1,310,720:
+    H x and H^T x at 256 exact rows and columns of the Galerkin oracle
+    within 10 eps, double and float vectors."""
+    import paper_1806_11558_amd as hm
+    from synthetic import icosphere, mesh_sha256, normal_columns
+    V, T = icosphere(8)
+    g = np.load(GOLDEN_GAL_L8, allow_pickle=False)
+    assert str(g["mesh_sha256"]) == mesh_sha256(V, T), "golden file is for another mesh"
+    n = T.shape[0]
+    X = normal_columns(n, g["y"].shape[1], seed=int(g["x_seed"]))
+    say("fullsize L8 galerkin f32 N =", n)
+    H = hm.HMatrix(V, T, leaf_size=64, eta=1.0, eps=EPS["f32"], max_rank=64, precision="f32",
+                   operator="galerkin")
+    assert H.stats()["cap_hits"] == 0
+    _l8_products(H, X, g["rows"], g["y"], g["yT"], EPS["f32"], ("f64", "f32"))
     H.free()
     hm.release_memory()
