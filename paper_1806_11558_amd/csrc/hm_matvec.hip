@@ -918,20 +918,37 @@ __global__ __launch_bounds__(256) void k_fwd2x(const Run* __restrict__ runs, MvL
 
 // ------------------------------------------------------------------ transposed, phase 1
 // Per row leaf: w[col0 + j] = sum_i P[i][j] x_c[i] for every panel column.
+//
+// Lane (cg, g) forms the partial dot of its granule of column group
+// cg with x; the R partials of a column are then added by one lane, which
+// reads them from the wavefront's own LDS area (a shift-down tree over the
+// R lanes cost about four times the instructions per column).  Only the
+// wavefront itself reads what it wrote: program order of its LDS
+// instructions is enough, and wave_lds_order keeps the compiler from
+// moving LDS accesses across the exchange.
+template <int NR>
+constexpr int tr1_unr() { return NR <= 2 ? 4 : 1; }   // column groups per wavefront in flight
+
+__device__ inline void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, typename A, int NR, int G>
 __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int C, int cg, int g,
-                               bool act, int wave, const A (&xg)[G][NR], A* __restrict__ w) {
+                               bool act, int wave, const A (&xg)[G][NR], A* __restrict__ w,
+                               A* __restrict__ red) {
   static_assert(Gran<T>::G == G, "panel granules must cover the same rows");
-  constexpr int UNR = NR <= 2 ? 4 : 1;   // column groups per wavefront in flight
+  constexpr int UNR = tr1_unr<NR>();
   const int lane = threadIdx.x & 63;
   const T* S = reinterpret_cast<const T*>((uintptr_t)rn.data) + (int64_t)a * ld + g * G;
   const int64_t col0 = rn.col0 + a;
   const int ngrp = (uw + C - 1) / C;
-  // lane L = u C + c stores column group q0 + u0 + u, segment c: the UG C
-  // columns of a store round are contiguous and leave in one instruction
-  // (UG = 64 / C groups per round, so a round covers at most 64 lanes)
-  const int UG = 64 / C;
-  const int ul0 = lane / C, cl = lane - ul0 * C;
+  // a step covers the UNR C consecutive columns q0 C ... (q0 + UNR) C - 1;
+  // reader t of a step sums column q0 C + t: group u = t / C, segment c
+  const int ncol = UNR * C;
+  const int ur = lane / C, cr = lane - ur * C;       // the reader's column in the first 64
   for (int q0 = wave * UNR; q0 < ngrp; q0 += 4 * UNR) {
     // UNR consecutive column groups, all granules loaded before any is reduced
     typename Gran<T>::E sv[UNR][G];
@@ -945,35 +962,49 @@ __device__ inline void tr1_run(const Run& rn, int a, int uw, int ld, int R, int 
     A ps[UNR][NR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
-      A p[NR];
 #pragma unroll
-      for (int k = 0; k < NR; ++k) p[k] = 0;
+      for (int k = 0; k < NR; ++k) ps[u][k] = 0;
 #pragma unroll
       for (int e = 0; e < G; ++e) {
         const A x = ok[u] ? (A)sv[u][e] : (A)0;
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] += x * xg[e][k];
+        for (int k = 0; k < NR; ++k) ps[u][k] += x * xg[e][k];
       }
-#pragma unroll
-      for (int k = 0; k < NR; ++k) ps[u][k] = seg_sum(p[k], g, R);
     }
-    for (int u0 = 0; u0 < UNR; u0 += UG) {              // uniform over the wavefront
-      const int ul = u0 + ul0;
+    wave_lds_order();                                   // the last step's reads are done
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int k = 0; k < NR; ++k) red[(u * 64 + lane) * NR + k] = ps[u][k];
+    wave_lds_order();
+    for (int t = lane; t < ncol; t += 64) {
+      int u = ur, c = cr;
+      if (t >= 64) {
+        u = t / C;
+        c = t - u * C;
+      }
+      const A* rp = red + (u * 64 + c * R) * NR;
       A v[NR];
 #pragma unroll
       for (int k = 0; k < NR; ++k) v[k] = 0;
+      // partials added in order of g, read four at a time
+      int e = 0;
+      for (; e + 4 <= R; e += 4) {
+        A r4[4][NR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        if (u >= u0 && u < u0 + UG) {                   // uniform over the wavefront
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int k = 0; k < NR; ++k) {
-            const A t = __shfl(ps[u][k], cl * R, 64);
-            if (ul == u) v[k] = t;
-          }
-        }
+          for (int k = 0; k < NR; ++k) r4[i][k] = rp[(e + i) * NR + k];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int k = 0; k < NR; ++k) v[k] += r4[i][k];
       }
-      const int jj = (q0 + ul) * C + cl;
-      if (ul0 < UG && ul < UNR && jj < uw) {
+      for (; e < R; ++e)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] += rp[e * NR + k];
+      const int jj = q0 * C + t;
+      if (jj < uw) {
 #pragma unroll
         for (int k = 0; k < NR; ++k) w[(col0 + jj) * NR + k] = v[k];
       }
@@ -986,6 +1017,7 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, MvLea
                                              const Unit* __restrict__ units, int64_t nunits,
                                              const A* __restrict__ z, A* __restrict__ w) {
   constexpr int G = Gran<TD>::G;
+  __shared__ A red[4][tr1_unr<NR>() * 64 * NR];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t per = (nunits + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
@@ -1008,9 +1040,9 @@ __global__ __launch_bounds__(256) void k_tr1(const Run* __restrict__ runs, MvLea
     }
     const Run rn = runs[(int64_t)U.run * L.nleaf + c];
     if (std::is_same<TD, TL>::value || U.run == 0)
-      tr1_run<TD, A, NR, G>(rn, U.a, U.w, ld, R, C, cg, g, act, wave, xg, w);
+      tr1_run<TD, A, NR, G>(rn, U.a, U.w, ld, R, C, cg, g, act, wave, xg, w, red[wave]);
     else
-      tr1_run<TL, A, NR, G>(rn, U.a, U.w, ld, R, C, cg, g, act, wave, xg, w);
+      tr1_run<TL, A, NR, G>(rn, U.a, U.w, ld, R, C, cg, g, act, wave, xg, w, red[wave]);
   }
 }
 
