@@ -1157,7 +1157,8 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
                                              A* __restrict__ ypart, int ldmax) {
   constexpr int G = Gran<T>::G;
   __shared__ A ybuf[4][kMaxLeaf][NR];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave-uniform index: item descriptors come in by scalar loads
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t nwork = L.nleaf * S;
   const int64_t per = (nwork + kXcds - 1) / kXcds;
   for (int64_t li = blockIdx.x; li < per * kXcds; li += gridDim.x) {
@@ -1178,8 +1179,13 @@ __global__ __launch_bounds__(256) void k_tr2(const int32_t* __restrict__ beg,
       for (int e = 0; e < G; ++e) acc[e][k] = 0;
     }
     const int b0 = beg[c], b1 = beg[c + 1];
-    for (int it = b0 + 4 * sp + wave; it < b1; it += 4 * S) {
-      const TItem I = items[it];
+    // the next item's descriptor is loaded one iteration ahead
+    const int it0 = b0 + 4 * sp + wave;
+    TItem In;
+    if (it0 < b1) In = items[it0];
+    for (int it = it0; it < b1; it += 4 * S) {
+      const TItem I = In;
+      if (it + 4 * S < b1) In = items[it + 4 * S];
       if (I.kind == 0) {
         if (lane < I.w) {
 #pragma unroll
